@@ -1,0 +1,269 @@
+/*
+ * FP64 CPU oracle for multi-level foreground estimation
+ * (Germer, Uelwer, Conrad, Harmeling: "Fast Multi-Level Foreground Estimation", arXiv 2006.14970).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the slow, plain reference that the GPU path is checked
+ * against.  Only tests, the smoke check and the benchmark's CPU-baseline leg may load it; the
+ * product library never links, includes or calls anything here, and nothing here comes from the
+ * product library.
+ *
+ * What it computes (all in IEEE double, no blocking, no fusion, no reordering):
+ *   - Algorithm 1 (Section III-D, "Implementation"): the multi-level driver, with the level count
+ *     n_l = ceil(log2(max(w, h))), level sizes round(w^(l/n_l)), round(h^(l/n_l)), a resize of the
+ *     full-resolution image and matte and of the previous level's F and B to every level, and a
+ *     fixed number of sweeps per level (10 when the level is at most 32x32, else 2; Section III-D
+ *     text before Algorithm 1).
+ *   - The per-pixel update of Algorithm 1's inner loop: the 2x2 system of eq. 9 built from the
+ *     compositing data term (eq. 1) and the four clamped neighbours with weights
+ *     eps_r + omega |alpha_i - alpha_j| (eq. 3), solved by Cramer's rule, then clamped to [0, 1].
+ *   - The global quadratic energy whose stationarity conditions are the per-pixel equations.
+ *
+ * Readings where the paper is silent (each is listed with its reason in the design notes):
+ *   - N_i is the 4-neighbourhood (left, right, up, down); out-of-range neighbours are clamped to
+ *     the image, so a border pixel sees itself (Algorithm 1, neighbour clamp).
+ *   - "resize" is nearest-neighbour with source index (x * w_src) / w_dst in integer arithmetic.
+ *   - "low resolution" means w <= 32 and h <= 32.
+ *   - A 1x1 input gets one level (the formula gives zero).
+ *   - Sweep order: raster (the paper's sequential in-place loop, y outer, x inner), red-black
+ *     (all pixels with (x + y) even, then all odd, each in place) or Jacobi (every pixel from the
+ *     previous sweep's values).
+ *
+ * Layout: planar, row-major, x fastest.  A 3-channel image of size w x h is 3 planes of w*h
+ * doubles (plane c starts at c*w*h); the matte is one plane.
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+enum { FGO_RASTER = 0, FGO_REDBLACK = 1, FGO_JACOBI = 2 };
+
+/* Number of levels, Algorithm 1: ceil(log2(max(w, h))), at least 1. */
+int fgo_num_levels(int w, int h)
+{
+    int m = w > h ? w : h;
+    int n = 0;
+    /* smallest n with 2^n >= m, computed with integers so no rounding enters */
+    while (((long long)1 << n) < (long long)m) n++;
+    return n < 1 ? 1 : n;
+}
+
+/* Level size, Algorithm 1: round(full^(level / num_levels)). */
+int fgo_level_size(int full, int level, int num_levels)
+{
+    double v = pow((double)full, (double)level / (double)num_levels);
+    return (int)floor(v + 0.5);
+}
+
+/* Nearest-neighbour resize of `planes` planes from ws x hs to wd x hd. */
+void fgo_resize_nearest(const double *src, int ws, int hs, int planes, double *dst, int wd, int hd)
+{
+    for (int c = 0; c < planes; c++) {
+        for (int y = 0; y < hd; y++) {
+            int ys = (int)(((long long)y * hs) / hd);
+            for (int x = 0; x < wd; x++) {
+                int xs = (int)(((long long)x * ws) / wd);
+                dst[(size_t)c * wd * hd + (size_t)y * wd + x] =
+                    src[(size_t)c * ws * hs + (size_t)ys * ws + xs];
+            }
+        }
+    }
+}
+
+static double clamp01(double v)
+{
+    return v < 0.0 ? 0.0 : (v > 1.0 ? 1.0 : v);
+}
+
+static int clampi(int v, int lo, int hi)
+{
+    return v < lo ? lo : (v > hi ? hi : v);
+}
+
+/*
+ * Solve the per-pixel system of eq. 9 for pixel (x, y), reading F and B from (Fs, Bs) and the
+ * input I and matte a, and return the clamped solution in fout[3], bout[3].
+ *
+ * Following Algorithm 1's inner loop: U = [a, 1 - a]^T, A = U U^T, b_c = U I_c; every clamped
+ * neighbour j adds Delta = eps + omega |a_i - a_j| to both diagonal entries of A and Delta F_j,
+ * Delta B_j to the two rows of b_c; then g_c = A^{-1} b_c (Cramer's rule) and both components are
+ * clamped to [0, 1].
+ */
+static void solve_pixel(const double *Fs, const double *Bs, const double *I, const double *a,
+                        int w, int h, int x, int y, double omega, double eps,
+                        double fout[3], double bout[3])
+{
+    const size_t plane = (size_t)w * h;
+    const size_t i = (size_t)y * w + x;
+    const double ai = a[i];
+    const double u0 = ai, u1 = 1.0 - ai;
+
+    double A00 = u0 * u0, A01 = u0 * u1, A11 = u1 * u1;
+    double b0[3], b1[3];
+    for (int c = 0; c < 3; c++) {
+        b0[c] = u0 * I[c * plane + i];
+        b1[c] = u1 * I[c * plane + i];
+    }
+
+    const int dx[4] = {-1, 1, 0, 0};
+    const int dy[4] = {0, 0, -1, 1};
+    for (int k = 0; k < 4; k++) {
+        int xj = clampi(x + dx[k], 0, w - 1);
+        int yj = clampi(y + dy[k], 0, h - 1);
+        size_t j = (size_t)yj * w + xj;
+        double d = eps + omega * fabs(ai - a[j]);
+        A00 += d;
+        A11 += d;
+        for (int c = 0; c < 3; c++) {
+            b0[c] += d * Fs[c * plane + j];
+            b1[c] += d * Bs[c * plane + j];
+        }
+    }
+
+    double det = A00 * A11 - A01 * A01;
+    for (int c = 0; c < 3; c++) {
+        double f = (A11 * b0[c] - A01 * b1[c]) / det;
+        double g = (A00 * b1[c] - A01 * b0[c]) / det;
+        fout[c] = clamp01(f);
+        bout[c] = clamp01(g);
+    }
+}
+
+static void update_in_place(double *F, double *B, const double *I, const double *a,
+                            int w, int h, int x, int y, double omega, double eps)
+{
+    const size_t plane = (size_t)w * h;
+    const size_t i = (size_t)y * w + x;
+    double f[3], g[3];
+    solve_pixel(F, B, I, a, w, h, x, y, omega, eps, f, g);
+    for (int c = 0; c < 3; c++) {
+        F[c * plane + i] = f[c];
+        B[c * plane + i] = g[c];
+    }
+}
+
+/* One sweep over every pixel of a w x h level, in the given order, updating F and B. */
+void fgo_sweep(double *F, double *B, const double *I, const double *a, int w, int h,
+               double omega, double eps, int order)
+{
+    if (order == FGO_RASTER) {
+        for (int y = 0; y < h; y++)
+            for (int x = 0; x < w; x++)
+                update_in_place(F, B, I, a, w, h, x, y, omega, eps);
+    } else if (order == FGO_REDBLACK) {
+        for (int colour = 0; colour < 2; colour++)
+            for (int y = 0; y < h; y++)
+                for (int x = 0; x < w; x++)
+                    if (((x + y) & 1) == colour)
+                        update_in_place(F, B, I, a, w, h, x, y, omega, eps);
+    } else {
+        const size_t plane = (size_t)w * h;
+        double *Fo = (double *)malloc(3 * plane * sizeof(double));
+        double *Bo = (double *)malloc(3 * plane * sizeof(double));
+        memcpy(Fo, F, 3 * plane * sizeof(double));
+        memcpy(Bo, B, 3 * plane * sizeof(double));
+        for (int y = 0; y < h; y++) {
+            for (int x = 0; x < w; x++) {
+                double f[3], g[3];
+                size_t i = (size_t)y * w + x;
+                solve_pixel(Fo, Bo, I, a, w, h, x, y, omega, eps, f, g);
+                for (int c = 0; c < 3; c++) {
+                    F[c * plane + i] = f[c];
+                    B[c * plane + i] = g[c];
+                }
+            }
+        }
+        free(Fo);
+        free(Bo);
+    }
+}
+
+/*
+ * Algorithm 1.  I: 3 x H x W, a: H x W, outputs F, B: 3 x H x W each.
+ * init_f / init_b: the three channel values of the 1x1 starting F and B (the paper uses zeros;
+ * NULL means zeros).  Returns the number of levels run.
+ */
+int fgo_ml(const double *I, const double *a, int W, int H, double omega, double eps,
+           int small_size, int iters_small, int iters_big, int order,
+           const double *init_f, const double *init_b, double *F, double *B)
+{
+    const int n = fgo_num_levels(W, H);
+    int wp = 1, hp = 1;
+    double *Fp = (double *)calloc(3, sizeof(double));
+    double *Bp = (double *)calloc(3, sizeof(double));
+    for (int c = 0; c < 3; c++) {
+        Fp[c] = init_f ? init_f[c] : 0.0;
+        Bp[c] = init_b ? init_b[c] : 0.0;
+    }
+
+    for (int l = 1; l <= n; l++) {
+        int w = fgo_level_size(W, l, n);
+        int h = fgo_level_size(H, l, n);
+        size_t plane = (size_t)w * h;
+        double *Il = (double *)malloc(3 * plane * sizeof(double));
+        double *al = (double *)malloc(plane * sizeof(double));
+        double *Fl = (double *)malloc(3 * plane * sizeof(double));
+        double *Bl = (double *)malloc(3 * plane * sizeof(double));
+
+        fgo_resize_nearest(I, W, H, 3, Il, w, h);
+        fgo_resize_nearest(a, W, H, 1, al, w, h);
+        fgo_resize_nearest(Fp, wp, hp, 3, Fl, w, h);
+        fgo_resize_nearest(Bp, wp, hp, 3, Bl, w, h);
+
+        int iters = (w <= small_size && h <= small_size) ? iters_small : iters_big;
+        for (int it = 0; it < iters; it++)
+            fgo_sweep(Fl, Bl, Il, al, w, h, omega, eps, order);
+
+        free(Il);
+        free(al);
+        free(Fp);
+        free(Bp);
+        Fp = Fl;
+        Bp = Bl;
+        wp = w;
+        hp = h;
+    }
+
+    /* the last level has the full size, since round(W^1) = W */
+    memcpy(F, Fp, 3 * (size_t)W * H * sizeof(double));
+    memcpy(B, Bp, 3 * (size_t)W * H * sizeof(double));
+    free(Fp);
+    free(Bp);
+    return n;
+}
+
+/*
+ * Quadratic energy whose stationary point every sweep order approaches while no clamp is active:
+ *   E = sum_i sum_c (a_i F_i^c + (1 - a_i) B_i^c - I_i^c)^2
+ *     + sum over undirected in-image 4-neighbour edges {i, j} of
+ *       (eps + omega |a_i - a_j|) sum_c [(F_i^c - F_j^c)^2 + (B_i^c - B_j^c)^2].
+ * Setting dE/dF_i, dE/dB_i to zero gives, pixel by pixel, the normal equations of eq. 9 (the
+ * weights are symmetric in i and j, so every edge is counted once).
+ */
+double fgo_energy(const double *F, const double *B, const double *I, const double *a,
+                  int w, int h, double omega, double eps)
+{
+    const size_t plane = (size_t)w * h;
+    double e = 0.0;
+    for (int y = 0; y < h; y++) {
+        for (int x = 0; x < w; x++) {
+            size_t i = (size_t)y * w + x;
+            for (int c = 0; c < 3; c++) {
+                double r = a[i] * F[c * plane + i] + (1.0 - a[i]) * B[c * plane + i] - I[c * plane + i];
+                e += r * r;
+            }
+            /* right and down edges, so each edge appears once */
+            for (int k = 0; k < 2; k++) {
+                int xj = x + (k == 0), yj = y + (k == 1);
+                if (xj >= w || yj >= h) continue;
+                size_t j = (size_t)yj * w + xj;
+                double s = eps + omega * fabs(a[i] - a[j]);
+                for (int c = 0; c < 3; c++) {
+                    double df = F[c * plane + i] - F[c * plane + j];
+                    double db = B[c * plane + i] - B[c * plane + j];
+                    e += s * (df * df + db * db);
+                }
+            }
+        }
+    }
+    return e;
+}
