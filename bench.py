@@ -1,0 +1,203 @@
+#!/usr/bin/env python3
+"""Benchmark: multi-level foreground estimation of one 4096x3072 RGB image on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+
+A step is one full pass of the method (all 12 levels: LDS-resident coarse block, then one fused
+launch per fine level) over one image whose inputs are already in HBM.  The step is timed for
+float32 storage (``value``) and float16 storage (``fp16_store``), with float32 arithmetic in
+both.  Two input/output sets alternate between steps so that consecutive steps do not reuse
+cached data.  Reported beside throughput: per-step latency percentiles (HIP events), the
+max-abs error of each run against the FP64 oracle, the roofline of the dominant kernel (the
+finest level) from HIP events recorded around every launch in a second timed pass, and the FP64
+oracle's own throughput on the host (the paper's single-thread protocol).
+
+Prints progress on stderr and ONE JSON line on stdout.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+W_IMG, H_IMG = 4096, 3072
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def level_bytes(levels, elem):
+    """Algorithmic HBM bytes of one fused launch per level: gather I (3) and alpha (1) at the
+    level size, read the previous level's F and B (6 planes at its size), write F and B (6)."""
+    out = []
+    for i, (w, h, _) in enumerate(levels):
+        prev = levels[i - 1][0] * levels[i - 1][1] if i > 0 else 0
+        out.append((10 * w * h + 6 * prev) * elem)
+    return out
+
+
+def run_storage(torch, fge, sample, storage, steps, warmup, oracle_F=None, oracle_B=None):
+    dt = torch.float16 if storage == fge.F16 else torch.float32
+    p = fge.default_params(storage=storage)
+    dev = torch.device("cuda:0")
+    sets = []
+    for _ in range(2):
+        I = torch.from_numpy(sample.I).to(dt).to(dev).contiguous()
+        a = torch.from_numpy(sample.alpha).to(dt).to(dev).contiguous()
+        F = torch.empty((3, H_IMG, W_IMG), dtype=dt, device=dev)
+        B = torch.empty_like(F)
+        ws = torch.empty(max(1, fge.workspace_bytes(W_IMG, H_IMG, p)), dtype=torch.uint8, device=dev)
+        sets.append((I, a, F, B, ws))
+    stream = torch.cuda.current_stream()
+
+    def step(k):
+        I, a, F, B, ws = sets[k % 2]
+        fge.estimate_foreground(I, a, p, F=F, B=B, workspace=ws, stream=stream)
+
+    for k in range(warmup):
+        step(k)
+    torch.cuda.synchronize()
+    err = None
+    if oracle_F is not None:
+        F = sets[(warmup - 1) % 2][2].double().cpu().numpy()
+        B = sets[(warmup - 1) % 2][3].double().cpu().numpy()
+        err = float(max(np.abs(F - oracle_F).max(), np.abs(B - oracle_B).max()))
+
+    # pass 1: throughput and per-step latency
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        ev[k][0].record(stream)
+        step(k)
+        ev[k][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    lat = np.array([s.elapsed_time(e) for s, e in ev])
+
+    # pass 2: the same steps with HIP events around every kernel launch (per level)
+    fge.profile_start(64 * steps)
+    torch.cuda.synchronize()
+    for k in range(steps):
+        step(k)
+    torch.cuda.synchronize()
+    lvl_ms, lvl_n = fge.profile_stop()
+    return {
+        "ms_per_step": wall / steps * 1e3,
+        "lat_ms": lat,
+        "level_ms": [lvl_ms[i] / lvl_n[i] if lvl_n[i] else None for i in range(len(lvl_ms))],
+        "max_abs_vs_oracle": err,
+        "params": p,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: the method has no multi-GPU path in this build "
+              "(images are independent; see the design notes on sharding).", file=sys.stderr)
+        sys.exit(2)
+    if args.steps < 1 or args.warmup < 1:
+        sys.exit("--steps and --warmup must be >= 1")
+
+    import torch
+    from paper_2006_14970_amd import fge, synth
+    fge.load()
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+
+    log("generating the 4096x3072 strands workload (seed 3)")
+    t = time.perf_counter()
+    sample = synth.config3()
+    log(f"  done in {time.perf_counter() - t:.1f} s, fractional alpha {sample.fractional_fraction():.3f}")
+
+    oracle_F = oracle_B = None
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        log("FP64 oracle, red-black order (parity reference for the error figures)")
+        oracle_F, oracle_B = oracle.ml(sample.I, sample.alpha, order="redblack")
+        log("FP64 oracle, raster order, 1 thread: timing (CPU baseline)")
+        times = []
+        for _ in range(3):
+            t = time.perf_counter()
+            oracle.ml(sample.I, sample.alpha, order="raster")
+            times.append(time.perf_counter() - t)
+        med = float(np.median(times))
+        cpu = {"value": W_IMG * H_IMG / 1e6 / med, "unit": "MP/s", "cores": 1, "kind": "oracle",
+               "sample": "the full 4096x3072 image, FP64 raster order (the paper's sequential "
+                         "sweep), one thread, median of 3 runs of "
+                         f"{med:.2f} s"}
+
+    plan = fge.plan(W_IMG, H_IMG)
+    res = {}
+    for name, storage in (("f32", fge.F32), ("f16", fge.F16)):
+        log(f"GPU {name} storage: {args.warmup} warm-up + {args.steps} timed steps (x2 passes)")
+        res[name] = run_storage(torch, fge, sample, storage, args.steps, args.warmup,
+                                oracle_F, oracle_B)
+        log(f"  {res[name]['ms_per_step']:.4f} ms/step, max-abs vs oracle {res[name]['max_abs_vs_oracle']}")
+
+    mp = W_IMG * H_IMG / 1e6
+
+    def summary(r, elem):
+        lb = level_bytes(plan.levels, elem)
+        fin_ms = r["level_ms"][0]
+        achieved = lb[-1] / (fin_ms * 1e-3) / 1e9
+        return {
+            "value": mp / (r["ms_per_step"] * 1e-3),
+            "ms_per_step": r["ms_per_step"],
+            "latency_ms": {"p50": float(np.percentile(r["lat_ms"], 50)),
+                           "p99": float(np.percentile(r["lat_ms"], 99))},
+            "max_abs_vs_oracle": r["max_abs_vs_oracle"],
+            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                         "kernel": "fine_kernel, finest level 4096x3072",
+                         "kernel_ms": fin_ms, "algorithmic_bytes": lb[-1]},
+            "level_ms_finest_first": [round(x, 5) if x is not None else None
+                                      for x in r["level_ms"][:len(plan.levels) - plan.n_coarse + 1]],
+        }
+
+    s32 = summary(res["f32"], 4)
+    s16 = summary(res["f16"], 2)
+    out = {
+        "metric": "MP/s foreground estimation @4096x3072 FP32 vs FP16-store; p50/p99 latency",
+        "value": s32["value"],
+        "unit": "MP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": s32["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "one 4096x3072 RGB image per step (strand-matte generator, seed 3), "
+                               "float32 storage; fp16_store: same with float16 storage",
+                   "levels": len(plan.levels), "coarse_levels": plan.n_coarse},
+        "latency_ms": s32["latency_ms"],
+        "max_abs_vs_oracle": s32["max_abs_vs_oracle"],
+        "roofline": s32["roofline"],
+        "fp16_store": s16,
+        "level_ms_finest_first": s32["level_ms_finest_first"],
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

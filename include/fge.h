@@ -1,0 +1,141 @@
+/*
+ * fge.h -- C ABI of the MI355X (gfx950) multi-level foreground estimation library.
+ *
+ * Method: Germer, Uelwer, Conrad, Harmeling, "Fast Multi-Level Foreground Estimation"
+ * (arXiv 2006.14970).  Given an RGB image I and an alpha matte alpha, the library recovers a
+ * foreground F and background B with I ~ alpha F + (1 - alpha) B (eq. 1), by Algorithm 1
+ * (Section III-D): a coarse-to-fine pyramid of n_l = ceil(log2(max(W, H))) levels of size
+ * round(W^(l/n_l)) x round(H^(l/n_l)); at every level the full-resolution I and alpha and the
+ * previous level's F, B are resized to the level, then a fixed number of sweeps (10 when the level
+ * is at most 32x32, else 2) update every pixel by the closed-form 2x2 solve of eq. 9 -- the
+ * compositing data term coupled to the 4 clamped neighbours with weights
+ * eps_r + omega |alpha_i - alpha_j| (eq. 3) -- and clamp the result to [0, 1].
+ *
+ * Choices where the paper is silent: "resize" is nearest-neighbour with source index
+ * (x * w_src) / w_dst (integer division); the sweep is red-black (pixels with (x + y) even
+ * first, then odd) because the paper's in-place sequential sweep has no parallel form; a 1x1
+ * input runs one level.
+ *
+ * Conventions for every entry point:
+ *   - Images are planar, row-major, x fastest: I, F and B are 3 planes of W*H elements (plane c
+ *     starts at element c*W*H); alpha is one plane of W*H elements.  Element type is float32 or
+ *     IEEE binary16 according to fge_params.storage; values are expected in [0, 1] and are not
+ *     checked.
+ *   - All data pointers are DEVICE pointers owned by the caller; the library never frees or
+ *     keeps them past the call.  F and B must not overlap I, alpha, each other or the workspace.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Work is enqueued asynchronously;
+ *     the call returns once it is enqueued.  The caller synchronises before reading F, B.
+ *   - Argument errors are reported synchronously (FGE_EINVAL / FGE_EWORKSPACE /
+ *     FGE_EUNSUPPORTED) before anything is enqueued; a failed launch returns FGE_EHIP.
+ *   - The estimation entry points allocate no device memory: scratch lives in the caller's
+ *     workspace (size from fge_workspace_bytes, 256-byte aligned start).
+ *   - Arithmetic is float32 on the device for both storage types.  With binary16 storage the
+ *     input is read as given and F, B are rounded to binary16 (round to nearest even) once per
+ *     level, when a level's state is written to memory.
+ */
+#ifndef FGE_H
+#define FGE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum fge_status {
+    FGE_OK = 0,
+    FGE_EINVAL = -1,        /* bad argument (size, pointer, parameter value) */
+    FGE_ENOMEM = -2,        /* host allocation failed */
+    FGE_EHIP = -3,          /* a HIP runtime call or kernel launch failed */
+    FGE_EUNSUPPORTED = -4,  /* valid request this build does not implement */
+    FGE_EWORKSPACE = -5     /* workspace missing or smaller than fge_workspace_bytes */
+} fge_status;
+
+typedef enum fge_dtype { FGE_F32 = 0, FGE_F16 = 1 } fge_dtype;
+
+/* Sweep order on the device.  Only red-black is implemented; the paper's sequential raster
+ * order exists in the CPU oracle only. */
+typedef enum fge_order { FGE_REDBLACK = 0 } fge_order;
+
+/* Kernel family for the levels above the LDS-resident coarse block. */
+typedef enum fge_kernel {
+    FGE_KERNEL_AUTO = 0,   /* fused streaming kernel where supported, else per-half-sweep */
+    FGE_KERNEL_FUSED = 1,  /* one fused launch per level (requires iters_big == 2) */
+    FGE_KERNEL_NAIVE = 2   /* debug path: one launch per resize and per half-sweep */
+} fge_kernel;
+
+typedef struct fge_params {
+    uint32_t size;          /* sizeof(fge_params), for ABI versioning */
+    float omega;            /* alpha-gradient weight omega (Algorithm 1 default 0.1) */
+    float eps_r;            /* regulariser eps_r (Algorithm 1 default 5e-3) */
+    int32_t small_size;     /* a level is "low resolution" when w <= small and h <= small (32) */
+    int32_t iters_small;    /* sweeps on low-resolution levels (10) */
+    int32_t iters_big;      /* sweeps on the other levels (2) */
+    int32_t storage;        /* fge_dtype of I, alpha, F, B and the workspace state */
+    int32_t order;          /* fge_order */
+    int32_t kernel;         /* fge_kernel */
+    int32_t strip_rows;     /* fused kernel: output rows per wave strip; 0 = automatic */
+    int32_t coarse_max_px;  /* levels with w*h <= this (and all smaller ones) run in the
+                               LDS-resident coarse kernel; 0 = automatic (4096), -1 = never */
+} fge_params;
+
+/* Fill *p with the paper's defaults: omega 0.1, eps_r 5e-3, 32 / 10 / 2, float32 storage,
+ * red-black order, automatic kernels. */
+void fge_default_params(fge_params *p);
+
+/* Human-readable name of a status code (static string). */
+const char *fge_status_string(int status);
+
+/* Library ABI version (increments when fge_params or a signature changes). */
+int32_t fge_version(void);
+
+/* ---- host-only planning (no GPU needed) ---------------------------------------------- */
+
+/* Level count of Algorithm 1 for a W x H input: ceil(log2(max(W, H))), at least 1.
+ * Returns 0 if W or H is outside [1, 32767]. */
+int32_t fge_num_levels(int32_t W, int32_t H);
+
+/* Size of level `level` (1-based) of `n_levels` along an axis of `full` pixels:
+ * round(full^(level / n_levels)) (Algorithm 1).  Returns 0 on bad arguments. */
+int32_t fge_level_size(int32_t full, int32_t level, int32_t n_levels);
+
+/* The level schedule for a W x H input under *p: for l = 1..n, w_out[l-1], h_out[l-1] and
+ * iters_out[l-1] (10 or 2 by the low-resolution rule), and *n_coarse_out, the number of leading
+ * levels the LDS-resident coarse kernel runs.  Arrays hold at least max_levels entries (16 is
+ * always enough).  FGE_EINVAL on bad sizes or parameters. */
+fge_status fge_plan(int32_t W, int32_t H, const fge_params *p, int32_t max_levels,
+                    int32_t *w_out, int32_t *h_out, int32_t *iters_out, int32_t *n_levels_out,
+                    int32_t *n_coarse_out);
+
+/* Workspace bytes fge_estimate_foreground needs for a W x H input under *p (0 on bad
+ * arguments; may be 0 for inputs whose pyramid fits the coarse kernel). */
+size_t fge_workspace_bytes(int32_t W, int32_t H, const fge_params *p);
+
+/* ---- estimation ------------------------------------------------------------------------ */
+
+/* Algorithm 1 for one image: reads I (3 x H x W) and alpha (H x W), writes F and B
+ * (3 x H x W each), all in p->storage element type, on `stream`.  `workspace` must hold
+ * fge_workspace_bytes(W, H, p) bytes (it may be NULL when that is 0).  p == NULL means the
+ * defaults. */
+fge_status fge_estimate_foreground(const void *I, const void *alpha, int32_t W, int32_t H,
+                                   const fge_params *p, void *F, void *B, void *workspace,
+                                   size_t workspace_bytes, void *stream);
+
+/* ---- profiling ------------------------------------------------------------------------- */
+
+/* Start recording HIP events around every kernel launch of the following estimation calls
+ * (on the caller's stream).  Level 0 is the finest level, 1 the next coarser, ...; the coarse
+ * kernel is recorded under the index of the last level it runs.  `capacity` bounds the number
+ * of recorded launches (events are created here, not in the estimation calls). */
+fge_status fge_profile_start(int32_t capacity);
+
+/* Stop recording, wait for the recorded events and report, for each level index below
+ * max_levels, the summed milliseconds and the number of launches recorded.  Frees the events. */
+fge_status fge_profile_stop(double *level_ms, int32_t *level_launches, int32_t max_levels);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FGE_H */

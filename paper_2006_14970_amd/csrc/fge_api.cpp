@@ -1,0 +1,244 @@
+// C ABI of libfge (declared in include/fge.h): argument checks, the launch sequence of
+// Algorithm 1's levels on the caller's stream, and optional per-level event timing.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "fge_internal.h"
+
+namespace {
+
+constexpr int32_t kAbiVersion = 1;
+
+struct ProfileRecord {
+    int level;          // 0 = finest
+    hipEvent_t start, stop;
+};
+
+struct Profiler {
+    std::mutex mu;
+    bool on = false;
+    std::vector<ProfileRecord> recs;   // events created in fge_profile_start
+    size_t used = 0;
+};
+
+Profiler &profiler() {
+    static Profiler p;
+    return p;
+}
+
+// Brackets one launch with events when profiling is on.
+struct LaunchTimer {
+    ProfileRecord *rec = nullptr;
+    hipStream_t s;
+    LaunchTimer(int level_from_finest, hipStream_t stream) : s(stream) {
+        Profiler &p = profiler();
+        std::lock_guard<std::mutex> g(p.mu);
+        if (p.on && p.used < p.recs.size()) {
+            rec = &p.recs[p.used++];
+            rec->level = level_from_finest;
+            hipEventRecord(rec->start, s);
+        }
+    }
+    ~LaunchTimer() {
+        if (rec) hipEventRecord(rec->stop, s);
+    }
+};
+
+const fge_params &resolve(const fge_params *p, fge_params &tmp) {
+    if (p) return *p;
+    fge_default_params(&tmp);
+    return tmp;
+}
+
+}  // namespace
+
+extern "C" {
+
+void fge_default_params(fge_params *p) {
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->size = sizeof(fge_params);
+    p->omega = 0.1f;
+    p->eps_r = 5e-3f;
+    p->small_size = 32;
+    p->iters_small = 10;
+    p->iters_big = 2;
+    p->storage = FGE_F32;
+    p->order = FGE_REDBLACK;
+    p->kernel = FGE_KERNEL_AUTO;
+    p->strip_rows = 0;
+    p->coarse_max_px = 0;
+}
+
+const char *fge_status_string(int status) {
+    switch (status) {
+        case FGE_OK: return "FGE_OK";
+        case FGE_EINVAL: return "FGE_EINVAL: invalid argument";
+        case FGE_ENOMEM: return "FGE_ENOMEM: host allocation failed";
+        case FGE_EHIP: return "FGE_EHIP: HIP runtime or launch error";
+        case FGE_EUNSUPPORTED: return "FGE_EUNSUPPORTED: not implemented for these parameters";
+        case FGE_EWORKSPACE: return "FGE_EWORKSPACE: workspace missing or too small";
+        default: return "unknown fge status";
+    }
+}
+
+int32_t fge_version(void) { return kAbiVersion; }
+
+int32_t fge_num_levels(int32_t W, int32_t H) {
+    if (W < 1 || H < 1 || W > fge::kMaxSide || H > fge::kMaxSide) return 0;
+    return fge::num_levels(W, H);
+}
+
+int32_t fge_level_size(int32_t full, int32_t level, int32_t n_levels) {
+    if (full < 1 || full > fge::kMaxSide || n_levels < 1 || n_levels > fge::kMaxLevels ||
+        level < 1 || level > n_levels)
+        return 0;
+    return fge::level_size(full, level, n_levels);
+}
+
+fge_status fge_plan(int32_t W, int32_t H, const fge_params *p, int32_t max_levels, int32_t *w_out,
+                    int32_t *h_out, int32_t *iters_out, int32_t *n_levels_out,
+                    int32_t *n_coarse_out) {
+    fge_params tmp;
+    fge::Plan plan;
+    const fge_status st = fge::make_plan(W, H, resolve(p, tmp), &plan);
+    if (st != FGE_OK) return st;
+    if (max_levels < plan.n) return FGE_EINVAL;
+    for (int i = 0; i < plan.n; ++i) {
+        if (w_out) w_out[i] = plan.lv[i].w;
+        if (h_out) h_out[i] = plan.lv[i].h;
+        if (iters_out) iters_out[i] = plan.lv[i].iters;
+    }
+    if (n_levels_out) *n_levels_out = plan.n;
+    if (n_coarse_out) *n_coarse_out = plan.nc;
+    return FGE_OK;
+}
+
+size_t fge_workspace_bytes(int32_t W, int32_t H, const fge_params *p) {
+    fge_params tmp;
+    fge::Plan plan;
+    if (fge::make_plan(W, H, resolve(p, tmp), &plan) != FGE_OK) return 0;
+    return plan.ws_bytes;
+}
+
+fge_status fge_estimate_foreground(const void *I, const void *alpha, int32_t W, int32_t H,
+                                   const fge_params *p, void *F, void *B, void *workspace,
+                                   size_t workspace_bytes, void *stream) {
+    fge_params tmp;
+    const fge_params &prm = resolve(p, tmp);
+    fge::Plan plan;
+    const fge_status st = fge::make_plan(W, H, prm, &plan);
+    if (st != FGE_OK) return st;
+    if (!I || !alpha || !F || !B || F == B) return FGE_EINVAL;
+    if (plan.ws_bytes > 0 && (!workspace || workspace_bytes < plan.ws_bytes)) return FGE_EWORKSPACE;
+    if (workspace && (reinterpret_cast<uintptr_t>(workspace) & 255)) return FGE_EWORKSPACE;
+
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    char *ws = static_cast<char *>(workspace);
+    const int n = plan.n;
+    // F and B of level i (0-based): the caller's buffers for the last level, else a ping-pong
+    // workspace buffer holding F's 3 planes followed by B's.
+    auto state = [&](int i, void **f, void **b) {
+        if (i == n - 1) {
+            *f = F;
+            *b = B;
+            return;
+        }
+        const int k = (n - 2 - i) % 2;
+        char *base = ws + plan.buf_off[k];
+        *f = base;
+        *b = base + 3 * static_cast<size_t>(plan.lv[i].w) * plan.lv[i].h * plan.elem;
+    };
+
+    if (plan.nc > 0) {
+        void *fo, *bo;
+        state(plan.nc - 1, &fo, &bo);
+        LaunchTimer timer(n - plan.nc, s);
+        if (fge::launch_coarse(plan, I, alpha, fo, bo, prm.omega, prm.eps_r, prm.storage, s))
+            return FGE_EHIP;
+    }
+    for (int i = plan.nc; i < n; ++i) {
+        fge::LevelIO io{};
+        io.I = I;
+        io.A = alpha;
+        io.W = W;
+        io.H = H;
+        if (i > 0) {
+            void *fp, *bp;
+            state(i - 1, &fp, &bp);
+            io.Fp = fp;
+            io.Bp = bp;
+            io.wp = plan.lv[i - 1].w;
+            io.hp = plan.lv[i - 1].h;
+        } else {
+            io.Fp = io.Bp = nullptr;
+            io.wp = io.hp = 1;
+        }
+        state(i, &io.Fo, &io.Bo);
+        io.w = plan.lv[i].w;
+        io.h = plan.lv[i].h;
+        io.omega = prm.omega;
+        io.eps = prm.eps_r;
+        LaunchTimer timer(n - 1 - i, s);
+        const int err = plan.fused[i]
+                            ? fge::launch_fine_fused(io, prm.strip_rows, prm.storage, s)
+                            : fge::launch_naive_level(io, plan.lv[i].iters, prm.storage, s);
+        if (err) return FGE_EHIP;
+    }
+    return FGE_OK;
+}
+
+fge_status fge_profile_start(int32_t capacity) {
+    if (capacity < 1 || capacity > (1 << 20)) return FGE_EINVAL;
+    Profiler &p = profiler();
+    std::lock_guard<std::mutex> g(p.mu);
+    for (auto &r : p.recs) {
+        hipEventDestroy(r.start);
+        hipEventDestroy(r.stop);
+    }
+    p.recs.clear();
+    p.used = 0;
+    p.recs.resize(capacity);
+    for (auto &r : p.recs) {
+        if (hipEventCreate(&r.start) != hipSuccess || hipEventCreate(&r.stop) != hipSuccess)
+            return FGE_EHIP;
+    }
+    p.on = true;
+    return FGE_OK;
+}
+
+fge_status fge_profile_stop(double *level_ms, int32_t *level_launches, int32_t max_levels) {
+    Profiler &p = profiler();
+    std::lock_guard<std::mutex> g(p.mu);
+    p.on = false;
+    for (int i = 0; i < max_levels; ++i) {
+        if (level_ms) level_ms[i] = 0.0;
+        if (level_launches) level_launches[i] = 0;
+    }
+    fge_status st = FGE_OK;
+    for (size_t k = 0; k < p.used; ++k) {
+        ProfileRecord &r = p.recs[k];
+        float ms = 0.0f;
+        if (hipEventSynchronize(r.stop) != hipSuccess ||
+            hipEventElapsedTime(&ms, r.start, r.stop) != hipSuccess) {
+            st = FGE_EHIP;
+            continue;
+        }
+        if (r.level >= 0 && r.level < max_levels) {
+            if (level_ms) level_ms[r.level] += ms;
+            if (level_launches) level_launches[r.level] += 1;
+        }
+    }
+    for (auto &r : p.recs) {
+        hipEventDestroy(r.start);
+        hipEventDestroy(r.stop);
+    }
+    p.recs.clear();
+    p.used = 0;
+    return st;
+}
+
+}  // extern "C"

@@ -1,0 +1,61 @@
+// Internal declarations shared by the planner, the kernels and the C ABI of libfge.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+
+#include "fge.h"
+
+namespace fge {
+
+constexpr int kMaxLevels = 16;         // 32767 needs 15 levels
+constexpr int kMaxSide = 32767;        // keeps x * w_src inside int32
+constexpr int kCoarseMaxPx = 4096;     // LDS-resident coarse levels: 7 float planes fit 112 KB
+constexpr int kCoarseThreads = 1024;
+constexpr int kCoarsePxPerThread = kCoarseMaxPx / kCoarseThreads;
+
+struct Level {
+    int w, h, iters;
+};
+
+// The level schedule of Algorithm 1 plus the execution layout chosen for it.
+struct Plan {
+    int W = 0, H = 0;
+    int n = 0;      // number of levels
+    int nc = 0;     // levels [0, nc) run inside the coarse kernel
+    Level lv[kMaxLevels];
+    int elem = 4;   // bytes per stored element
+    // Two ping-pong state buffers in the workspace.  Each holds F (3 planes) then B (3 planes)
+    // of one level at that level's size.  Level i < n-1 lives in buffer (n - 2 - i) % 2; the
+    // last level is written straight into the caller's F and B.
+    size_t buf_off[2] = {0, 0};
+    size_t buf_px[2] = {0, 0};
+    size_t ws_bytes = 0;
+    bool fused[kMaxLevels] = {};   // per fine level: fused streaming kernel or naive path
+};
+
+int num_levels(int W, int H);
+int level_size(int full, int level, int n);
+bool params_valid(const fge_params &p);
+fge_status make_plan(int W, int H, const fge_params &p, Plan *out);
+
+// Kernel launchers (fge_kernels.hip).  All enqueue on `stream` and return a HIP error code.
+struct LevelIO {
+    const void *I;      // full-resolution input, 3 planes of W*H
+    const void *A;      // full-resolution alpha, W*H
+    int W, H;
+    const void *Fp;     // previous level F (3 planes wp*hp), nullptr: the 1x1 zero start
+    const void *Bp;
+    int wp, hp;
+    void *Fo;           // this level's F, B (3 planes w*h each)
+    void *Bo;
+    int w, h;
+    float omega, eps;
+};
+
+int launch_coarse(const Plan &plan, const void *I, const void *A, void *Fo, void *Bo,
+                  float omega, float eps, int storage, void *stream);
+int launch_fine_fused(const LevelIO &io, int strip_rows, int storage, void *stream);
+int launch_naive_level(const LevelIO &io, int iters, int storage, void *stream);
+
+}  // namespace fge

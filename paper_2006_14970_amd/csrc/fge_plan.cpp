@@ -1,0 +1,83 @@
+// Level planner: Algorithm 1's schedule (level count, level sizes, sweeps per level) and the
+// workspace layout of the device path.  Host-only code.
+#include <cmath>
+#include <cstring>
+
+#include "fge_internal.h"
+
+namespace fge {
+
+// Algorithm 1: n_l = ceil(log2(max(W, H))); a 1x1 input still runs one level.
+int num_levels(int W, int H) {
+    const int m = W > H ? W : H;
+    int n = 0;
+    while ((1 << n) < m) ++n;
+    return n < 1 ? 1 : n;
+}
+
+// Algorithm 1: round(full^(level / n)).  For full <= 32767 and n <= 15 the value is never
+// closer than ~1e-9 (relative) to a half-integer, far above double rounding error, so the
+// double evaluation is exact (checked exhaustively against exact integer arithmetic in tests).
+int level_size(int full, int level, int n) {
+    const double v = std::pow(static_cast<double>(full), static_cast<double>(level) / n);
+    return static_cast<int>(std::lround(v));
+}
+
+bool params_valid(const fge_params &p) {
+    if (p.size != sizeof(fge_params)) return false;
+    if (!(p.omega >= 0.0f) || !std::isfinite(p.omega)) return false;
+    if (!(p.eps_r > 0.0f) || !std::isfinite(p.eps_r)) return false;   // eps_r > 0 keeps det > 0
+    if (p.small_size < 0 || p.iters_small < 0 || p.iters_big < 0) return false;
+    if (p.iters_small > 1000 || p.iters_big > 1000) return false;
+    if (p.storage != FGE_F32 && p.storage != FGE_F16) return false;
+    if (p.order != FGE_REDBLACK) return false;
+    if (p.kernel < FGE_KERNEL_AUTO || p.kernel > FGE_KERNEL_NAIVE) return false;
+    if (p.strip_rows < 0 || p.strip_rows > 1 << 20) return false;
+    if (p.coarse_max_px < -1 || p.coarse_max_px > kCoarseMaxPx) return false;
+    return true;
+}
+
+static size_t align256(size_t v) { return (v + 255) & ~static_cast<size_t>(255); }
+
+fge_status make_plan(int W, int H, const fge_params &p, Plan *out) {
+    if (W < 1 || H < 1 || W > kMaxSide || H > kMaxSide) return FGE_EINVAL;
+    if (!params_valid(p)) return FGE_EINVAL;
+    Plan pl;
+    pl.W = W;
+    pl.H = H;
+    pl.n = num_levels(W, H);
+    pl.elem = p.storage == FGE_F16 ? 2 : 4;
+    for (int i = 0; i < pl.n; ++i) {
+        const int w = level_size(W, i + 1, pl.n);
+        const int h = level_size(H, i + 1, pl.n);
+        const bool small = w <= p.small_size && h <= p.small_size;
+        pl.lv[i] = {w, h, small ? p.iters_small : p.iters_big};
+    }
+    // Coarse block: the longest prefix of levels with w*h <= limit (sizes grow with l).
+    const int limit = p.coarse_max_px == 0 ? kCoarseMaxPx : p.coarse_max_px;
+    pl.nc = 0;
+    if (limit > 0)
+        while (pl.nc < pl.n && static_cast<long>(pl.lv[pl.nc].w) * pl.lv[pl.nc].h <= limit) ++pl.nc;
+    // Fine levels: the fused kernel implements exactly two sweeps per level.
+    for (int i = pl.nc; i < pl.n; ++i) {
+        const bool can_fuse = pl.lv[i].iters == 2;
+        pl.fused[i] = p.kernel == FGE_KERNEL_NAIVE ? false : can_fuse;
+        if (p.kernel == FGE_KERNEL_FUSED && !can_fuse) return FGE_EUNSUPPORTED;
+    }
+    // Workspace: the state of every level except the last goes through a ping-pong buffer.
+    // Only levels from nc-1 on are materialised (coarser ones live in LDS).
+    const int first_mat = pl.nc > 0 ? pl.nc - 1 : 0;
+    for (int i = first_mat; i < pl.n - 1; ++i) {
+        const int b = (pl.n - 2 - i) % 2;
+        const size_t px = static_cast<size_t>(pl.lv[i].w) * pl.lv[i].h;
+        if (px > pl.buf_px[b]) pl.buf_px[b] = px;
+    }
+    pl.buf_off[0] = 0;
+    pl.buf_off[1] = align256(6 * pl.buf_px[0] * pl.elem);
+    pl.ws_bytes = pl.buf_px[1] ? pl.buf_off[1] + align256(6 * pl.buf_px[1] * pl.elem)
+                               : (pl.buf_px[0] ? pl.buf_off[1] : 0);
+    *out = pl;
+    return FGE_OK;
+}
+
+}  // namespace fge
