@@ -107,6 +107,8 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 512 MiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: the method has no multi-GPU path in this build "
@@ -196,6 +198,14 @@ def main():
         "level_ms_finest_first": s32["level_ms_finest_first"],
         "cpu_baseline": cpu,
     }
+    if args.copy_calibration:
+        n = 512 * 1024 * 1024 // 4
+        src = torch.rand(n, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = {"read": n * 4, "write": n * 4}
     print(json.dumps(out), flush=True)
 
 
