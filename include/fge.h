@@ -61,7 +61,8 @@ typedef enum fge_order { FGE_REDBLACK = 0 } fge_order;
 /* Kernel family for the levels above the LDS-resident coarse block. */
 typedef enum fge_kernel {
     FGE_KERNEL_AUTO = 0,   /* fused streaming kernel where supported, else per-half-sweep */
-    FGE_KERNEL_FUSED = 1,  /* one fused launch per level (requires iters_big == 2) */
+    FGE_KERNEL_FUSED = 1,  /* one fused launch per fine level, tile or streaming kernel
+                              (requires iters_big == 2) */
     FGE_KERNEL_NAIVE = 2   /* debug path: one launch per resize and per half-sweep */
 } fge_kernel;
 
@@ -78,6 +79,8 @@ typedef struct fge_params {
     int32_t strip_rows;     /* fused kernel: output rows per wave strip; 0 = automatic */
     int32_t coarse_max_px;  /* levels with w*h <= this (and all smaller ones) run in the
                                LDS-resident coarse kernel; 0 = automatic (4096), -1 = never */
+    int32_t tile_max_px;    /* fine levels with w*h <= this use the LDS tile kernel, larger ones
+                               the streaming kernel; 0 = automatic (2^20), -1 = never */
 } fge_params;
 
 /* Fill *p with the paper's defaults: omega 0.1, eps_r 5e-3, 32 / 10 / 2, float32 storage,
@@ -87,7 +90,7 @@ void fge_default_params(fge_params *p);
 /* Human-readable name of a status code (static string). */
 const char *fge_status_string(int status);
 
-/* Library ABI version (increments when fge_params or a signature changes). */
+/* Library ABI version (increments when fge_params or a signature changes); this header is 2. */
 int32_t fge_version(void);
 
 /* ---- host-only planning (no GPU needed) ---------------------------------------------- */

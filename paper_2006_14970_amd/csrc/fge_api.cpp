@@ -10,7 +10,7 @@
 
 namespace {
 
-constexpr int32_t kAbiVersion = 1;
+constexpr int32_t kAbiVersion = 2;
 
 struct ProfileRecord {
     int level;          // 0 = finest
@@ -71,6 +71,7 @@ void fge_default_params(fge_params *p) {
     p->kernel = FGE_KERNEL_AUTO;
     p->strip_rows = 0;
     p->coarse_max_px = 0;
+    p->tile_max_px = 0;
 }
 
 const char *fge_status_string(int status) {
@@ -183,9 +184,12 @@ fge_status fge_estimate_foreground(const void *I, const void *alpha, int32_t W, 
         io.omega = prm.omega;
         io.eps = prm.eps_r;
         LaunchTimer timer(n - 1 - i, s);
-        const int err = plan.fused[i]
-                            ? fge::launch_fine_fused(io, prm.strip_rows, prm.storage, s)
-                            : fge::launch_naive_level(io, plan.lv[i].iters, prm.storage, s);
+        int err = 0;
+        switch (plan.kind[i]) {
+            case fge::kKindStream: err = fge::launch_fine_fused(io, prm.strip_rows, prm.storage, s); break;
+            case fge::kKindTile: err = fge::launch_fine_tile(io, prm.storage, s); break;
+            default: err = fge::launch_naive_level(io, plan.lv[i].iters, prm.storage, s); break;
+        }
         if (err) return FGE_EHIP;
     }
     return FGE_OK;

@@ -10,9 +10,13 @@ namespace fge {
 
 constexpr int kMaxLevels = 16;         // 32767 needs 15 levels
 constexpr int kMaxSide = 32767;        // keeps x * w_src inside int32
-constexpr int kCoarseMaxPx = 4096;     // LDS-resident coarse levels: 7 float planes fit 112 KB
-constexpr int kCoarseThreads = 1024;
-constexpr int kCoarsePxPerThread = kCoarseMaxPx / kCoarseThreads;
+constexpr int kCoarseMaxPx = 4096;     // LDS-resident coarse levels: 2 float4 per pixel = 128 KB
+constexpr int kCoarseThreads = 512;
+constexpr int kCoarsePairsPerThread = 4;   // a coarse level has at most 2048 pixel pairs
+constexpr int kCoarseMaxPairs = kCoarseThreads * kCoarsePairsPerThread;
+
+enum LevelKind { kKindCoarse = 0, kKindStream = 1, kKindTile = 2, kKindNaive = 3 };
+constexpr long kTileMaxPxDefault = 1L << 20;   // fine levels up to ~1 MP use the tile kernel
 
 struct Level {
     int w, h, iters;
@@ -31,7 +35,7 @@ struct Plan {
     size_t buf_off[2] = {0, 0};
     size_t buf_px[2] = {0, 0};
     size_t ws_bytes = 0;
-    bool fused[kMaxLevels] = {};   // per fine level: fused streaming kernel or naive path
+    int kind[kMaxLevels] = {};     // per fine level: a LevelKind
 };
 
 int num_levels(int W, int H);
@@ -45,7 +49,7 @@ struct LevelIO {
     const void *A;      // full-resolution alpha, W*H
     int W, H;
     const void *Fp;     // previous level F (3 planes wp*hp), nullptr: the 1x1 zero start
-    const void *Bp;
+    const void *Bp;     // previous level B; always Fp + 3 planes (one workspace buffer)
     int wp, hp;
     void *Fo;           // this level's F, B (3 planes w*h each)
     void *Bo;
@@ -56,6 +60,7 @@ struct LevelIO {
 int launch_coarse(const Plan &plan, const void *I, const void *A, void *Fo, void *Bo,
                   float omega, float eps, int storage, void *stream);
 int launch_fine_fused(const LevelIO &io, int strip_rows, int storage, void *stream);
+int launch_fine_tile(const LevelIO &io, int storage, void *stream);
 int launch_naive_level(const LevelIO &io, int iters, int storage, void *stream);
 
 }  // namespace fge

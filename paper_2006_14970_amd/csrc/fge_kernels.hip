@@ -52,6 +52,14 @@ __device__ __forceinline__ float rcp(float v) { return __builtin_amdgcn_rcpf(v);
 // that branches on it are scalar.
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// Workgroup barrier that orders LDS only.  __syncthreads() also waits for every outstanding
+// global load of the thread, which would serialise the prefetches issued before a barrier.
+__device__ __forceinline__ void lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // Lane i receives v from lane i-1; lane 0 keeps `self` (DPP wave_shr:1, disabled lanes keep old).
 __device__ __forceinline__ float from_left(float v, float self) {
     return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(self), __float_as_int(v),
@@ -83,103 +91,210 @@ struct CoarseArgs {
     float omega, eps;
 };
 
-template <typename T>
-__global__ __launch_bounds__(kCoarseThreads) void coarse_kernel(CoarseArgs args) {
-    __shared__ float sA[kCoarseMaxPx];
-    __shared__ float sF[3 * kCoarseMaxPx];
-    __shared__ float sB[3 * kCoarseMaxPx];
+// Pixel pairs (2j, 2j+1) of row y owned by one thread: thread t owns pairs t and t + 1024.
+struct CoarsePair {
+    int p0;          // LDS index of the pair's first pixel (y * w + 2j)
+    int x0, y;
+    bool valid0, valid1;
+};
 
+template <typename T>
+__device__ __forceinline__ void coarse_gather_inputs(const CoarseArgs &args, int w, int h,
+                                                     const CoarsePair (&pr)[kCoarsePairsPerThread],
+                                                     float (&ni)[kCoarsePairsPerThread][2][3],
+                                                     float (&na)[kCoarsePairsPerThread][2]) {
     const T *I = static_cast<const T *>(args.I);
     const T *A = static_cast<const T *>(args.A);
-    const int W = args.W, H = args.H;
-    const size_t planeI = static_cast<size_t>(W) * H;
+    const size_t planeI = static_cast<size_t>(args.W) * args.H;
+#pragma unroll
+    for (int k = 0; k < kCoarsePairsPerThread; ++k) {
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            const bool ok = s == 0 ? pr[k].valid0 : pr[k].valid1;
+            const int x = ok ? pr[k].x0 + s : 0, y = ok ? pr[k].y : 0;
+            const size_t src = static_cast<size_t>(y * args.H / h) * args.W + x * args.W / w;
+            na[k][s] = ldf(A + src);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) ni[k][s][c] = ldf(I + c * planeI + src);
+        }
+    }
+}
+
+__device__ __forceinline__ void coarse_pairs(int tid, int w, int h,
+                                             CoarsePair (&pr)[kCoarsePairsPerThread]) {
+    const int pw = (w + 1) >> 1;
+#pragma unroll
+    for (int k = 0; k < kCoarsePairsPerThread; ++k) {
+        const int q = tid + k * kCoarseThreads;
+        const int y = q / pw;
+        const int j = q - y * pw;
+        pr[k].y = y;
+        pr[k].x0 = 2 * j;
+        pr[k].p0 = y * w + 2 * j;
+        pr[k].valid0 = y < h;
+        pr[k].valid1 = y < h && 2 * j + 1 < w;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kCoarseThreads) void coarse_kernel(CoarseArgs args) {
+    // Per pixel two float4 records: (F0, F1, F2, alpha) and (B0, B1, B2, unused).
+    __shared__ float4 sFA[kCoarseMaxPx];
+    __shared__ float4 sB[kCoarseMaxPx];
+
     const int tid = threadIdx.x;
     const float omega = args.omega, eps = args.eps;
+
+    CoarsePair pr[kCoarsePairsPerThread];
+    float iv[kCoarsePairsPerThread][2][3], av[kCoarsePairsPerThread][2];
+    float ni[kCoarsePairsPerThread][2][3], na[kCoarsePairsPerThread][2];
+    coarse_pairs(tid, args.lw[0], args.lh[0], pr);
+    coarse_gather_inputs<T>(args, args.lw[0], args.lh[0], pr, ni, na);
 
     int wp = 1, hp = 1;
     for (int l = 0; l < args.nc; ++l) {
         const int w = args.lw[l], h = args.lh[l], iters = args.lit[l];
-        const int n = w * h;
-
-        // Resize: alpha from the full-resolution matte, F and B from the previous level (the
-        // level before the first is the 1x1 zero start).  Gather into registers first, since
-        // the new level overwrites the old one in place.
-        float ra[kCoarsePxPerThread], rf[kCoarsePxPerThread][3], rb[kCoarsePxPerThread][3];
 #pragma unroll
-        for (int k = 0; k < kCoarsePxPerThread; ++k) {
-            const int p = tid + k * kCoarseThreads;
-            ra[k] = 0.0f;
+        for (int k = 0; k < kCoarsePairsPerThread; ++k)
 #pragma unroll
-            for (int c = 0; c < 3; ++c) rf[k][c] = rb[k][c] = 0.0f;
-            if (p < n) {
-                const int y = p / w, x = p - y * w;
-                ra[k] = ldf(A + static_cast<size_t>(y * H / h) * W + x * W / w);
-                if (l > 0) {
-                    const int q = (y * hp / h) * wp + x * wp / w;
+            for (int s = 0; s < 2; ++s) {
+                av[k][s] = na[k][s];
 #pragma unroll
-                    for (int c = 0; c < 3; ++c) {
-                        rf[k][c] = sF[c * kCoarseMaxPx + q];
-                        rb[k][c] = sB[c * kCoarseMaxPx + q];
-                    }
+                for (int c = 0; c < 3; ++c) iv[k][s][c] = ni[k][s][c];
+            }
+        // Resize F and B from the previous level (the 1x1 zero start before level 0): gather
+        // into registers, then overwrite LDS with the new level.
+        float4 rf[kCoarsePairsPerThread][2], rb[kCoarsePairsPerThread][2];
+#pragma unroll
+        for (int k = 0; k < kCoarsePairsPerThread; ++k)
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                rf[k][s] = make_float4(0.f, 0.f, 0.f, av[k][s]);
+                rb[k][s] = make_float4(0.f, 0.f, 0.f, 0.f);
+                const bool ok = (s == 0 ? pr[k].valid0 : pr[k].valid1) && l > 0;
+                const int q = ok ? (pr[k].y * hp / h) * wp + (pr[k].x0 + s) * wp / w : 0;
+                const float4 f = sFA[q];
+                const float4 g = sB[q];
+                if (ok) {
+                    rf[k][s] = make_float4(f.x, f.y, f.z, av[k][s]);
+                    rb[k][s] = g;
                 }
             }
-        }
-        __syncthreads();
+        lds_sync();
 #pragma unroll
-        for (int k = 0; k < kCoarsePxPerThread; ++k) {
-            const int p = tid + k * kCoarseThreads;
-            if (p < n) {
-                sA[p] = ra[k];
+        for (int k = 0; k < kCoarsePairsPerThread; ++k)
 #pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    sF[c * kCoarseMaxPx + p] = rf[k][c];
-                    sB[c * kCoarseMaxPx + p] = rb[k][c];
+            for (int s = 0; s < 2; ++s) {
+                const bool ok = s == 0 ? pr[k].valid0 : pr[k].valid1;
+                if (ok) {
+                    sFA[pr[k].p0 + s] = rf[k][s];
+                    sB[pr[k].p0 + s] = rb[k][s];
                 }
             }
+        // Start the next level's input gather now; it completes during this level's sweeps.
+        CoarsePair nx[kCoarsePairsPerThread];
+        if (l + 1 < args.nc) {
+            coarse_pairs(tid, args.lw[l + 1], args.lh[l + 1], nx);
+            coarse_gather_inputs<T>(args, args.lw[l + 1], args.lh[l + 1], nx, ni, na);
         }
-        __syncthreads();
+        lds_sync();
 
-        // Sweeps: each half-sweep updates one colour; thread q owns the pair of columns
-        // (2j, 2j+1) of row y and updates the one of the current colour.
-        const int pw = (w + 1) >> 1;
-        const int npairs = pw * h;
+        // Per-pixel constants of this level, stored by colour: entry [k][c] describes the pixel
+        // of pair k updated in half-sweep c, i.e. column x0 + ((y + c) & 1).
+        int cpix[kCoarsePairsPerThread][2], cnb[kCoarsePairsPerThread][2][4];
+        bool cok[kCoarsePairsPerThread][2];
+        float cw[kCoarsePairsPerThread][2][4], cka[kCoarsePairsPerThread][2], ckb[kCoarsePairsPerThread][2];
+        float ca[kCoarsePairsPerThread][2], ci[kCoarsePairsPerThread][2][3];
+#pragma unroll
+        for (int k = 0; k < kCoarsePairsPerThread; ++k) {
+            int tnb[2][4];
+            float tw[2][4], tka[2], tkb[2];
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                const int x = min(pr[k].x0 + s, w - 1), y = min(pr[k].y, h - 1);
+                const int i = y * w + x;
+                tnb[s][0] = x > 0 ? i - 1 : i;
+                tnb[s][1] = x < w - 1 ? i + 1 : i;
+                tnb[s][2] = y > 0 ? i - w : i;
+                tnb[s][3] = y < h - 1 ? i + w : i;
+                const float a = av[k][s];
+                float sj[4], S = 0.0f;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    sj[j] = weight(a, sFA[tnb[s][j]].w, omega, eps);
+                    S += sj[j];
+                }
+                const float iS = rcp(S), b = 1.0f - a;
+                const float kk = rcp(S + fmaf(a, a, b * b));
+#pragma unroll
+                for (int j = 0; j < 4; ++j) tw[s][j] = sj[j] * iS;
+                tka[s] = a * kk;
+                tkb[s] = b * kk;
+            }
+            const bool odd = pr[k].y & 1;
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                // pixel slot updated in half-sweep c: c for even rows, 1 - c for odd rows
+                const bool hi = odd ? (c == 0) : (c == 1);
+                cpix[k][c] = pr[k].p0 + (hi ? 1 : 0);
+                cok[k][c] = hi ? pr[k].valid1 : pr[k].valid0;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    cnb[k][c][j] = hi ? tnb[1][j] : tnb[0][j];
+                    cw[k][c][j] = hi ? tw[1][j] : tw[0][j];
+                }
+                cka[k][c] = hi ? tka[1] : tka[0];
+                ckb[k][c] = hi ? tkb[1] : tkb[0];
+                ca[k][c] = hi ? av[k][1] : av[k][0];
+#pragma unroll
+                for (int ch = 0; ch < 3; ++ch) ci[k][c][ch] = hi ? iv[k][1][ch] : iv[k][0][ch];
+            }
+        }
+
+        // Sweeps: in half-sweep c every pair updates its pixel of colour c.  Pair slots that no
+        // thread of the level uses are skipped as a whole (a uniform test); inside a slot the
+        // reads and the arithmetic are unconditional (indices are clamped), only the store is
+        // guarded, so the slot's LDS reads are all in flight together.
+        const int npairs = ((w + 1) >> 1) * h;
         for (int it = 0; it < iters; ++it) {
-            for (int colour = 0; colour < 2; ++colour) {
-                for (int q = tid; q < npairs; q += kCoarseThreads) {
-                    const int y = q / pw;
-                    const int x = 2 * (q - y * pw) + ((y + colour) & 1);
-                    if (x < w) {
-                        const int i = y * w + x;
-                        const float a = sA[i];
-                        const int nb[4] = {y * w + (x > 0 ? x - 1 : 0), y * w + (x < w - 1 ? x + 1 : w - 1),
-                                           (y > 0 ? y - 1 : 0) * w + x, (y < h - 1 ? y + 1 : h - 1) * w + x};
-                        float s[4], S = 0.0f;
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+#pragma unroll
+                for (int k = 0; k < kCoarsePairsPerThread; ++k) {
+                    if (k * kCoarseThreads < npairs) {
+                        float fb[3] = {0.f, 0.f, 0.f}, bb[3] = {0.f, 0.f, 0.f};
 #pragma unroll
                         for (int j = 0; j < 4; ++j) {
-                            s[j] = weight(a, sA[nb[j]], omega, eps);
-                            S += s[j];
+                            const float wj = cw[k][c][j];
+                            const float4 f = sFA[cnb[k][c][j]];
+                            const float4 g = sB[cnb[k][c][j]];
+                            fb[0] = fmaf(wj, f.x, fb[0]);
+                            fb[1] = fmaf(wj, f.y, fb[1]);
+                            fb[2] = fmaf(wj, f.z, fb[2]);
+                            bb[0] = fmaf(wj, g.x, bb[0]);
+                            bb[1] = fmaf(wj, g.y, bb[1]);
+                            bb[2] = fmaf(wj, g.z, bb[2]);
                         }
-                        const float iS = 1.0f / S;
-                        const float b = 1.0f - a;
-                        const float k = 1.0f / (S + fmaf(a, a, b * b));
-                        const size_t src = static_cast<size_t>(y * H / h) * W + x * W / w;
+                        const float a = ca[k][c], b = 1.0f - a;
+                        float fo[3], bo[3];
 #pragma unroll
-                        for (int c = 0; c < 3; ++c) {
-                            float P = 0.0f, Q = 0.0f;
-#pragma unroll
-                            for (int j = 0; j < 4; ++j) {
-                                P = fmaf(s[j], sF[c * kCoarseMaxPx + nb[j]], P);
-                                Q = fmaf(s[j], sB[c * kCoarseMaxPx + nb[j]], Q);
-                            }
-                            const float fb = P * iS, bb = Q * iS;
-                            const float r = ldf(I + c * planeI + src) - a * fb - b * bb;
-                            sF[c * kCoarseMaxPx + i] = clamp01(fmaf(a * k, r, fb));
-                            sB[c * kCoarseMaxPx + i] = clamp01(fmaf(b * k, r, bb));
+                        for (int ch = 0; ch < 3; ++ch) {
+                            const float r = ci[k][c][ch] - a * fb[ch] - b * bb[ch];
+                            fo[ch] = clamp01(fmaf(cka[k][c], r, fb[ch]));
+                            bo[ch] = clamp01(fmaf(ckb[k][c], r, bb[ch]));
+                        }
+                        if (cok[k][c]) {
+                            sFA[cpix[k][c]] = make_float4(fo[0], fo[1], fo[2], a);
+                            sB[cpix[k][c]] = make_float4(bo[0], bo[1], bo[2], 0.0f);
                         }
                     }
                 }
-                __syncthreads();
+                lds_sync();
             }
+        }
+        if (l + 1 < args.nc) {
+#pragma unroll
+            for (int k = 0; k < kCoarsePairsPerThread; ++k) pr[k] = nx[k];
         }
         wp = w;
         hp = h;
@@ -190,12 +305,243 @@ __global__ __launch_bounds__(kCoarseThreads) void coarse_kernel(CoarseArgs args)
     T *Bo = static_cast<T *>(args.Bo);
     const int n = wp * hp;
     for (int p = tid; p < n; p += kCoarseThreads) {
+        const float4 f = sFA[p], g = sB[p];
+        stf(Fo + p, f.x);
+        stf(Fo + n + p, f.y);
+        stf(Fo + 2 * static_cast<size_t>(n) + p, f.z);
+        stf(Bo + p, g.x);
+        stf(Bo + n + p, g.y);
+        stf(Bo + 2 * static_cast<size_t>(n) + p, g.z);
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// Tile kernel: one fine level, one workgroup per 32x32 output tile, state in LDS.
+// ------------------------------------------------------------------------------------------
+//
+// The workgroup loads its tile plus a ring of kTileHalo pixels (clamped to the image) in one
+// shot -- alpha, F and B into LDS, I into registers -- runs the level's red-black half-sweeps
+// with neighbours clamped to the loaded region, and stores the core.  Where the region edge is
+// the image border the clamp is exactly Algorithm 1's; elsewhere the ring absorbs the stale
+// neighbours (one ring per half-sweep).  For mid-size levels this replaces the streaming
+// kernel's per-row pipeline fill by a single memory round trip.
+
+constexpr int kTileCore = 32;
+constexpr int kTileHalo = 4;                      // = half-sweeps of a 2-sweep level
+constexpr int kTileSide = kTileCore + 2 * kTileHalo;
+constexpr int kTilePx = kTileSide * kTileSide;
+constexpr int kTileThreads = 512;
+constexpr int kTilePairs = (kTileSide / 2) * kTileSide;
+constexpr int kTilePairsPerThread = (kTilePairs + kTileThreads - 1) / kTileThreads;
+
+struct TileArgs {
+    const void *I;
+    const void *A;
+    int W, H;
+    const void *Fp;
+    const void *Bp;
+    int wp, hp;
+    void *Fo;
+    void *Bo;
+    int w, h;
+    int tiles_x;
+    float omega, eps;
+};
+
+template <typename T>
+__global__ __launch_bounds__(kTileThreads) void tile_kernel(TileArgs args) {
+    __shared__ float4 sFA[kTilePx];   // (F0, F1, F2, alpha)
+    __shared__ float4 sB[kTilePx];    // (B0, B1, B2, unused)
+
+    const T *I = static_cast<const T *>(args.I);
+    const T *A = static_cast<const T *>(args.A);
+    const T *Fp = static_cast<const T *>(args.Fp);
+    const T *Bp = static_cast<const T *>(args.Bp);
+    const int w = args.w, h = args.h;
+    const size_t planeI = static_cast<size_t>(args.W) * args.H;
+    const size_t planeP = static_cast<size_t>(args.wp) * args.hp;
+    const float omega = args.omega, eps = args.eps;
+    const int tid = threadIdx.x;
+
+    const int tx = blockIdx.x % args.tiles_x, ty = blockIdx.x / args.tiles_x;
+    const int cx0 = tx * kTileCore, cy0 = ty * kTileCore;
+    const int cx1 = min(w, cx0 + kTileCore), cy1 = min(h, cy0 + kTileCore);
+    const int rx0 = max(0, cx0 - kTileHalo), ry0 = max(0, cy0 - kTileHalo);
+    const int rw = min(w, cx1 + kTileHalo) - rx0, rh = min(h, cy1 + kTileHalo) - ry0;
+    const int pw = (rw + 1) >> 1;
+    const int npairs = pw * rh;
+
+    // Owned pairs: q = tid + k * threads covers region columns (2j, 2j+1) of region row y.
+    // All global gathers are issued before any LDS store, so they are in flight together.
+    int qy[kTilePairsPerThread], qx[kTilePairsPerThread];
+    bool qv0[kTilePairsPerThread], qv1[kTilePairsPerThread];
+    float iv[kTilePairsPerThread][2][3];
+    float4 lf[kTilePairsPerThread][2], lb[kTilePairsPerThread][2];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            stf(Fo + static_cast<size_t>(c) * n + p, sF[c * kCoarseMaxPx + p]);
-            stf(Bo + static_cast<size_t>(c) * n + p, sB[c * kCoarseMaxPx + p]);
+    for (int k = 0; k < kTilePairsPerThread; ++k) {
+        const int q = tid + k * kTileThreads;
+        const int y = q / pw;
+        qy[k] = y;
+        qx[k] = 2 * (q - y * pw);
+        qv0[k] = q < npairs;
+        qv1[k] = q < npairs && qx[k] + 1 < rw;
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            const bool ok = s ? qv1[k] : qv0[k];
+            const int gx = rx0 + (ok ? qx[k] + s : 0), gy = ry0 + (ok ? y : 0);
+            const size_t src = static_cast<size_t>(gy * args.H / h) * args.W + gx * args.W / w;
+            const size_t prv = static_cast<size_t>(gy * args.hp / h) * args.wp + gx * args.wp / w;
+            const float a = ldf(A + src);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) iv[k][s][c] = ldf(I + c * planeI + src);
+            lf[k][s] = make_float4(ldf(Fp + prv), ldf(Fp + planeP + prv), ldf(Fp + 2 * planeP + prv), a);
+            lb[k][s] = make_float4(ldf(Bp + prv), ldf(Bp + planeP + prv), ldf(Bp + 2 * planeP + prv), 0.0f);
         }
     }
+#pragma unroll
+    for (int k = 0; k < kTilePairsPerThread; ++k)
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+            if (s ? qv1[k] : qv0[k]) {
+                const int li = qy[k] * rw + qx[k] + s;
+                sFA[li] = lf[k][s];
+                sB[li] = lb[k][s];
+            }
+    lds_sync();
+
+    // Weights of the pixel updated in half-sweep c of each pair (colour-ordered, as in the
+    // coarse kernel): slot (rx0 + ry0 + y + c) & 1 of the pair.
+    int cpix[kTilePairsPerThread][2], cnb[kTilePairsPerThread][2][4];
+    bool cok[kTilePairsPerThread][2];
+    float cw[kTilePairsPerThread][2][4], cka[kTilePairsPerThread][2], ckb[kTilePairsPerThread][2];
+    float ca[kTilePairsPerThread][2], ci[kTilePairsPerThread][2][3];
+#pragma unroll
+    for (int k = 0; k < kTilePairsPerThread; ++k) {
+        int tnb[2][4];
+        float tw[2][4], tka[2], tkb[2], ta[2];
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            const int x = min(qx[k] + s, rw - 1), y = min(qy[k], rh - 1);
+            const int i = y * rw + x;
+            tnb[s][0] = x > 0 ? i - 1 : i;
+            tnb[s][1] = x < rw - 1 ? i + 1 : i;
+            tnb[s][2] = y > 0 ? i - rw : i;
+            tnb[s][3] = y < rh - 1 ? i + rw : i;
+            const float a = sFA[i].w;
+            float sj[4], S = 0.0f;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                sj[j] = weight(a, sFA[tnb[s][j]].w, omega, eps);
+                S += sj[j];
+            }
+            const float iS = rcp(S), b = 1.0f - a;
+            const float kk = rcp(S + fmaf(a, a, b * b));
+#pragma unroll
+            for (int j = 0; j < 4; ++j) tw[s][j] = sj[j] * iS;
+            tka[s] = a * kk;
+            tkb[s] = b * kk;
+            ta[s] = a;
+        }
+        const bool flip = (rx0 + ry0 + qy[k]) & 1;
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const bool hi = flip ? (c == 0) : (c == 1);
+            cpix[k][c] = qy[k] * rw + qx[k] + (hi ? 1 : 0);
+            cok[k][c] = hi ? qv1[k] : qv0[k];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                cnb[k][c][j] = hi ? tnb[1][j] : tnb[0][j];
+                cw[k][c][j] = hi ? tw[1][j] : tw[0][j];
+            }
+            cka[k][c] = hi ? tka[1] : tka[0];
+            ckb[k][c] = hi ? tkb[1] : tkb[0];
+            ca[k][c] = hi ? ta[1] : ta[0];
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) ci[k][c][ch] = hi ? iv[k][1][ch] : iv[k][0][ch];
+        }
+    }
+
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            // Unconditional reads and arithmetic (indices are clamped into the region), guarded
+            // stores: the reads of all owned pairs are in flight together.
+            float fo[kTilePairsPerThread][3], bo[kTilePairsPerThread][3];
+#pragma unroll
+            for (int k = 0; k < kTilePairsPerThread; ++k) {
+                float fb[3] = {0.f, 0.f, 0.f}, bb[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const float wj = cw[k][c][j];
+                    const float4 f = sFA[cnb[k][c][j]];
+                    const float4 g = sB[cnb[k][c][j]];
+                    fb[0] = fmaf(wj, f.x, fb[0]);
+                    fb[1] = fmaf(wj, f.y, fb[1]);
+                    fb[2] = fmaf(wj, f.z, fb[2]);
+                    bb[0] = fmaf(wj, g.x, bb[0]);
+                    bb[1] = fmaf(wj, g.y, bb[1]);
+                    bb[2] = fmaf(wj, g.z, bb[2]);
+                }
+                const float a = ca[k][c], b = 1.0f - a;
+#pragma unroll
+                for (int ch = 0; ch < 3; ++ch) {
+                    const float r = ci[k][c][ch] - a * fb[ch] - b * bb[ch];
+                    fo[k][ch] = clamp01(fmaf(cka[k][c], r, fb[ch]));
+                    bo[k][ch] = clamp01(fmaf(ckb[k][c], r, bb[ch]));
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < kTilePairsPerThread; ++k)
+                if (cok[k][c]) {
+                    sFA[cpix[k][c]] = make_float4(fo[k][0], fo[k][1], fo[k][2], ca[k][c]);
+                    sB[cpix[k][c]] = make_float4(bo[k][0], bo[k][1], bo[k][2], 0.0f);
+                }
+            lds_sync();
+        }
+    }
+
+    // Store the core.
+    T *Fo = static_cast<T *>(args.Fo);
+    T *Bo = static_cast<T *>(args.Bo);
+    const size_t planeO = static_cast<size_t>(w) * h;
+    const int cw_ = cx1 - cx0, ch_ = cy1 - cy0;
+    for (int p = tid; p < cw_ * ch_; p += kTileThreads) {
+        const int yy = p / cw_, xx = p - yy * cw_;
+        const int gx = cx0 + xx, gy = cy0 + yy;
+        const int li = (gy - ry0) * rw + (gx - rx0);
+        const float4 f = sFA[li], g = sB[li];
+        const size_t o = static_cast<size_t>(gy) * w + gx;
+        stf(Fo + o, f.x);
+        stf(Fo + planeO + o, f.y);
+        stf(Fo + 2 * planeO + o, f.z);
+        stf(Bo + o, g.x);
+        stf(Bo + planeO + o, g.y);
+        stf(Bo + 2 * planeO + o, g.z);
+    }
+}
+
+template <typename T>
+int launch_tile_t(const LevelIO &io, hipStream_t s) {
+    TileArgs a{};
+    a.I = io.I;
+    a.A = io.A;
+    a.W = io.W;
+    a.H = io.H;
+    a.Fp = io.Fp;
+    a.Bp = io.Bp;
+    a.wp = io.wp;
+    a.hp = io.hp;
+    a.Fo = io.Fo;
+    a.Bo = io.Bo;
+    a.w = io.w;
+    a.h = io.h;
+    a.omega = io.omega;
+    a.eps = io.eps;
+    a.tiles_x = (io.w + kTileCore - 1) / kTileCore;
+    const int tiles = a.tiles_x * ((io.h + kTileCore - 1) / kTileCore);
+    hipLaunchKernelGGL(tile_kernel<T>, dim3(tiles), dim3(kTileThreads), 0, s, a);
+    return static_cast<int>(hipGetLastError());
 }
 
 // ------------------------------------------------------------------------------------------
@@ -264,13 +610,14 @@ __global__ void halfsweep_kernel(const T *I, const T *A, int W, int H, T *F, T *
 // ------------------------------------------------------------------------------------------
 
 constexpr int kNHS = 4;                 // half-sweeps per level (two sweeps)
-constexpr int kWin = kNHS + 2;          // rows held per wave: r-1 .. r+NHS
+constexpr int kPD = 2;                  // rows loaded ahead of the row being consumed
+constexpr int kWin = kNHS + 2 + kPD;    // rows held per wave: t-5 .. t+kPD
 constexpr int kHalo = kNHS;             // invalid ring after kNHS half-sweeps
 constexpr int kStripCols = 128;         // two columns per lane
 constexpr int kFirstCore = kStripCols - kHalo;          // strip 0 keeps columns [0, 124)
 constexpr int kMidCore = kStripCols - 2 * kHalo;        // interior strips keep 120 columns
-constexpr int kPD = 2;                  // rows prefetched ahead
 constexpr int kWavesPerBlock = 4;
+constexpr int kRsrcWord3 = 0x00020000;  // raw buffer resource, gfx9 family
 
 struct FineArgs {
     const void *I;
@@ -286,39 +633,99 @@ struct FineArgs {
     int nx, ny, strip_rows;
 };
 
-// Number of column strips for a level of width w (see the geometry in fine_kernel).
+// Number of column strips for a level of width w (see the geometry in fine_strip).
 __host__ __device__ inline int fine_strips_x(int w) {
     if (w <= kStripCols) return 1;
     const int rest = w - (kFirstCore + kFirstCore);
     return 2 + (rest > 0 ? (rest + kMidCore - 1) / kMidCore : 0);
 }
 
-template <typename T>
-struct Raw {
-    T a[2];
-    T i[2][3];
-    T f[2][3];
-    T b[2][3];
-};
+// Raw buffer resource over `bytes` bytes (< 4 GiB, checked by the planner).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t tensor_rsrc(const void *base, size_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), 0,
+                                             static_cast<int>(static_cast<uint32_t>(bytes)),
+                                             kRsrcWord3);
+}
 
-// Per-wave constants of a strip.  Every image plane has its own base pointer (uniform, kept in
-// SGPRs) and is addressed with 32-bit byte offsets: one plane holds at most 32767^2 elements,
-// whose float32 byte offsets still fit in 32 bits, so the loads use the scalar-base form.
 template <typename T>
+__device__ __forceinline__ uint32_t bload(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    if constexpr (sizeof(T) == 4)
+        return __builtin_amdgcn_raw_buffer_load_b32(r, static_cast<int>(voff), static_cast<int>(soff), 0);
+    else
+        return __builtin_amdgcn_raw_buffer_load_b16(r, static_cast<int>(voff), static_cast<int>(soff), 0);
+}
+
+// Float-typed raw buffer loads (the LLVM intrinsics directly): the register window then only
+// ever holds floats, which keeps it promotable to registers.
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+__device__ float raw_load_f32(__amdgpu_buffer_rsrc_t r, int voff, int soff, int aux)
+    __asm("llvm.amdgcn.raw.ptr.buffer.load.f32");
+__device__ f32x2 raw_load_v2f32(__amdgpu_buffer_rsrc_t r, int voff, int soff, int aux)
+    __asm("llvm.amdgcn.raw.ptr.buffer.load.v2f32");
+
+__device__ __forceinline__ float loadf(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    return raw_load_f32(r, static_cast<int>(voff), static_cast<int>(soff), 0);
+}
+__device__ __forceinline__ f32x2 loadf2(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    return raw_load_v2f32(r, static_cast<int>(voff), static_cast<int>(soff), 0);
+}
+
+template <typename T>
+__device__ __forceinline__ float bits_to_float(uint32_t v) {
+    if constexpr (sizeof(T) == 4) {
+        return __uint_as_float(v);
+    } else {
+        const unsigned short hb = static_cast<unsigned short>(v);
+        return static_cast<float>(__builtin_bit_cast(_Float16, hb));
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, float v) {
+    if constexpr (sizeof(T) == 4) {
+        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, static_cast<int>(voff),
+                                              static_cast<int>(soff), 0);
+    } else {
+        const _Float16 hv = static_cast<_Float16>(v);
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, hv), r,
+                                              static_cast<int>(voff), static_cast<int>(soff), 0);
+    }
+}
+
+// Lane i receives v from lane i-1; lane 0 receives 0 (DPP wave_shr:1 with bound control), a
+// form the compiler can fold into the consuming FMA.  Only used where lane 0 is halo.
+__device__ __forceinline__ float from_left_z(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xF, 0xF, true));
+}
+
+// Lane i receives v from lane i+1; lane 63 receives 0.
+__device__ __forceinline__ float from_right_z(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xF, 0xF, true));
+}
+
+// Per-wave constants of a strip.  Each tensor (I, alpha, previous F and B, F, B) is one buffer
+// resource (the previous level's F and B are one workspace buffer, B right after F); a load takes the row's byte offset plus the plane's byte offset as the scalar
+// offset and the lane's column as the (loop-invariant) vector offset, so there is no per-row
+// vector address arithmetic.  The planner sends a level here only when every tensor is below
+// 4 GiB, the reach of a buffer resource.
 struct FineGeo {
-    const char *I[3], *A, *Fp[3], *Bp[3];
-    char *Fo[3], *Bo[3];
+    __amdgpu_buffer_rsrc_t I, A, P, Fo, Bo;   // P: previous F (planes 0-2) then B (3-5)
+    uint32_t pI, pP, pO;           // plane sizes in bytes (input, previous level, output)
     int W, H, wp, hp, w, h;
     uint32_t sia, sib, spa, spb;   // byte offsets of this lane's source columns
     uint32_t oxa, oxb;             // byte offsets of this lane's output columns
     bool store_a, store_b;         // columns inside this strip's core
-    bool edge_a, edge_b;           // column == w - 1 (right border inside the wave)
+    bool left_a;                   // column a == 0 (left image border inside the wave)
+    bool right_a, right_b;         // column == w - 1 (right image border inside the wave)
     int y0, y1, t0, tlast;
     float omega, eps;
 };
 
-// Register window: row slot = (row - t0) mod kWin, column of the lane's pair.
+// Register window: row slot = (row - t0) mod kWin, column of the lane's pair.  Rows are loaded
+// kPD steps ahead straight into their slot as raw bits (float32: final values; binary16:
+// converted when the row is consumed).
 struct FineWin {
+    uint32_t ra[kWin][2], ri[kWin][2][3], rf[kWin][2][3], rb[kWin][2][3];
     float al[kWin][2];
     float iv[kWin][2][3];
     float fv[kWin][2][3];
@@ -347,47 +754,107 @@ struct RowMap {
     }
 };
 
-template <typename T>
-__device__ __forceinline__ T ldb(const char *base, uint32_t off) {
-    return *reinterpret_cast<const T *>(base + off);
-}
-
-template <typename T>
-__device__ __forceinline__ void stb(char *base, uint32_t off, float v) {
-    *reinterpret_cast<T *>(base + off) = static_cast<T>(v);
-}
-
-// Gather one row: I and alpha from input row qi (nearest), F and B from previous-level row qp.
-template <typename T>
-__device__ __forceinline__ void fine_load_row(const FineGeo<T> &g, Raw<T> &r, int qi, int qp) {
-    const uint32_t ri = static_cast<uint32_t>(qi) * static_cast<uint32_t>(g.W) * sizeof(T);
-    const uint32_t rp = static_cast<uint32_t>(qp) * static_cast<uint32_t>(g.wp) * sizeof(T);
-    const uint32_t ia = ri + g.sia, ib = ri + g.sib, pa = rp + g.spa, pb = rp + g.spb;
-    r.a[0] = ldb<T>(g.A, ia);
-    r.a[1] = ldb<T>(g.A, ib);
+// Gather one row into slot R: I and alpha from input row qi (nearest), F and B from
+// previous-level row qp.
+// Gather one row into slot R: I and alpha from input row qi (nearest), F and B from
+// previous-level row qp.  float32 lands in the float window directly; binary16 lands as raw
+// bits and is converted when the row is consumed.
+template <int R, bool PAIR, typename T>
+__device__ __forceinline__ void fine_load_row(FineWin &v, const FineGeo &g, int qi, int qp) {
+    const uint32_t si = static_cast<uint32_t>(qi) * static_cast<uint32_t>(g.W) * sizeof(T);
+    const uint32_t sp = static_cast<uint32_t>(qp) * static_cast<uint32_t>(g.wp) * sizeof(T);
+    if constexpr (sizeof(T) == 4) {
+        if constexpr (PAIR) {
+            // The lane's two columns are adjacent in the input (identity map) and share one
+            // source column of the previous level (exact 2:1): one load per plane.
+            const f32x2 av = loadf2(g.A, g.sia, si);
+            v.al[R][0] = av.x;
+            v.al[R][1] = av.y;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        r.i[0][c] = ldb<T>(g.I[c], ia);
-        r.i[1][c] = ldb<T>(g.I[c], ib);
-        r.f[0][c] = ldb<T>(g.Fp[c], pa);
-        r.f[1][c] = ldb<T>(g.Fp[c], pb);
-        r.b[0][c] = ldb<T>(g.Bp[c], pa);
-        r.b[1][c] = ldb<T>(g.Bp[c], pb);
+            for (int c = 0; c < 3; ++c) {
+                const f32x2 iv = loadf2(g.I, g.sia, si + c * g.pI);
+                v.iv[R][0][c] = iv.x;
+                v.iv[R][1][c] = iv.y;
+                const uint32_t cp = sp + c * g.pP;
+                v.fv[R][0][c] = v.fv[R][1][c] = loadf(g.P, g.spa, cp);
+                v.bv[R][0][c] = v.bv[R][1][c] = loadf(g.P, g.spa, cp + 3 * g.pP);
+            }
+        } else {
+            v.al[R][0] = loadf(g.A, g.sia, si);
+            v.al[R][1] = loadf(g.A, g.sib, si);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const uint32_t ci = si + c * g.pI, cp = sp + c * g.pP;
+                v.iv[R][0][c] = loadf(g.I, g.sia, ci);
+                v.iv[R][1][c] = loadf(g.I, g.sib, ci);
+                v.fv[R][0][c] = loadf(g.P, g.spa, cp);
+                v.fv[R][1][c] = loadf(g.P, g.spb, cp);
+                v.bv[R][0][c] = loadf(g.P, g.spa, cp + 3 * g.pP);
+                v.bv[R][1][c] = loadf(g.P, g.spb, cp + 3 * g.pP);
+            }
+        }
+    } else {
+        if constexpr (PAIR) {
+            const uint32_t av = bload<float>(g.A, g.sia, si);
+            v.ra[R][0] = av;
+            v.ra[R][1] = av >> 16;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const uint32_t iv = bload<float>(g.I, g.sia, si + c * g.pI);
+                v.ri[R][0][c] = iv;
+                v.ri[R][1][c] = iv >> 16;
+                const uint32_t cp = sp + c * g.pP;
+                v.rf[R][0][c] = v.rf[R][1][c] = bload<T>(g.P, g.spa, cp);
+                v.rb[R][0][c] = v.rb[R][1][c] = bload<T>(g.P, g.spa, cp + 3 * g.pP);
+            }
+        } else {
+            v.ra[R][0] = bload<T>(g.A, g.sia, si);
+            v.ra[R][1] = bload<T>(g.A, g.sib, si);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const uint32_t ci = si + c * g.pI, cp = sp + c * g.pP;
+                v.ri[R][0][c] = bload<T>(g.I, g.sia, ci);
+                v.ri[R][1][c] = bload<T>(g.I, g.sib, ci);
+                v.rf[R][0][c] = bload<T>(g.P, g.spa, cp);
+                v.rf[R][1][c] = bload<T>(g.P, g.spb, cp);
+                v.rb[R][0][c] = bload<T>(g.P, g.spa, cp + 3 * g.pP);
+                v.rb[R][1][c] = bload<T>(g.P, g.spb, cp + 3 * g.pP);
+            }
+        }
     }
 }
 
 template <int R, typename T>
-__device__ __forceinline__ void fine_consume(FineWin &v, const Raw<T> &r) {
+__device__ __forceinline__ void fine_consume(FineWin &v) {
+    if constexpr (sizeof(T) == 4) return;   // already final
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
-        v.al[R][s] = static_cast<float>(r.a[s]);
+        v.al[R][s] = bits_to_float<T>(v.ra[R][s]);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            v.iv[R][s][c] = static_cast<float>(r.i[s][c]);
-            v.fv[R][s][c] = static_cast<float>(r.f[s][c]);
-            v.bv[R][s][c] = static_cast<float>(r.b[s][c]);
+            v.iv[R][s][c] = bits_to_float<T>(v.ri[R][s][c]);
+            v.fv[R][s][c] = bits_to_float<T>(v.rf[R][s][c]);
+            v.bv[R][s][c] = bits_to_float<T>(v.rb[R][s][c]);
         }
     }
+}
+
+// Horizontal neighbours of the pair's two pixels from a per-lane value pair (a, b):
+// left of a is lane-1's b, right of b is lane+1's a.  EDGE strips contain an image border: there
+// the clamp makes the border pixel its own neighbour; elsewhere the wave-edge lanes are halo.
+template <bool EDGE>
+__device__ __forceinline__ float left_of_a(const FineGeo &g, float a, float b) {
+    const float l = from_left_z(b);
+    return EDGE && g.left_a ? a : l;
+}
+template <bool EDGE>
+__device__ __forceinline__ float right_of_b(const FineGeo &g, float a, float b) {
+    const float r = from_right_z(a);
+    return EDGE && g.right_b ? b : r;
+}
+template <bool EDGE>
+__device__ __forceinline__ float right_of_a(const FineGeo &g, float a, float b) {
+    return EDGE && g.right_a ? a : b;
 }
 
 // Weights of row r (slot R) from its own and its neighbours' alpha (rows in slots U and D).
@@ -396,17 +863,13 @@ __device__ __forceinline__ void fine_consume(FineWin &v, const Raw<T> &r) {
 // "update" copies the adjacent image row (weights 1 toward it, 0 elsewhere, no data term).
 // Rows beyond the phantom rows are loaded from the clamped border row and never feed a stored
 // result.
-template <int R, int U, int D, bool EDGE, bool BORDER, typename T>
-__device__ __forceinline__ void fine_constants(FineWin &v, const FineGeo<T> &g, int r) {
+template <int R, int U, int D, bool EDGE, bool BORDER>
+__device__ __forceinline__ void fine_constants(FineWin &v, const FineGeo &g, int r) {
     const float omega = g.omega, eps = g.eps;
     const float a0 = v.al[R][0], a1 = v.al[R][1];
-    const float l0 = from_left(v.al[R][1], a0);        // left of column a: lane-1's column b
-    float r1 = from_right(v.al[R][0], a1);             // right of column b: lane+1's column a
-    float r0 = a1;
-    if (EDGE) {
-        r0 = g.edge_a ? a0 : r0;
-        r1 = g.edge_b ? a1 : r1;
-    }
+    const float l0 = left_of_a<EDGE>(g, a0, a1);
+    const float r0 = right_of_a<EDGE>(g, a0, a1);
+    const float r1 = right_of_b<EDGE>(g, a0, a1);
     const float mid = weight(a0, r0, omega, eps);      // edge between the lane's two columns
     const float sl[2] = {weight(a0, l0, omega, eps), EDGE ? weight(a1, a0, omega, eps) : mid};
     const float sr[2] = {mid, weight(a1, r1, omega, eps)};
@@ -438,110 +901,141 @@ __device__ __forceinline__ void fine_constants(FineWin &v, const FineGeo<T> &g, 
 }
 
 // Half-sweep on the row in slot R: update column S of every lane.
-template <int R, int U, int D, int S, bool EDGE, typename T>
-__device__ __forceinline__ void fine_update(FineWin &v, const FineGeo<T> &g) {
+template <int R, int U, int D, int S, bool EDGE>
+__device__ __forceinline__ void fine_update(FineWin &v, const FineGeo &g) {
     const float a = v.al[R][S], b = 1.0f - a;
     const float cl = v.wl[R][S], cr = v.wr[R][S], cu = v.wu[R][S], cd = v.wd[R][S];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        const float fs = v.fv[R][S][c], bs = v.bv[R][S][c];
         float fL, fR, bL, bR;
         if (S == 0) {
-            fL = from_left(v.fv[R][1][c], fs);
-            bL = from_left(v.bv[R][1][c], bs);
-            fR = v.fv[R][1][c];
-            bR = v.bv[R][1][c];
-            if (EDGE) {
-                fR = g.edge_a ? fs : fR;
-                bR = g.edge_a ? bs : bR;
-            }
+            fL = left_of_a<EDGE>(g, v.fv[R][0][c], v.fv[R][1][c]);
+            bL = left_of_a<EDGE>(g, v.bv[R][0][c], v.bv[R][1][c]);
+            fR = right_of_a<EDGE>(g, v.fv[R][0][c], v.fv[R][1][c]);
+            bR = right_of_a<EDGE>(g, v.bv[R][0][c], v.bv[R][1][c]);
         } else {
             fL = v.fv[R][0][c];
             bL = v.bv[R][0][c];
-            fR = from_right(v.fv[R][0][c], fs);
-            bR = from_right(v.bv[R][0][c], bs);
-            if (EDGE) {
-                fR = g.edge_b ? fs : fR;
-                bR = g.edge_b ? bs : bR;
-            }
+            fR = right_of_b<EDGE>(g, v.fv[R][0][c], v.fv[R][1][c]);
+            bR = right_of_b<EDGE>(g, v.bv[R][0][c], v.bv[R][1][c]);
         }
-        const float fb = fmaf(cd, v.fv[D][S][c], fmaf(cu, v.fv[U][S][c], fmaf(cr, fR, cl * fL)));
-        const float bb = fmaf(cd, v.bv[D][S][c], fmaf(cu, v.bv[U][S][c], fmaf(cr, bR, cl * bL)));
+        // The lane-shifted neighbour (left for column a, right for column b) enters through the
+        // first product, a plain multiply into which the DPP move folds.
+        float fb, bb;
+        if (S == 0) {
+            fb = fmaf(cd, v.fv[D][S][c], fmaf(cu, v.fv[U][S][c], fmaf(cr, fR, cl * fL)));
+            bb = fmaf(cd, v.bv[D][S][c], fmaf(cu, v.bv[U][S][c], fmaf(cr, bR, cl * bL)));
+        } else {
+            fb = fmaf(cd, v.fv[D][S][c], fmaf(cu, v.fv[U][S][c], fmaf(cl, fL, cr * fR)));
+            bb = fmaf(cd, v.bv[D][S][c], fmaf(cu, v.bv[U][S][c], fmaf(cl, bL, cr * bR)));
+        }
         const float r = v.iv[R][S][c] - a * fb - b * bb;
         v.fv[R][S][c] = clamp01(fmaf(v.ka[R][S], r, fb));
         v.bv[R][S][c] = clamp01(fmaf(v.kb[R][S], r, bb));
     }
 }
 
-template <int R, typename T>
-__device__ __forceinline__ void fine_store_row(const FineWin &v, const FineGeo<T> &g, int r) {
-    const uint32_t ro = static_cast<uint32_t>(r) * static_cast<uint32_t>(g.w) * sizeof(T);
-    const uint32_t oa = ro + g.oxa, ob = ro + g.oxb;
+template <typename T>
+__device__ __forceinline__ void bstore_pair(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff,
+                                            float v0, float v1) {
+    // non-temporal: the finest level's F and B are not read again by this pass
+    if constexpr (sizeof(T) == 4) {
+        // The empty asm pins the two values as separate registers: otherwise the compiler reads
+        // them from the window as one vector, which keeps the window out of registers.
+        asm volatile("" : "+v"(v0), "+v"(v1));
+        typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+        const u32x2 d = {__float_as_uint(v0), __float_as_uint(v1)};
+        __builtin_amdgcn_raw_buffer_store_b64(d, r, static_cast<int>(voff), static_cast<int>(soff), 2);
+    } else {
+        const _Float16 h0 = static_cast<_Float16>(v0), h1 = static_cast<_Float16>(v1);
+        const uint32_t d = static_cast<uint32_t>(__builtin_bit_cast(unsigned short, h0)) |
+                           (static_cast<uint32_t>(__builtin_bit_cast(unsigned short, h1)) << 16);
+        __builtin_amdgcn_raw_buffer_store_b32(d, r, static_cast<int>(voff), static_cast<int>(soff), 2);
+    }
+}
+
+template <int R, bool PAIR, typename T>
+__device__ __forceinline__ void fine_store_row(const FineWin &v, const FineGeo &g, int r) {
+    const uint32_t so = static_cast<uint32_t>(r) * static_cast<uint32_t>(g.w) * sizeof(T);
+    if constexpr (PAIR) {
+        if (g.store_a) {   // == store_b: core boundaries are even in a paired strip
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        if (g.store_a) {
-            stb<T>(g.Fo[c], oa, v.fv[R][0][c]);
-            stb<T>(g.Bo[c], oa, v.bv[R][0][c]);
+            for (int c = 0; c < 3; ++c) {
+                bstore_pair<T>(g.Fo, g.oxa, so + c * g.pO, v.fv[R][0][c], v.fv[R][1][c]);
+                bstore_pair<T>(g.Bo, g.oxa, so + c * g.pO, v.bv[R][0][c], v.bv[R][1][c]);
+            }
         }
-        if (g.store_b) {
-            stb<T>(g.Fo[c], ob, v.fv[R][1][c]);
-            stb<T>(g.Bo[c], ob, v.bv[R][1][c]);
+        return;
+    }
+    if (g.store_a) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            bstore<T>(g.Fo, g.oxa, so + c * g.pO, v.fv[R][0][c]);
+            bstore<T>(g.Bo, g.oxa, so + c * g.pO, v.bv[R][0][c]);
+        }
+    }
+    if (g.store_b) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            bstore<T>(g.Fo, g.oxb, so + c * g.pO, v.fv[R][1][c]);
+            bstore<T>(g.Bo, g.oxb, so + c * g.pO, v.bv[R][1][c]);
         }
     }
 }
 
-// One pipeline step at row t (TT = (t - t0) mod 6): take row t from the prefetch buffer and
-// prefetch row t + kPD, compute the weights of row t-1, run half-sweep k on row t-1-k for
+// One pipeline step at row t (TT = (t - t0) mod kWin): load row t + kPD (clamped into the image)
+// into its slot, take row t, compute the weights of row t-1, run half-sweep k on row t-1-k for
 // k = 0..3, and store row t-4, which has now seen both sweeps.
-template <int TT, bool EDGE, bool BORDER, typename T>
-__device__ __forceinline__ void fine_step(FineWin &v, Raw<T> (&raw)[kPD], const FineGeo<T> &g,
-                                          RowMap &mi, RowMap &mp, int t) {
+template <int TT, bool EDGE, bool BORDER, bool PAIR, typename T>
+__device__ __forceinline__ void fine_step(FineWin &v, const FineGeo &g, RowMap &mi, RowMap &mp,
+                                          int t) {
     constexpr int S = (TT + 1) & 1;       // column of the pair updated in this step
-    fine_consume<TT % kWin>(v, raw[TT % kPD]);
     {
         const int tl = t + kPD;
         if (tl >= 1 && tl <= g.h - 1) {
             mi.advance();
             mp.advance();
         }
-        fine_load_row(g, raw[TT % kPD], mi.q, mp.q);
+        fine_load_row<(TT + kPD) % kWin, PAIR, T>(v, g, mi.q, mp.q);
     }
-    fine_constants<(TT + 5) % kWin, (TT + 4) % kWin, TT % kWin, EDGE, BORDER>(v, g, t - 1);
-    fine_update<(TT + 5) % kWin, (TT + 4) % kWin, TT % kWin, S, EDGE>(v, g);
-    fine_update<(TT + 4) % kWin, (TT + 3) % kWin, (TT + 5) % kWin, S, EDGE>(v, g);
-    fine_update<(TT + 3) % kWin, (TT + 2) % kWin, (TT + 4) % kWin, S, EDGE>(v, g);
-    fine_update<(TT + 2) % kWin, (TT + 1) % kWin, (TT + 3) % kWin, S, EDGE>(v, g);
-    if (t - 4 >= g.y0 && t - 4 < g.y1) fine_store_row<(TT + 2) % kWin>(v, g, t - 4);
+    fine_consume<TT % kWin, T>(v);
+    fine_constants<(TT + kWin - 1) % kWin, (TT + kWin - 2) % kWin, TT % kWin, EDGE, BORDER>(v, g, t - 1);
+    fine_update<(TT + kWin - 1) % kWin, (TT + kWin - 2) % kWin, TT % kWin, S, EDGE>(v, g);
+    fine_update<(TT + kWin - 2) % kWin, (TT + kWin - 3) % kWin, (TT + kWin - 1) % kWin, S, EDGE>(v, g);
+    fine_update<(TT + kWin - 3) % kWin, (TT + kWin - 4) % kWin, (TT + kWin - 2) % kWin, S, EDGE>(v, g);
+    fine_update<(TT + kWin - 4) % kWin, (TT + kWin - 5) % kWin, (TT + kWin - 3) % kWin, S, EDGE>(v, g);
+    if (t - 4 >= g.y0 && t - 4 < g.y1) fine_store_row<(TT + kWin - 4) % kWin, PAIR, T>(v, g, t - 4);
     // keep the scheduler from interleaving consecutive steps, which only raises register pressure
     __builtin_amdgcn_sched_barrier(0);
 }
 
-template <bool EDGE, bool BORDER, typename T>
-__device__ __forceinline__ void fine_block(FineWin &v, Raw<T> (&raw)[kPD], const FineGeo<T> &g,
-                                           RowMap &mi, RowMap &mp, int t) {
-    fine_step<0, EDGE, BORDER>(v, raw, g, mi, mp, t);
-    fine_step<1, EDGE, BORDER>(v, raw, g, mi, mp, t + 1);
-    fine_step<2, EDGE, BORDER>(v, raw, g, mi, mp, t + 2);
-    fine_step<3, EDGE, BORDER>(v, raw, g, mi, mp, t + 3);
-    fine_step<4, EDGE, BORDER>(v, raw, g, mi, mp, t + 4);
-    fine_step<5, EDGE, BORDER>(v, raw, g, mi, mp, t + 5);
+template <bool EDGE, bool BORDER, bool PAIR, typename T>
+__device__ __forceinline__ void fine_block(FineWin &v, const FineGeo &g, RowMap &mi, RowMap &mp,
+                                           int t) {
+    fine_step<0, EDGE, BORDER, PAIR, T>(v, g, mi, mp, t);
+    fine_step<1, EDGE, BORDER, PAIR, T>(v, g, mi, mp, t + 1);
+    fine_step<2, EDGE, BORDER, PAIR, T>(v, g, mi, mp, t + 2);
+    fine_step<3, EDGE, BORDER, PAIR, T>(v, g, mi, mp, t + 3);
+    fine_step<4, EDGE, BORDER, PAIR, T>(v, g, mi, mp, t + 4);
+    fine_step<5, EDGE, BORDER, PAIR, T>(v, g, mi, mp, t + 5);
+    fine_step<6, EDGE, BORDER, PAIR, T>(v, g, mi, mp, t + 6);
+    fine_step<7, EDGE, BORDER, PAIR, T>(v, g, mi, mp, t + 7);
 }
 
-template <typename T, bool EDGE>
+template <typename T, bool EDGE, bool PAIR>
 __device__ __forceinline__ void fine_strip(const FineArgs &args, int sx, int sy, int lane) {
-    FineGeo<T> g;
+    FineGeo g;
     const size_t planeI = static_cast<size_t>(args.W) * args.H * sizeof(T);
     const size_t planeP = static_cast<size_t>(args.wp) * args.hp * sizeof(T);
     const size_t planeO = static_cast<size_t>(args.w) * args.h * sizeof(T);
-    g.A = static_cast<const char *>(args.A);
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        g.I[c] = static_cast<const char *>(args.I) + c * planeI;
-        g.Fp[c] = static_cast<const char *>(args.Fp) + c * planeP;
-        g.Bp[c] = static_cast<const char *>(args.Bp) + c * planeP;
-        g.Fo[c] = static_cast<char *>(args.Fo) + c * planeO;
-        g.Bo[c] = static_cast<char *>(args.Bo) + c * planeO;
-    }
+    g.pI = static_cast<uint32_t>(planeI);
+    g.pP = static_cast<uint32_t>(planeP);
+    g.pO = static_cast<uint32_t>(planeO);
+    g.A = tensor_rsrc(args.A, planeI);
+    g.I = tensor_rsrc(args.I, 3 * planeI);
+    g.P = tensor_rsrc(args.Fp, 6 * planeP);
+    g.Fo = tensor_rsrc(args.Fo, 3 * planeO);
+    g.Bo = tensor_rsrc(args.Bo, 3 * planeO);
     g.W = args.W;
     g.H = args.H;
     g.wp = args.wp;
@@ -552,9 +1046,9 @@ __device__ __forceinline__ void fine_strip(const FineArgs &args, int sx, int sy,
     g.eps = args.eps;
     const int w = args.w, h = args.h, nx = args.nx;
 
-    // Column geometry.  Strip 0 starts at column 0 (its left edge is the image border, so DPP
-    // lane 0 sees itself, which is the clamp); the last strip ends at column w-1 (lane 63 sees
-    // itself); interior strips keep 120 core columns.  EDGE: a single strip narrower than 128.
+    // Column geometry.  Strip 0 starts at column 0 and the last strip ends at column w-1;
+    // interior strips keep 120 core columns.  EDGE strips (the first, the last, or a single
+    // strip) contain an image border and resolve it with per-lane selects.
     int xs, cx0, cx1;
     if (nx == 1) {
         xs = 0;
@@ -583,8 +1077,9 @@ __device__ __forceinline__ void fine_strip(const FineArgs &args, int sx, int sy,
     g.oxb = static_cast<uint32_t>(xb) * sizeof(T);
     g.store_a = xa >= cx0 && xa < cx1;
     g.store_b = xb >= cx0 && xb < cx1;
-    g.edge_a = xa == w - 1;
-    g.edge_b = xb == w - 1;
+    g.left_a = xa == 0;
+    g.right_a = xa == w - 1;
+    g.right_b = xb == w - 1;
 
     // Row geometry.  Core rows [y0, y1).  The pipeline starts kHalo rows above y0 (one more when
     // needed so that (xs + t0) is even, which makes the updated column of the pair a
@@ -601,27 +1096,27 @@ __device__ __forceinline__ void fine_strip(const FineArgs &args, int sx, int sy,
     for (int r = 0; r < kWin; ++r)
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
+            v.ra[r][s] = 0;
             v.al[r][s] = 0.0f;
             v.wl[r][s] = v.wr[r][s] = v.wu[r][s] = v.wd[r][s] = v.ka[r][s] = v.kb[r][s] = 0.0f;
 #pragma unroll
-            for (int c = 0; c < 3; ++c) v.iv[r][s][c] = v.fv[r][s][c] = v.bv[r][s][c] = 0.0f;
+            for (int c = 0; c < 3; ++c) {
+                v.ri[r][s][c] = v.rf[r][s][c] = v.rb[r][s][c] = 0;
+                v.iv[r][s][c] = v.fv[r][s][c] = v.bv[r][s][c] = 0.0f;
+            }
         }
     // Row maps for the clamped rows t0, t0+1, ...: input row and previous-level row.
     RowMap mi, mp;
     const int tc0 = min(max(g.t0, 0), h - 1);
     mi.init(tc0, args.H, h);
     mp.init(tc0, args.hp, h);
-    Raw<T> raw[kPD];
-    fine_load_row(g, raw[0], mi.q, mp.q);
-#pragma unroll
-    for (int k = 1; k < kPD; ++k) {
-        const int tl = g.t0 + k;
-        if (tl >= 1 && tl <= h - 1) {
-            mi.advance();
-            mp.advance();
-        }
-        fine_load_row(g, raw[k], mi.q, mp.q);
+    fine_load_row<0, PAIR, T>(v, g, mi.q, mp.q);
+    static_assert(kPD == 2, "the prologue loads rows t0 and t0 + 1");
+    if (g.t0 + 1 >= 1 && g.t0 + 1 <= h - 1) {
+        mi.advance();
+        mp.advance();
     }
+    fine_load_row<1, PAIR, T>(v, g, mi.q, mp.q);
 
     // Phantom rows -1 and h get their weights at steps 0 and h + 1.  Only the blocks holding
     // those steps use the border variant: the first block of a top strip, and the blocks from
@@ -629,11 +1124,11 @@ __device__ __forceinline__ void fine_strip(const FineArgs &args, int sx, int sy,
     // inside one loop), which keeps the register allocation of the steady state spill-free.
     int t = g.t0;
     if (t <= 0) {
-        fine_block<EDGE, true>(v, raw, g, mi, mp, t);
+        fine_block<EDGE, true, PAIR, T>(v, g, mi, mp, t);
         t += kWin;
     }
-    for (; t <= g.tlast && t + kWin <= h + 1; t += kWin) fine_block<EDGE, false>(v, raw, g, mi, mp, t);
-    for (; t <= g.tlast; t += kWin) fine_block<EDGE, true>(v, raw, g, mi, mp, t);
+    for (; t <= g.tlast && t + kWin <= h + 1; t += kWin) fine_block<EDGE, false, PAIR, T>(v, g, mi, mp, t);
+    for (; t <= g.tlast; t += kWin) fine_block<EDGE, true, PAIR, T>(v, g, mi, mp, t);
 }
 
 template <typename T>
@@ -642,10 +1137,16 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, 2) void fine_kernel(FineArgs a
     if (wave >= args.nx * args.ny) return;
     const int lane = threadIdx.x & 63;
     const int sx = wave % args.nx, sy = wave / args.nx;
-    if (args.w < kStripCols)
-        fine_strip<T, true>(args, sx, sy, lane);
+    // Paired access: identity input map and an exact 2:1 previous level, even width (interior
+    // strips then start on even columns and their core boundaries are even).
+    const bool pair = args.w == args.W && args.h == args.H && 2 * args.wp == args.w &&
+                      (args.w & 1) == 0;
+    if (args.w <= kStripCols || sx == 0 || sx == args.nx - 1)
+        fine_strip<T, true, false>(args, sx, sy, lane);
+    else if (pair)
+        fine_strip<T, false, true>(args, sx, sy, lane);
     else
-        fine_strip<T, false>(args, sx, sy, lane);
+        fine_strip<T, false, false>(args, sx, sy, lane);
 }
 
 template <typename T>
@@ -671,9 +1172,13 @@ int launch_coarse_t(const Plan &plan, const void *I, const void *A, void *Fo, vo
 }
 
 int auto_strip_rows(int w, int h) {
-    // Aim at about one wave per SIMD (256 CUs x 4) and at least 8 core rows per strip.
+    // Large levels: about two waves per SIMD (256 CUs x 4 SIMDs x 2), so one wave's memory
+    // waits overlap the other's arithmetic.  Smaller levels: up to one wave per SIMD with strips
+    // of at most 28 rows, which keeps the halo overhead (8 extra rows per strip) bounded.
     const long nx = fine_strips_x(w);
-    long rows = (static_cast<long>(h) * nx + 1023) / 1024;
+    const long two = (static_cast<long>(h) * nx + 2047) / 2048;
+    const long one = (static_cast<long>(h) * nx + 1023) / 1024;
+    long rows = two > 28 ? two : (one < 28 ? one : 28);
     rows = (rows + 1) & ~1L;
     if (rows < 8) rows = 8;
     if (rows > h) rows = h;
@@ -741,6 +1246,12 @@ int launch_fine_fused(const LevelIO &io, int strip_rows, int storage, void *stre
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (storage == FGE_F16) return launch_fine_t<_Float16>(io, strip_rows, s);
     return launch_fine_t<float>(io, strip_rows, s);
+}
+
+int launch_fine_tile(const LevelIO &io, int storage, void *stream) {
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (storage == FGE_F16) return launch_tile_t<_Float16>(io, s);
+    return launch_tile_t<float>(io, s);
 }
 
 int launch_naive_level(const LevelIO &io, int iters, int storage, void *stream) {

@@ -34,6 +34,7 @@ bool params_valid(const fge_params &p) {
     if (p.kernel < FGE_KERNEL_AUTO || p.kernel > FGE_KERNEL_NAIVE) return false;
     if (p.strip_rows < 0 || p.strip_rows > 1 << 20) return false;
     if (p.coarse_max_px < -1 || p.coarse_max_px > kCoarseMaxPx) return false;
+    if (p.tile_max_px < -1) return false;
     return true;
 }
 
@@ -56,13 +57,27 @@ fge_status make_plan(int W, int H, const fge_params &p, Plan *out) {
     // Coarse block: the longest prefix of levels with w*h <= limit (sizes grow with l).
     const int limit = p.coarse_max_px == 0 ? kCoarseMaxPx : p.coarse_max_px;
     pl.nc = 0;
+    // A coarse level must also have at most kCoarseMaxPairs pairs of columns (thin levels of
+    // odd width can exceed that while still having <= 4096 pixels).
     if (limit > 0)
-        while (pl.nc < pl.n && static_cast<long>(pl.lv[pl.nc].w) * pl.lv[pl.nc].h <= limit) ++pl.nc;
-    // Fine levels: the fused kernel implements exactly two sweeps per level.
+        while (pl.nc < pl.n && static_cast<long>(pl.lv[pl.nc].w) * pl.lv[pl.nc].h <= limit &&
+               static_cast<long>((pl.lv[pl.nc].w + 1) / 2) * pl.lv[pl.nc].h <= kCoarseMaxPairs)
+            ++pl.nc;
+    // Fine levels: the fused kernels (tile and streaming) implement exactly two sweeps per
+    // level and need a previous level; mid-size levels take the tile kernel, large ones the
+    // streaming kernel.
+    const long tile_max = p.tile_max_px == 0 ? kTileMaxPxDefault : p.tile_max_px;
+    for (int i = 0; i < pl.n; ++i) pl.kind[i] = kKindCoarse;
     for (int i = pl.nc; i < pl.n; ++i) {
-        const bool can_fuse = pl.lv[i].iters == 2;
-        pl.fused[i] = p.kernel == FGE_KERNEL_NAIVE ? false : can_fuse;
+        const bool can_fuse = pl.lv[i].iters == 2 && i > 0;
         if (p.kernel == FGE_KERNEL_FUSED && !can_fuse) return FGE_EUNSUPPORTED;
+        if (p.kernel == FGE_KERNEL_NAIVE || !can_fuse)
+            pl.kind[i] = kKindNaive;
+        else if (static_cast<long>(pl.lv[i].w) * pl.lv[i].h <= tile_max ||
+                 3 * static_cast<long long>(W) * H * pl.elem >= (1LL << 32))
+            pl.kind[i] = kKindTile;   // the streaming kernel addresses each tensor in 4 GiB
+        else
+            pl.kind[i] = kKindStream;
     }
     // Workspace: the state of every level except the last goes through a ping-pong buffer.
     // Only levels from nc-1 on are materialised (coarser ones live in LDS).

@@ -43,6 +43,7 @@ class Params(ctypes.Structure):
         ("kernel", ctypes.c_int32),
         ("strip_rows", ctypes.c_int32),
         ("coarse_max_px", ctypes.c_int32),
+        ("tile_max_px", ctypes.c_int32),
     ]
 
 

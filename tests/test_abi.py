@@ -40,11 +40,11 @@ def test_header_symbols_exported(fge):
 
 def test_params_layout_and_defaults(fge):
     p = fge.default_params()
-    assert p.size == ctypes.sizeof(fge.Params) == 44
+    assert p.size == ctypes.sizeof(fge.Params) == 48
     assert abs(p.omega - 0.1) < 1e-7 and abs(p.eps_r - 5e-3) < 1e-9
     assert (p.small_size, p.iters_small, p.iters_big) == (32, 10, 2)
-    assert (p.storage, p.order, p.kernel, p.strip_rows, p.coarse_max_px) == (0, 0, 0, 0, 0)
-    assert fge.load().fge_version() == 1
+    assert (p.storage, p.order, p.kernel, p.strip_rows, p.coarse_max_px, p.tile_max_px) == (0,) * 6
+    assert fge.load().fge_version() == 2
 
 
 def test_plan_matches_golden(fge):
@@ -116,7 +116,7 @@ def test_argument_errors_before_launch(fge):
     assert _call(fge, 64, 64, p, F=0x5000, B=0x5000) == fge.FGE_EINVAL
     for field, bad in (("size", 12), ("storage", 7), ("order", 3), ("kernel", 9),
                        ("eps_r", 0.0), ("omega", -1.0), ("iters_big", -2), ("strip_rows", -1),
-                       ("coarse_max_px", 5000)):
+                       ("coarse_max_px", 5000), ("tile_max_px", -2)):
         q = fge.default_params()
         setattr(q, field, bad)
         assert _call(fge, 64, 64, q) == fge.FGE_EINVAL, field

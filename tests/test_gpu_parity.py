@@ -112,14 +112,42 @@ def test_strands_sizes_f16(gpu, wh):
 
 
 def test_strip_rows_do_not_change_results(gpu):
-    """Every stored pixel goes through the same arithmetic whatever the strip height, so the
-    output is bit-identical across strip heights (only halo work differs)."""
+    """Streaming kernel on every fine level: every stored pixel goes through the same arithmetic
+    whatever the strip height, so the output is bit-identical across strip heights (only halo
+    work differs), and it matches the oracle."""
     torch, fge = gpu
     s = sample_of("c2")
-    ref = run(gpu, s.I, s.alpha, strip_rows=0)
+    Fo, Bo = oracle_of("c2")
+    ref = run(gpu, s.I, s.alpha, strip_rows=0, tile_max_px=-1)
+    assert max(maxabs(ref[0], Fo), maxabs(ref[1], Bo)) <= TOL["f32"]
     for rows in (1, 2, 3, 8, 13, 64, 400, 768):
-        F, B = run(gpu, s.I, s.alpha, strip_rows=rows)
+        F, B = run(gpu, s.I, s.alpha, strip_rows=rows, tile_max_px=-1)
         assert np.array_equal(F, ref[0]) and np.array_equal(B, ref[1]), rows
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_fine_kernel_choices_match_oracle(gpu, storage):
+    """Tile kernel on every fine level, streaming kernel on every fine level, and the default
+    split, each against the oracle."""
+    torch, fge = gpu
+    st = fge.F16 if storage == "f16" else fge.F32
+    s = sample_of("c2")
+    Fo, Bo = oracle_of("c2")
+    for kw in ({"tile_max_px": 1 << 30}, {"tile_max_px": -1}, {"tile_max_px": 0},
+               {"tile_max_px": 100000}):
+        F, B = run(gpu, s.I, s.alpha, storage=st, **kw)
+        assert max(maxabs(F, Fo), maxabs(B, Bo)) <= TOL[storage], kw
+
+
+@pytest.mark.parametrize("wh", [(33, 35), (65, 64), (100, 37), (129, 130), (300, 7), (7, 300),
+                                (511, 259), (1001, 257)])
+def test_tile_kernel_ragged(gpu, wh):
+    W, H = wh
+    s = synth.strands(W, H, seed=300 + W, n_strands=max(1, W * H // 3000))
+    Fo, Bo = oracle.ml(s.I, s.alpha)
+    for kw in ({"tile_max_px": 1 << 30}, {"tile_max_px": -1}):
+        F, B = run(gpu, s.I, s.alpha, **kw)
+        assert max(maxabs(F, Fo), maxabs(B, Bo)) <= TOL["f32"], (wh, kw)
 
 
 def test_naive_path_matches_oracle(gpu):
