@@ -80,7 +80,7 @@ typedef struct fge_params {
     int32_t coarse_max_px;  /* levels with w*h <= this (and all smaller ones) run in the
                                LDS-resident coarse kernel; 0 = automatic (4096), -1 = never */
     int32_t tile_max_px;    /* fine levels with w*h <= this use the LDS tile kernel, larger ones
-                               the streaming kernel; 0 = automatic (2^20), -1 = never */
+                               the streaming kernel; 0 = automatic (2^18), -1 = never */
 } fge_params;
 
 /* Fill *p with the paper's defaults: omega 0.1, eps_r 5e-3, 32 / 10 / 2, float32 storage,
@@ -129,7 +129,8 @@ fge_status fge_estimate_foreground(const void *I, const void *alpha, int32_t W, 
 
 /* Start recording HIP events around every kernel launch of the following estimation calls
  * (on the caller's stream).  Level 0 is the finest level, 1 the next coarser, ...; the coarse
- * kernel is recorded under the index of the last level it runs.  `capacity` bounds the number
+ * kernel is recorded under the index of the last level it runs, and the gather pre-pass (the
+ * compact copy of the small levels' inputs) under index n_levels.  `capacity` bounds the number
  * of recorded launches (events are created here, not in the estimation calls). */
 fge_status fge_profile_start(int32_t capacity);
 

@@ -154,19 +154,38 @@ fge_status fge_estimate_foreground(const void *I, const void *alpha, int32_t W, 
         *b = base + 3 * static_cast<size_t>(plan.lv[i].w) * plan.lv[i].h * plan.elem;
     };
 
+    // I and alpha of level i: its compact copy from the gather pre-pass, or full resolution.
+    auto source = [&](int i, const void **Ii, const void **Ai, int *Wi, int *Hi) {
+        if (i < plan.ng) {
+            const char *base = ws + plan.pyr_off + plan.pyr_lv[i];
+            const size_t plane = static_cast<size_t>(plan.lv[i].w) * plan.lv[i].h * plan.elem;
+            *Ii = base;
+            *Ai = base + 3 * plane;
+            *Wi = plan.lv[i].w;
+            *Hi = plan.lv[i].h;
+        } else {
+            *Ii = I;
+            *Ai = alpha;
+            *Wi = W;
+            *Hi = H;
+        }
+    };
+    if (plan.ng > 0) {
+        LaunchTimer timer(n, s);   // recorded under index n_levels
+        if (fge::launch_gather(plan, I, alpha, ws + plan.pyr_off, prm.storage, s)) return FGE_EHIP;
+    }
     if (plan.nc > 0) {
         void *fo, *bo;
         state(plan.nc - 1, &fo, &bo);
+        fge::LevelSrc src{};
+        for (int i = 0; i < plan.nc; ++i) source(i, &src.I[i], &src.A[i], &src.W[i], &src.H[i]);
         LaunchTimer timer(n - plan.nc, s);
-        if (fge::launch_coarse(plan, I, alpha, fo, bo, prm.omega, prm.eps_r, prm.storage, s))
+        if (fge::launch_coarse(plan, src, fo, bo, prm.omega, prm.eps_r, prm.storage, s))
             return FGE_EHIP;
     }
     for (int i = plan.nc; i < n; ++i) {
         fge::LevelIO io{};
-        io.I = I;
-        io.A = alpha;
-        io.W = W;
-        io.H = H;
+        source(i, &io.I, &io.A, &io.W, &io.H);
         if (i > 0) {
             void *fp, *bp;
             state(i - 1, &fp, &bp);

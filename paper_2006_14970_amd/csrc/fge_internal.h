@@ -16,7 +16,8 @@ constexpr int kCoarsePairsPerThread = 4;   // a coarse level has at most 2048 pi
 constexpr int kCoarseMaxPairs = kCoarseThreads * kCoarsePairsPerThread;
 
 enum LevelKind { kKindCoarse = 0, kKindStream = 1, kKindTile = 2, kKindNaive = 3 };
-constexpr long kTileMaxPxDefault = 1L << 20;   // fine levels up to ~1 MP use the tile kernel
+constexpr long kTileMaxPxDefault = 1L << 18;   // fine levels up to 256K px use the tile kernel
+constexpr long kGatherMaxPx = 1L << 16;        // coarse/tile levels up to 64K px read a compact copy
 
 struct Level {
     int w, h, iters;
@@ -36,6 +37,11 @@ struct Plan {
     size_t buf_px[2] = {0, 0};
     size_t ws_bytes = 0;
     int kind[kMaxLevels] = {};     // per fine level: a LevelKind
+    // Gather pre-pass: levels [0, ng) get a compact copy of their resized I (3 planes) and alpha
+    // (1 plane) at pyr_off + pyr_lv[i] bytes of the workspace.
+    int ng = 0;
+    size_t pyr_off = 0;
+    size_t pyr_lv[kMaxLevels] = {};
 };
 
 int num_levels(int W, int H);
@@ -45,8 +51,8 @@ fge_status make_plan(int W, int H, const fge_params &p, Plan *out);
 
 // Kernel launchers (fge_kernels.hip).  All enqueue on `stream` and return a HIP error code.
 struct LevelIO {
-    const void *I;      // full-resolution input, 3 planes of W*H
-    const void *A;      // full-resolution alpha, W*H
+    const void *I;      // input image, 3 planes of W*H (full resolution or a compact level copy)
+    const void *A;      // alpha, W*H
     int W, H;
     const void *Fp;     // previous level F (3 planes wp*hp), nullptr: the 1x1 zero start
     const void *Bp;     // previous level B; always Fp + 3 planes (one workspace buffer)
@@ -57,8 +63,17 @@ struct LevelIO {
     float omega, eps;
 };
 
-int launch_coarse(const Plan &plan, const void *I, const void *A, void *Fo, void *Bo,
-                  float omega, float eps, int storage, void *stream);
+// Per-level source of I and alpha for the coarse kernel: the compact copy or full resolution.
+struct LevelSrc {
+    const void *I[kMaxLevels];
+    const void *A[kMaxLevels];
+    int W[kMaxLevels], H[kMaxLevels];
+};
+
+int launch_gather(const Plan &plan, const void *I, const void *A, void *pyr, int storage,
+                  void *stream);
+int launch_coarse(const Plan &plan, const LevelSrc &src, void *Fo, void *Bo, float omega,
+                  float eps, int storage, void *stream);
 int launch_fine_fused(const LevelIO &io, int strip_rows, int storage, void *stream);
 int launch_fine_tile(const LevelIO &io, int storage, void *stream);
 int launch_naive_level(const LevelIO &io, int iters, int storage, void *stream);

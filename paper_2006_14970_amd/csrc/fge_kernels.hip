@@ -81,9 +81,7 @@ __device__ __forceinline__ float weight(float a, float b, float omega, float eps
 // ------------------------------------------------------------------------------------------
 
 struct CoarseArgs {
-    const void *I;
-    const void *A;
-    int W, H;
+    LevelSrc src;       // per level: I, alpha and their size (compact copy or full resolution)
     void *Fo;
     void *Bo;
     int nc;
@@ -99,20 +97,21 @@ struct CoarsePair {
 };
 
 template <typename T>
-__device__ __forceinline__ void coarse_gather_inputs(const CoarseArgs &args, int w, int h,
+__device__ __forceinline__ void coarse_gather_inputs(const CoarseArgs &args, int l, int w, int h,
                                                      const CoarsePair (&pr)[kCoarsePairsPerThread],
                                                      float (&ni)[kCoarsePairsPerThread][2][3],
                                                      float (&na)[kCoarsePairsPerThread][2]) {
-    const T *I = static_cast<const T *>(args.I);
-    const T *A = static_cast<const T *>(args.A);
-    const size_t planeI = static_cast<size_t>(args.W) * args.H;
+    const T *I = static_cast<const T *>(args.src.I[l]);
+    const T *A = static_cast<const T *>(args.src.A[l]);
+    const int W = args.src.W[l], H = args.src.H[l];
+    const size_t planeI = static_cast<size_t>(W) * H;
 #pragma unroll
     for (int k = 0; k < kCoarsePairsPerThread; ++k) {
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
             const bool ok = s == 0 ? pr[k].valid0 : pr[k].valid1;
             const int x = ok ? pr[k].x0 + s : 0, y = ok ? pr[k].y : 0;
-            const size_t src = static_cast<size_t>(y * args.H / h) * args.W + x * args.W / w;
+            const size_t src = static_cast<size_t>(y * H / h) * W + x * W / w;
             na[k][s] = ldf(A + src);
 #pragma unroll
             for (int c = 0; c < 3; ++c) ni[k][s][c] = ldf(I + c * planeI + src);
@@ -149,7 +148,7 @@ __global__ __launch_bounds__(kCoarseThreads) void coarse_kernel(CoarseArgs args)
     float iv[kCoarsePairsPerThread][2][3], av[kCoarsePairsPerThread][2];
     float ni[kCoarsePairsPerThread][2][3], na[kCoarsePairsPerThread][2];
     coarse_pairs(tid, args.lw[0], args.lh[0], pr);
-    coarse_gather_inputs<T>(args, args.lw[0], args.lh[0], pr, ni, na);
+    coarse_gather_inputs<T>(args, 0, args.lw[0], args.lh[0], pr, ni, na);
 
     int wp = 1, hp = 1;
     for (int l = 0; l < args.nc; ++l) {
@@ -195,7 +194,7 @@ __global__ __launch_bounds__(kCoarseThreads) void coarse_kernel(CoarseArgs args)
         CoarsePair nx[kCoarsePairsPerThread];
         if (l + 1 < args.nc) {
             coarse_pairs(tid, args.lw[l + 1], args.lh[l + 1], nx);
-            coarse_gather_inputs<T>(args, args.lw[l + 1], args.lh[l + 1], nx, ni, na);
+            coarse_gather_inputs<T>(args, l + 1, args.lw[l + 1], args.lh[l + 1], nx, ni, na);
         }
         lds_sync();
 
@@ -252,16 +251,17 @@ __global__ __launch_bounds__(kCoarseThreads) void coarse_kernel(CoarseArgs args)
         }
 
         // Sweeps: in half-sweep c every pair updates its pixel of colour c.  Pair slots that no
-        // thread of the level uses are skipped as a whole (a uniform test); inside a slot the
+        // lane of the wave uses are skipped as a whole (a uniform test); inside a slot the
         // reads and the arithmetic are unconditional (indices are clamped), only the store is
         // guarded, so the slot's LDS reads are all in flight together.
         const int npairs = ((w + 1) >> 1) * h;
+        const int wave_q0 = uniform(tid & ~63);   // first pair index of this wave in slot 0
         for (int it = 0; it < iters; ++it) {
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
 #pragma unroll
                 for (int k = 0; k < kCoarsePairsPerThread; ++k) {
-                    if (k * kCoarseThreads < npairs) {
+                    if (k * kCoarseThreads + wave_q0 < npairs) {   // uniform: this wave has work
                         float fb[3] = {0.f, 0.f, 0.f}, bb[3] = {0.f, 0.f, 0.f};
 #pragma unroll
                         for (int j = 0; j < 4; ++j) {
@@ -1149,14 +1149,66 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, 2) void fine_kernel(FineArgs a
         fine_strip<T, false, false>(args, sx, sy, lane);
 }
 
+// Gather pre-pass: thread p writes pixel p of the concatenated small levels: I (3 planes) and
+// alpha resized from full resolution by the nearest map, into each level's compact planes.
+struct GatherArgs {
+    const void *I;
+    const void *A;
+    int W, H;
+    char *pyr;
+    int ng;
+    int lw[kMaxLevels], lh[kMaxLevels];
+    long long first[kMaxLevels + 1];   // first concatenated pixel of each level
+    long long off[kMaxLevels];         // byte offset of each level's planes in pyr
+};
+
 template <typename T>
-int launch_coarse_t(const Plan &plan, const void *I, const void *A, void *Fo, void *Bo,
-                    float omega, float eps, hipStream_t s) {
-    CoarseArgs a{};
+__global__ __launch_bounds__(256) void gather_kernel(GatherArgs args) {
+    const long long p = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (p >= args.first[args.ng]) return;
+    int l = 0;
+    while (l + 1 < args.ng && p >= args.first[l + 1]) ++l;
+    const int w = args.lw[l], h = args.lh[l];
+    const int q = static_cast<int>(p - args.first[l]);
+    const int y = q / w, x = q - y * w;
+    const size_t planeI = static_cast<size_t>(args.W) * args.H;
+    const size_t src = static_cast<size_t>(y * args.H / h) * args.W + x * args.W / w;
+    const T *I = static_cast<const T *>(args.I);
+    T *dst = reinterpret_cast<T *>(args.pyr + args.off[l]);
+    const size_t n = static_cast<size_t>(w) * h;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) dst[c * n + q] = I[c * planeI + src];
+    dst[3 * n + q] = static_cast<const T *>(args.A)[src];
+}
+
+template <typename T>
+int launch_gather_t(const Plan &plan, const void *I, const void *A, void *pyr, hipStream_t s) {
+    GatherArgs a{};
     a.I = I;
     a.A = A;
     a.W = plan.W;
     a.H = plan.H;
+    a.pyr = static_cast<char *>(pyr);
+    a.ng = plan.ng;
+    long long total = 0;
+    for (int i = 0; i < plan.ng; ++i) {
+        a.lw[i] = plan.lv[i].w;
+        a.lh[i] = plan.lv[i].h;
+        a.first[i] = total;
+        a.off[i] = static_cast<long long>(plan.pyr_lv[i]);
+        total += static_cast<long long>(plan.lv[i].w) * plan.lv[i].h;
+    }
+    a.first[plan.ng] = total;
+    const int blocks = static_cast<int>((total + 255) / 256);
+    hipLaunchKernelGGL(gather_kernel<T>, dim3(blocks), dim3(256), 0, s, a);
+    return static_cast<int>(hipGetLastError());
+}
+
+template <typename T>
+int launch_coarse_t(const Plan &plan, const LevelSrc &src, void *Fo, void *Bo, float omega,
+                    float eps, hipStream_t s) {
+    CoarseArgs a{};
+    a.src = src;
     a.Fo = Fo;
     a.Bo = Bo;
     a.nc = plan.nc;
@@ -1235,11 +1287,18 @@ int launch_naive_t(const LevelIO &io, int iters, hipStream_t s) {
 
 }  // namespace
 
-int launch_coarse(const Plan &plan, const void *I, const void *A, void *Fo, void *Bo,
-                  float omega, float eps, int storage, void *stream) {
+int launch_gather(const Plan &plan, const void *I, const void *A, void *pyr, int storage,
+                  void *stream) {
     hipStream_t s = static_cast<hipStream_t>(stream);
-    if (storage == FGE_F16) return launch_coarse_t<_Float16>(plan, I, A, Fo, Bo, omega, eps, s);
-    return launch_coarse_t<float>(plan, I, A, Fo, Bo, omega, eps, s);
+    if (storage == FGE_F16) return launch_gather_t<_Float16>(plan, I, A, pyr, s);
+    return launch_gather_t<float>(plan, I, A, pyr, s);
+}
+
+int launch_coarse(const Plan &plan, const LevelSrc &src, void *Fo, void *Bo, float omega,
+                  float eps, int storage, void *stream) {
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (storage == FGE_F16) return launch_coarse_t<_Float16>(plan, src, Fo, Bo, omega, eps, s);
+    return launch_coarse_t<float>(plan, src, Fo, Bo, omega, eps, s);
 }
 
 int launch_fine_fused(const LevelIO &io, int strip_rows, int storage, void *stream) {

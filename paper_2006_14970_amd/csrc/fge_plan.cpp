@@ -91,6 +91,22 @@ fge_status make_plan(int W, int H, const fge_params &p, Plan *out) {
     pl.buf_off[1] = align256(6 * pl.buf_px[0] * pl.elem);
     pl.ws_bytes = pl.buf_px[1] ? pl.buf_off[1] + align256(6 * pl.buf_px[1] * pl.elem)
                                : (pl.buf_px[0] ? pl.buf_off[1] : 0);
+    // Gather pre-pass for the small coarse and tile levels, whose nearest-neighbour reads from
+    // full resolution touch one cache line per pixel: one GPU-wide kernel copies them into
+    // compact per-level planes first.  Not when the full image is itself that small.
+    pl.ng = 0;
+    if (static_cast<long>(W) * H > kGatherMaxPx)
+        while (pl.ng < pl.n &&
+               (pl.kind[pl.ng] == kKindCoarse || pl.kind[pl.ng] == kKindTile) &&
+               static_cast<long>(pl.lv[pl.ng].w) * pl.lv[pl.ng].h <= kGatherMaxPx)
+            ++pl.ng;
+    pl.pyr_off = pl.ws_bytes;
+    size_t pyr = 0;
+    for (int i = 0; i < pl.ng; ++i) {
+        pl.pyr_lv[i] = pyr;
+        pyr += align256(4 * static_cast<size_t>(pl.lv[i].w) * pl.lv[i].h * pl.elem);
+    }
+    pl.ws_bytes += pyr;
     *out = pl;
     return FGE_OK;
 }
