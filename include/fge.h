@@ -125,6 +125,55 @@ fge_status fge_estimate_foreground(const void *I, const void *alpha, int32_t W, 
                                    const fge_params *p, void *F, void *B, void *workspace,
                                    size_t workspace_bytes, void *stream);
 
+/* ---- batches of images of different sizes ---------------------------------------------- */
+
+/* A batch plan: every image follows its own level plan (so its F and B are bit-identical to
+ * fge_estimate_foreground's), and the levels of all images are aligned from the finest.  A run
+ * is: one upload of descriptor tables into the workspace, a counter fill kernel, one batched
+ * gather pre-pass, one batched coarse block (a workgroup per image), then per fine step one
+ * persistent tile-kernel launch and one persistent streaming-kernel launch whose waves pull
+ * (level, tile|strip) items from a per-step work queue.  Requires the coarse block (coarse_max_px
+ * != -1) and fused fine levels (iters_big == 2, kernel != FGE_KERNEL_NAIVE). */
+typedef struct fge_batch fge_batch;
+
+/* Plan a batch of n images, image i of size W[i] x H[i], all under *p (NULL = defaults).
+ * Host-only; *out receives the plan.  FGE_EINVAL / FGE_EUNSUPPORTED on bad input. */
+fge_status fge_batch_create(int32_t n, const int32_t *W, const int32_t *H, const fge_params *p,
+                            fge_batch **out);
+
+/* Release the plan (waits for its last descriptor upload; a captured graph must not be running). */
+void fge_batch_destroy(fge_batch *b);
+
+/* Workspace bytes a run of this plan needs (state buffers, compact copies, tables, counters). */
+size_t fge_batch_workspace_bytes(const fge_batch *b);
+
+/* Number of aligned fine steps, and of kernel launches (plus one copy) per run. */
+int32_t fge_batch_steps(const fge_batch *b);
+int32_t fge_batch_launch_count(const fge_batch *b);
+
+/* Run the batch: I[i], alpha[i], F[i], B[i] are image i's device buffers (layout and type as in
+ * fge_estimate_foreground).  Asynchronous on `stream`; the descriptor tables are uploaded from a
+ * pinned staging buffer owned by the plan, and a second run first waits for the previous run's
+ * upload (not its kernels).  The plan must not be used by two threads at once. */
+fge_status fge_batch_run(fge_batch *b, const void *const *I, const void *const *alpha,
+                         void *const *F, void *const *B, void *workspace, size_t workspace_bytes,
+                         void *stream);
+
+/* Capture one run with these pointers into a hipGraph owned by the plan (stream must not be
+ * NULL); fge_batch_replay launches it again on any stream.  Nothing is executed by the capture. */
+fge_status fge_batch_capture(fge_batch *b, const void *const *I, const void *const *alpha,
+                             void *const *F, void *const *B, void *workspace,
+                             size_t workspace_bytes, void *stream);
+fge_status fge_batch_replay(fge_batch *b, void *stream);
+
+/* One-shot forms: workspace size for, and a run of, a batch planned on the fly. */
+size_t fge_batch_workspace_bytes_for(int32_t n, const int32_t *W, const int32_t *H,
+                                     const fge_params *p);
+fge_status fge_estimate_foreground_batch(int32_t n, const void *const *I, const void *const *alpha,
+                                         const int32_t *W, const int32_t *H, const fge_params *p,
+                                         void *const *F, void *const *B, void *workspace,
+                                         size_t workspace_bytes, void *stream);
+
 /* ---- profiling ------------------------------------------------------------------------- */
 
 /* Start recording HIP events around every kernel launch of the following estimation calls

@@ -78,4 +78,85 @@ int launch_fine_fused(const LevelIO &io, int strip_rows, int storage, void *stre
 int launch_fine_tile(const LevelIO &io, int storage, void *stream);
 int launch_naive_level(const LevelIO &io, int iters, int storage, void *stream);
 
+
+// ---- kernel argument records (shared by host and device code) ---------------------------
+
+// Coarse block of one image: levels [0, nc) in one workgroup.
+struct CoarseArgs {
+    LevelSrc src;       // per level: I, alpha and their size (compact copy or full resolution)
+    void *Fo;
+    void *Bo;
+    int nc;
+    int lw[kMaxLevels], lh[kMaxLevels], lit[kMaxLevels];
+    float omega, eps;
+};
+
+// One fine level on the LDS tile kernel: 32x32 output tiles, tiles_x per row.
+struct TileArgs {
+    const void *I;
+    const void *A;
+    int W, H;
+    const void *Fp;
+    const void *Bp;
+    int wp, hp;
+    void *Fo;
+    void *Bo;
+    int w, h;
+    int tiles_x;
+    float omega, eps;
+};
+
+// One fine level on the streaming kernel: nx x ny strips of strip_rows rows.
+struct FineArgs {
+    const void *I;
+    const void *A;
+    int W, H;
+    const void *Fp;
+    const void *Bp;
+    int wp, hp;
+    void *Fo;
+    void *Bo;
+    int w, h;
+    float omega, eps;
+    int nx, ny, strip_rows;
+};
+
+// Gather pre-pass of one image: compact copies of levels [0, ng).
+struct GatherArgs {
+    const void *I;
+    const void *A;
+    int W, H;
+    char *pyr;
+    int ng;
+    int lw[kMaxLevels], lh[kMaxLevels];
+    long long first[kMaxLevels + 1];   // first concatenated pixel of each level
+    long long off[kMaxLevels];         // byte offset of each level's planes in pyr
+};
+
+// One unit of work of a batched launch: a strip or tile of descriptor `desc`.
+struct WorkItem {
+    int desc;   // index into the launch's descriptor table
+    int unit;   // strip (streaming) or tile index
+};
+
+// Descriptor builders (host side; geometry as the single-image launches use it).
+void make_fine_args(const LevelIO &io, int strip_rows, FineArgs *a);
+void make_tile_args(const LevelIO &io, TileArgs *a);
+int fine_units(const FineArgs &a);
+int tile_units(const TileArgs &a);
+void make_coarse_args(const Plan &plan, const LevelSrc &src, void *Fo, void *Bo, float omega,
+                      float eps, CoarseArgs *a);
+void make_gather_args(const Plan &plan, const void *I, const void *A, void *pyr, GatherArgs *a);
+long long gather_units(const GatherArgs &a);
+
+// Batched launches: descriptor tables, work lists and counters are device pointers.
+int launch_zero(int *d, int n, void *stream);
+int launch_gather_batch(const GatherArgs *descs, const long long *first, int n, long long total,
+                        int storage, void *stream);
+int launch_coarse_batch(const CoarseArgs *descs, int n, int storage, void *stream);
+int launch_fine_batch(const FineArgs *descs, const WorkItem *items, int nitems, int *counter,
+                      int storage, void *stream);
+int launch_tile_batch(const TileArgs *descs, const WorkItem *items, int nitems, int *counter,
+                      int storage, void *stream);
+
 }  // namespace fge

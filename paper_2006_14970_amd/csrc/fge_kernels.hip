@@ -80,14 +80,6 @@ __device__ __forceinline__ float weight(float a, float b, float omega, float eps
 // Coarse kernel: levels [0, nc) in LDS.
 // ------------------------------------------------------------------------------------------
 
-struct CoarseArgs {
-    LevelSrc src;       // per level: I, alpha and their size (compact copy or full resolution)
-    void *Fo;
-    void *Bo;
-    int nc;
-    int lw[kMaxLevels], lh[kMaxLevels], lit[kMaxLevels];
-    float omega, eps;
-};
 
 // Pixel pairs (2j, 2j+1) of row y owned by one thread: thread t owns pairs t and t + 1024.
 struct CoarsePair {
@@ -135,11 +127,16 @@ __device__ __forceinline__ void coarse_pairs(int tid, int w, int h,
     }
 }
 
+// Per pixel two float4 records: (F0, F1, F2, alpha) and (B0, B1, B2, unused).
+struct CoarseLds {
+    float4 FA[kCoarseMaxPx];
+    float4 B[kCoarseMaxPx];
+};
+
 template <typename T>
-__global__ __launch_bounds__(kCoarseThreads) void coarse_kernel(CoarseArgs args) {
-    // Per pixel two float4 records: (F0, F1, F2, alpha) and (B0, B1, B2, unused).
-    __shared__ float4 sFA[kCoarseMaxPx];
-    __shared__ float4 sB[kCoarseMaxPx];
+__device__ __forceinline__ void coarse_body(const CoarseArgs &args, CoarseLds &lds) {
+    float4 *sFA = lds.FA;
+    float4 *sB = lds.B;
 
     const int tid = threadIdx.x;
     const float omega = args.omega, eps = args.eps;
@@ -315,6 +312,19 @@ __global__ __launch_bounds__(kCoarseThreads) void coarse_kernel(CoarseArgs args)
     }
 }
 
+template <typename T>
+__global__ __launch_bounds__(kCoarseThreads) void coarse_kernel(CoarseArgs args) {
+    __shared__ CoarseLds lds;
+    coarse_body<T>(args, lds);
+}
+
+// Batch: workgroup b runs the coarse block of image b.
+template <typename T>
+__global__ __launch_bounds__(kCoarseThreads) void coarse_batch_kernel(const CoarseArgs *descs) {
+    __shared__ CoarseLds lds;
+    coarse_body<T>(descs[blockIdx.x], lds);
+}
+
 // ------------------------------------------------------------------------------------------
 // Tile kernel: one fine level, one workgroup per 32x32 output tile, state in LDS.
 // ------------------------------------------------------------------------------------------
@@ -334,24 +344,16 @@ constexpr int kTileThreads = 512;
 constexpr int kTilePairs = (kTileSide / 2) * kTileSide;
 constexpr int kTilePairsPerThread = (kTilePairs + kTileThreads - 1) / kTileThreads;
 
-struct TileArgs {
-    const void *I;
-    const void *A;
-    int W, H;
-    const void *Fp;
-    const void *Bp;
-    int wp, hp;
-    void *Fo;
-    void *Bo;
-    int w, h;
-    int tiles_x;
-    float omega, eps;
+
+struct TileLds {
+    float4 FA[kTilePx];   // (F0, F1, F2, alpha)
+    float4 B[kTilePx];    // (B0, B1, B2, unused)
 };
 
 template <typename T>
-__global__ __launch_bounds__(kTileThreads) void tile_kernel(TileArgs args) {
-    __shared__ float4 sFA[kTilePx];   // (F0, F1, F2, alpha)
-    __shared__ float4 sB[kTilePx];    // (B0, B1, B2, unused)
+__device__ __forceinline__ void tile_body(const TileArgs &args, int tile, TileLds &lds) {
+    float4 *sFA = lds.FA;
+    float4 *sB = lds.B;
 
     const T *I = static_cast<const T *>(args.I);
     const T *A = static_cast<const T *>(args.A);
@@ -363,7 +365,7 @@ __global__ __launch_bounds__(kTileThreads) void tile_kernel(TileArgs args) {
     const float omega = args.omega, eps = args.eps;
     const int tid = threadIdx.x;
 
-    const int tx = blockIdx.x % args.tiles_x, ty = blockIdx.x / args.tiles_x;
+    const int tx = tile % args.tiles_x, ty = tile / args.tiles_x;
     const int cx0 = tx * kTileCore, cy0 = ty * kTileCore;
     const int cx1 = min(w, cx0 + kTileCore), cy1 = min(h, cy0 + kTileCore);
     const int rx0 = max(0, cx0 - kTileHalo), ry0 = max(0, cy0 - kTileHalo);
@@ -522,27 +524,11 @@ __global__ __launch_bounds__(kTileThreads) void tile_kernel(TileArgs args) {
 }
 
 template <typename T>
-int launch_tile_t(const LevelIO &io, hipStream_t s) {
-    TileArgs a{};
-    a.I = io.I;
-    a.A = io.A;
-    a.W = io.W;
-    a.H = io.H;
-    a.Fp = io.Fp;
-    a.Bp = io.Bp;
-    a.wp = io.wp;
-    a.hp = io.hp;
-    a.Fo = io.Fo;
-    a.Bo = io.Bo;
-    a.w = io.w;
-    a.h = io.h;
-    a.omega = io.omega;
-    a.eps = io.eps;
-    a.tiles_x = (io.w + kTileCore - 1) / kTileCore;
-    const int tiles = a.tiles_x * ((io.h + kTileCore - 1) / kTileCore);
-    hipLaunchKernelGGL(tile_kernel<T>, dim3(tiles), dim3(kTileThreads), 0, s, a);
-    return static_cast<int>(hipGetLastError());
+__global__ __launch_bounds__(kTileThreads) void tile_kernel(TileArgs args) {
+    __shared__ TileLds lds;
+    tile_body<T>(args, blockIdx.x, lds);
 }
+
 
 // ------------------------------------------------------------------------------------------
 // Naive path: upsample, then one launch per half-sweep.
@@ -619,19 +605,6 @@ constexpr int kMidCore = kStripCols - 2 * kHalo;        // interior strips keep 
 constexpr int kWavesPerBlock = 4;
 constexpr int kRsrcWord3 = 0x00020000;  // raw buffer resource, gfx9 family
 
-struct FineArgs {
-    const void *I;
-    const void *A;
-    int W, H;
-    const void *Fp;
-    const void *Bp;
-    int wp, hp;
-    void *Fo;
-    void *Bo;
-    int w, h;
-    float omega, eps;
-    int nx, ny, strip_rows;
-};
 
 // Number of column strips for a level of width w (see the geometry in fine_strip).
 __host__ __device__ inline int fine_strips_x(int w) {
@@ -1132,10 +1105,7 @@ __device__ __forceinline__ void fine_strip(const FineArgs &args, int sx, int sy,
 }
 
 template <typename T>
-__global__ __launch_bounds__(64 * kWavesPerBlock, 2) void fine_kernel(FineArgs args) {
-    const int wave = uniform(blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6));
-    if (wave >= args.nx * args.ny) return;
-    const int lane = threadIdx.x & 63;
+__device__ __forceinline__ void fine_body(const FineArgs &args, int wave, int lane) {
     const int sx = wave % args.nx, sy = wave / args.nx;
     // Paired access: identity input map and an exact 2:1 previous level, even width (interior
     // strips then start on even columns and their core boundaries are even).
@@ -1149,23 +1119,72 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, 2) void fine_kernel(FineArgs a
         fine_strip<T, false, false>(args, sx, sy, lane);
 }
 
-// Gather pre-pass: thread p writes pixel p of the concatenated small levels: I (3 planes) and
-// alpha resized from full resolution by the nearest map, into each level's compact planes.
-struct GatherArgs {
-    const void *I;
-    const void *A;
-    int W, H;
-    char *pyr;
-    int ng;
-    int lw[kMaxLevels], lh[kMaxLevels];
-    long long first[kMaxLevels + 1];   // first concatenated pixel of each level
-    long long off[kMaxLevels];         // byte offset of each level's planes in pyr
-};
+template <typename T>
+__global__ __launch_bounds__(64 * kWavesPerBlock, 2) void fine_kernel(FineArgs args) {
+    const int wave = uniform(blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6));
+    if (wave >= args.nx * args.ny) return;
+    fine_body<T>(args, wave, threadIdx.x & 63);
+}
+
+// ------------------------------------------------------------------------------------------
+// Batched, persistent kernels: many images' levels in one launch.
+// ------------------------------------------------------------------------------------------
+//
+// A launch gets a descriptor table (one FineArgs / TileArgs per image level) and a work list of
+// (descriptor, unit) items, unit = strip (streaming kernel) or tile (tile kernel).  Waves (or
+// workgroups) of a grid sized to the machine pull items from an atomic counter in the workspace
+// until the list is exhausted: the per-level work queue.  Every item is processed by the same
+// body as the single-image kernels, so a batched image's result is bit-identical to its
+// single-image result.  The counters are zeroed by zero_kernel (not a memset), so the schedule
+// can be captured in a hipGraph and replayed.
+
+
+__global__ void zero_kernel(int *p, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
+// One item per wave.  The counter is bumped by lane 0 with a vector atomic and broadcast.
+__device__ __forceinline__ int next_item_wave(int *counter, int lane) {
+    int v = 0;
+    if (lane == 0) v = atomicAdd(counter, 1);
+    return uniform(__shfl(v, 0));
+}
 
 template <typename T>
-__global__ __launch_bounds__(256) void gather_kernel(GatherArgs args) {
-    const long long p = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (p >= args.first[args.ng]) return;
+__global__ __launch_bounds__(64 * kWavesPerBlock, 2) void fine_batch_kernel(
+    const FineArgs *descs, const WorkItem *items, int nitems, int *counter) {
+    const int lane = threadIdx.x & 63;
+    for (;;) {
+        const int it = next_item_wave(counter, lane);
+        if (it >= nitems) return;
+        const WorkItem w = items[it];
+        fine_body<T>(descs[uniform(w.desc)], uniform(w.unit), lane);
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kTileThreads) void tile_batch_kernel(
+    const TileArgs *descs, const WorkItem *items, int nitems, int *counter) {
+    __shared__ TileLds lds;
+    __shared__ int s_item;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
+        lds_sync();
+        const int it = s_item;
+        lds_sync();   // everyone has read s_item (and the previous tile is stored)
+        if (it >= nitems) return;
+        const WorkItem w = items[it];
+        tile_body<T>(descs[w.desc], w.unit, lds);
+        lds_sync();   // the tile's LDS is free for the next item
+    }
+}
+
+// Gather pre-pass: unit p writes pixel p of the concatenated small levels of one image: I (3
+// planes) and alpha resized from full resolution by the nearest map, into each level's compact
+// planes.
+template <typename T>
+__device__ __forceinline__ void gather_body(const GatherArgs &args, long long p) {
     int l = 0;
     while (l + 1 < args.ng && p >= args.first[l + 1]) ++l;
     const int w = args.lw[l], h = args.lh[l];
@@ -1182,45 +1201,24 @@ __global__ __launch_bounds__(256) void gather_kernel(GatherArgs args) {
 }
 
 template <typename T>
-int launch_gather_t(const Plan &plan, const void *I, const void *A, void *pyr, hipStream_t s) {
-    GatherArgs a{};
-    a.I = I;
-    a.A = A;
-    a.W = plan.W;
-    a.H = plan.H;
-    a.pyr = static_cast<char *>(pyr);
-    a.ng = plan.ng;
-    long long total = 0;
-    for (int i = 0; i < plan.ng; ++i) {
-        a.lw[i] = plan.lv[i].w;
-        a.lh[i] = plan.lv[i].h;
-        a.first[i] = total;
-        a.off[i] = static_cast<long long>(plan.pyr_lv[i]);
-        total += static_cast<long long>(plan.lv[i].w) * plan.lv[i].h;
-    }
-    a.first[plan.ng] = total;
-    const int blocks = static_cast<int>((total + 255) / 256);
-    hipLaunchKernelGGL(gather_kernel<T>, dim3(blocks), dim3(256), 0, s, a);
-    return static_cast<int>(hipGetLastError());
+__global__ __launch_bounds__(256) void gather_kernel(GatherArgs args) {
+    const long long p = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (p < args.first[args.ng]) gather_body<T>(args, p);
 }
 
+// Batch: `first` holds each image's first pixel in the concatenation of all images' gathers.
 template <typename T>
-int launch_coarse_t(const Plan &plan, const LevelSrc &src, void *Fo, void *Bo, float omega,
-                    float eps, hipStream_t s) {
-    CoarseArgs a{};
-    a.src = src;
-    a.Fo = Fo;
-    a.Bo = Bo;
-    a.nc = plan.nc;
-    for (int i = 0; i < plan.nc; ++i) {
-        a.lw[i] = plan.lv[i].w;
-        a.lh[i] = plan.lv[i].h;
-        a.lit[i] = plan.lv[i].iters;
+__global__ __launch_bounds__(256) void gather_batch_kernel(const GatherArgs *descs,
+                                                           const long long *first, int n,
+                                                           long long total) {
+    const long long p = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (p >= total) return;
+    int lo = 0, hi = n - 1;   // last image whose first pixel is <= p
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (first[mid] <= p) lo = mid; else hi = mid - 1;
     }
-    a.omega = omega;
-    a.eps = eps;
-    hipLaunchKernelGGL(coarse_kernel<T>, dim3(1), dim3(kCoarseThreads), 0, s, a);
-    return static_cast<int>(hipGetLastError());
+    gather_body<T>(descs[lo], p - first[lo]);
 }
 
 int auto_strip_rows(int w, int h) {
@@ -1235,32 +1233,6 @@ int auto_strip_rows(int w, int h) {
     if (rows < 8) rows = 8;
     if (rows > h) rows = h;
     return static_cast<int>(rows);
-}
-
-template <typename T>
-int launch_fine_t(const LevelIO &io, int strip_rows, hipStream_t s) {
-    FineArgs a{};
-    a.I = io.I;
-    a.A = io.A;
-    a.W = io.W;
-    a.H = io.H;
-    a.Fp = io.Fp;
-    a.Bp = io.Bp;
-    a.wp = io.wp;
-    a.hp = io.hp;
-    a.Fo = io.Fo;
-    a.Bo = io.Bo;
-    a.w = io.w;
-    a.h = io.h;
-    a.omega = io.omega;
-    a.eps = io.eps;
-    a.nx = fine_strips_x(io.w);
-    a.strip_rows = strip_rows > 0 ? strip_rows : auto_strip_rows(io.w, io.h);
-    a.ny = (io.h + a.strip_rows - 1) / a.strip_rows;
-    const int waves = a.nx * a.ny;
-    const int blocks = (waves + kWavesPerBlock - 1) / kWavesPerBlock;
-    hipLaunchKernelGGL(fine_kernel<T>, dim3(blocks), dim3(64 * kWavesPerBlock), 0, s, a);
-    return static_cast<int>(hipGetLastError());
 }
 
 template <typename T>
@@ -1285,38 +1257,189 @@ int launch_naive_t(const LevelIO &io, int iters, hipStream_t s) {
     return 0;
 }
 
+// Persistent grids: enough waves / workgroups to fill the machine, never more than the items.
+constexpr int kPersistentWaves = 256 * 4 * 2;      // two waves per SIMD
+constexpr int kPersistentTileGroups = 256 * 2;     // two tile workgroups per CU
+
 }  // namespace
+
+// ---- descriptor builders ----------------------------------------------------------------
+
+void make_fine_args(const LevelIO &io, int strip_rows, FineArgs *a) {
+    *a = FineArgs{};
+    a->I = io.I;
+    a->A = io.A;
+    a->W = io.W;
+    a->H = io.H;
+    a->Fp = io.Fp;
+    a->Bp = io.Bp;
+    a->wp = io.wp;
+    a->hp = io.hp;
+    a->Fo = io.Fo;
+    a->Bo = io.Bo;
+    a->w = io.w;
+    a->h = io.h;
+    a->omega = io.omega;
+    a->eps = io.eps;
+    a->nx = fine_strips_x(io.w);
+    a->strip_rows = strip_rows > 0 ? strip_rows : auto_strip_rows(io.w, io.h);
+    a->ny = (io.h + a->strip_rows - 1) / a->strip_rows;
+}
+
+int fine_units(const FineArgs &a) { return a.nx * a.ny; }
+
+void make_tile_args(const LevelIO &io, TileArgs *a) {
+    *a = TileArgs{};
+    a->I = io.I;
+    a->A = io.A;
+    a->W = io.W;
+    a->H = io.H;
+    a->Fp = io.Fp;
+    a->Bp = io.Bp;
+    a->wp = io.wp;
+    a->hp = io.hp;
+    a->Fo = io.Fo;
+    a->Bo = io.Bo;
+    a->w = io.w;
+    a->h = io.h;
+    a->omega = io.omega;
+    a->eps = io.eps;
+    a->tiles_x = (io.w + kTileCore - 1) / kTileCore;
+}
+
+int tile_units(const TileArgs &a) { return a.tiles_x * ((a.h + kTileCore - 1) / kTileCore); }
+
+void make_coarse_args(const Plan &plan, const LevelSrc &src, void *Fo, void *Bo, float omega,
+                      float eps, CoarseArgs *a) {
+    *a = CoarseArgs{};
+    a->src = src;
+    a->Fo = Fo;
+    a->Bo = Bo;
+    a->nc = plan.nc;
+    for (int i = 0; i < plan.nc; ++i) {
+        a->lw[i] = plan.lv[i].w;
+        a->lh[i] = plan.lv[i].h;
+        a->lit[i] = plan.lv[i].iters;
+    }
+    a->omega = omega;
+    a->eps = eps;
+}
+
+void make_gather_args(const Plan &plan, const void *I, const void *A, void *pyr, GatherArgs *a) {
+    *a = GatherArgs{};
+    a->I = I;
+    a->A = A;
+    a->W = plan.W;
+    a->H = plan.H;
+    a->pyr = static_cast<char *>(pyr);
+    a->ng = plan.ng;
+    long long total = 0;
+    for (int i = 0; i < plan.ng; ++i) {
+        a->lw[i] = plan.lv[i].w;
+        a->lh[i] = plan.lv[i].h;
+        a->first[i] = total;
+        a->off[i] = static_cast<long long>(plan.pyr_lv[i]);
+        total += static_cast<long long>(plan.lv[i].w) * plan.lv[i].h;
+    }
+    a->first[plan.ng] = total;
+}
+
+long long gather_units(const GatherArgs &a) { return a.first[a.ng]; }
+
+// ---- single-image launches --------------------------------------------------------------
+
+#define FGE_DISPATCH(storage, KERNEL, ...)                                                    \
+    do {                                                                                      \
+        if ((storage) == FGE_F16)                                                             \
+            hipLaunchKernelGGL(KERNEL<_Float16>, __VA_ARGS__);                                \
+        else                                                                                  \
+            hipLaunchKernelGGL(KERNEL<float>, __VA_ARGS__);                                   \
+    } while (0)
 
 int launch_gather(const Plan &plan, const void *I, const void *A, void *pyr, int storage,
                   void *stream) {
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    if (storage == FGE_F16) return launch_gather_t<_Float16>(plan, I, A, pyr, s);
-    return launch_gather_t<float>(plan, I, A, pyr, s);
+    GatherArgs a;
+    make_gather_args(plan, I, A, pyr, &a);
+    const int blocks = static_cast<int>((gather_units(a) + 255) / 256);
+    FGE_DISPATCH(storage, gather_kernel, dim3(blocks), dim3(256), 0,
+                 static_cast<hipStream_t>(stream), a);
+    return static_cast<int>(hipGetLastError());
 }
 
 int launch_coarse(const Plan &plan, const LevelSrc &src, void *Fo, void *Bo, float omega,
                   float eps, int storage, void *stream) {
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    if (storage == FGE_F16) return launch_coarse_t<_Float16>(plan, src, Fo, Bo, omega, eps, s);
-    return launch_coarse_t<float>(plan, src, Fo, Bo, omega, eps, s);
+    CoarseArgs a;
+    make_coarse_args(plan, src, Fo, Bo, omega, eps, &a);
+    FGE_DISPATCH(storage, coarse_kernel, dim3(1), dim3(kCoarseThreads), 0,
+                 static_cast<hipStream_t>(stream), a);
+    return static_cast<int>(hipGetLastError());
 }
 
 int launch_fine_fused(const LevelIO &io, int strip_rows, int storage, void *stream) {
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    if (storage == FGE_F16) return launch_fine_t<_Float16>(io, strip_rows, s);
-    return launch_fine_t<float>(io, strip_rows, s);
+    FineArgs a;
+    make_fine_args(io, strip_rows, &a);
+    const int blocks = (fine_units(a) + kWavesPerBlock - 1) / kWavesPerBlock;
+    FGE_DISPATCH(storage, fine_kernel, dim3(blocks), dim3(64 * kWavesPerBlock), 0,
+                 static_cast<hipStream_t>(stream), a);
+    return static_cast<int>(hipGetLastError());
 }
 
 int launch_fine_tile(const LevelIO &io, int storage, void *stream) {
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    if (storage == FGE_F16) return launch_tile_t<_Float16>(io, s);
-    return launch_tile_t<float>(io, s);
+    TileArgs a;
+    make_tile_args(io, &a);
+    FGE_DISPATCH(storage, tile_kernel, dim3(tile_units(a)), dim3(kTileThreads), 0,
+                 static_cast<hipStream_t>(stream), a);
+    return static_cast<int>(hipGetLastError());
 }
 
 int launch_naive_level(const LevelIO &io, int iters, int storage, void *stream) {
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (storage == FGE_F16) return launch_naive_t<_Float16>(io, iters, s);
     return launch_naive_t<float>(io, iters, s);
+}
+
+// ---- batched launches -------------------------------------------------------------------
+
+int launch_zero(int *d, int n, void *stream) {
+    if (n <= 0) return 0;
+    hipLaunchKernelGGL(zero_kernel, dim3((n + 255) / 256), dim3(256), 0,
+                       static_cast<hipStream_t>(stream), d, n);
+    return static_cast<int>(hipGetLastError());
+}
+
+int launch_gather_batch(const GatherArgs *descs, const long long *first, int n, long long total,
+                        int storage, void *stream) {
+    if (total <= 0) return 0;
+    const int blocks = static_cast<int>((total + 255) / 256);
+    FGE_DISPATCH(storage, gather_batch_kernel, dim3(blocks), dim3(256), 0,
+                 static_cast<hipStream_t>(stream), descs, first, n, total);
+    return static_cast<int>(hipGetLastError());
+}
+
+int launch_coarse_batch(const CoarseArgs *descs, int n, int storage, void *stream) {
+    if (n <= 0) return 0;
+    FGE_DISPATCH(storage, coarse_batch_kernel, dim3(n), dim3(kCoarseThreads), 0,
+                 static_cast<hipStream_t>(stream), descs);
+    return static_cast<int>(hipGetLastError());
+}
+
+int launch_fine_batch(const FineArgs *descs, const WorkItem *items, int nitems, int *counter,
+                      int storage, void *stream) {
+    if (nitems <= 0) return 0;
+    const int waves = nitems < kPersistentWaves ? nitems : kPersistentWaves;
+    const int blocks = (waves + kWavesPerBlock - 1) / kWavesPerBlock;
+    FGE_DISPATCH(storage, fine_batch_kernel, dim3(blocks), dim3(64 * kWavesPerBlock), 0,
+                 static_cast<hipStream_t>(stream), descs, items, nitems, counter);
+    return static_cast<int>(hipGetLastError());
+}
+
+int launch_tile_batch(const TileArgs *descs, const WorkItem *items, int nitems, int *counter,
+                      int storage, void *stream) {
+    if (nitems <= 0) return 0;
+    const int groups = nitems < kPersistentTileGroups ? nitems : kPersistentTileGroups;
+    FGE_DISPATCH(storage, tile_batch_kernel, dim3(groups), dim3(kTileThreads), 0,
+                 static_cast<hipStream_t>(stream), descs, items, nitems, counter);
+    return static_cast<int>(hipGetLastError());
 }
 
 }  // namespace fge

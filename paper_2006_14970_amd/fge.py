@@ -78,6 +78,28 @@ def _lib():
     lib.fge_workspace_bytes.restype = sz
     lib.fge_estimate_foreground.argtypes = [vp, vp, i32, i32, pp, vp, vp, vp, sz, vp]
     lib.fge_estimate_foreground.restype = ctypes.c_int
+    bp = ctypes.c_void_p
+    vpp = ctypes.POINTER(ctypes.c_void_p)
+    lib.fge_batch_create.argtypes = [i32, ip, ip, pp, ctypes.POINTER(ctypes.c_void_p)]
+    lib.fge_batch_create.restype = ctypes.c_int
+    lib.fge_batch_destroy.argtypes = [bp]
+    lib.fge_batch_destroy.restype = None
+    lib.fge_batch_workspace_bytes.argtypes = [bp]
+    lib.fge_batch_workspace_bytes.restype = sz
+    lib.fge_batch_steps.argtypes = [bp]
+    lib.fge_batch_steps.restype = i32
+    lib.fge_batch_launch_count.argtypes = [bp]
+    lib.fge_batch_launch_count.restype = i32
+    for name in ("fge_batch_run", "fge_batch_capture"):
+        f = getattr(lib, name)
+        f.argtypes = [bp, vpp, vpp, vpp, vpp, vp, sz, vp]
+        f.restype = ctypes.c_int
+    lib.fge_batch_replay.argtypes = [bp, vp]
+    lib.fge_batch_replay.restype = ctypes.c_int
+    lib.fge_batch_workspace_bytes_for.argtypes = [i32, ip, ip, pp]
+    lib.fge_batch_workspace_bytes_for.restype = sz
+    lib.fge_estimate_foreground_batch.argtypes = [i32, vpp, vpp, ip, ip, pp, vpp, vpp, vp, sz, vp]
+    lib.fge_estimate_foreground_batch.restype = ctypes.c_int
     lib.fge_profile_start.argtypes = [i32]
     lib.fge_profile_start.restype = ctypes.c_int
     lib.fge_profile_stop.argtypes = [ctypes.POINTER(ctypes.c_double), ip, i32]
@@ -192,3 +214,93 @@ def profile_stop(max_levels: int = MAX_LEVELS):
     cnt = (ctypes.c_int32 * max_levels)()
     _check(_lib().fge_profile_stop(ms, cnt, max_levels), "fge_profile_stop")
     return list(ms), list(cnt)
+
+
+def _ptr_array(tensors):
+    arr = (ctypes.c_void_p * len(tensors))()
+    for i, t in enumerate(tensors):
+        arr[i] = t.data_ptr()
+    return arr
+
+
+class Batch:
+    """A batch plan for images of sizes [(W, H), ...] (fge_batch_create).  Every image follows
+    its own level plan, so its result is bit-identical to estimate_foreground's."""
+
+    def __init__(self, sizes, params: Params | None = None):
+        self.sizes = [(int(w), int(h)) for w, h in sizes]
+        self.params = params if params is not None else default_params()
+        n = len(self.sizes)
+        W = (ctypes.c_int32 * n)(*[w for w, _ in self.sizes])
+        H = (ctypes.c_int32 * n)(*[h for _, h in self.sizes])
+        handle = ctypes.c_void_p()
+        _check(_lib().fge_batch_create(n, W, H, ctypes.byref(self.params), ctypes.byref(handle)),
+               "fge_batch_create")
+        self._h = handle
+        self._keep = None
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib().fge_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def workspace_bytes(self) -> int:
+        return _lib().fge_batch_workspace_bytes(self._h)
+
+    @property
+    def steps(self) -> int:
+        return _lib().fge_batch_steps(self._h)
+
+    @property
+    def launch_count(self) -> int:
+        return _lib().fge_batch_launch_count(self._h)
+
+    def _args(self, Is, alphas, Fs, Bs, workspace):
+        import torch
+        dt = storage_dtype(self.params)
+        n = len(self.sizes)
+        if not (len(Is) == len(alphas) == n):
+            raise ValueError("one I and one alpha per image")
+        if Fs is None:
+            Fs = [torch.empty((3, h, w), dtype=dt, device=Is[0].device) for w, h in self.sizes]
+        if Bs is None:
+            Bs = [torch.empty((3, h, w), dtype=dt, device=Is[0].device) for w, h in self.sizes]
+        for (w, h), I, a, F, B in zip(self.sizes, Is, alphas, Fs, Bs):
+            for name, t, shp in (("I", I, (3, h, w)), ("alpha", a, (h, w)), ("F", F, (3, h, w)),
+                                 ("B", B, (3, h, w))):
+                if tuple(t.shape) != shp or t.dtype != dt or not t.is_cuda or not t.is_contiguous():
+                    raise ValueError(f"{name} must be a contiguous CUDA tensor {shp} of dtype {dt}")
+        if workspace is None:
+            workspace = torch.empty(max(1, self.workspace_bytes), dtype=torch.uint8,
+                                    device=Is[0].device)
+        return Fs, Bs, workspace
+
+    def run(self, Is, alphas, Fs=None, Bs=None, workspace=None, stream=None):
+        """Enqueue the batch; returns (Fs, Bs).  Does not synchronise."""
+        Fs, Bs, workspace = self._args(Is, alphas, Fs, Bs, workspace)
+        st = _lib().fge_batch_run(self._h, _ptr_array(Is), _ptr_array(alphas), _ptr_array(Fs),
+                                  _ptr_array(Bs), workspace.data_ptr(),
+                                  workspace.numel(), _stream_ptr(stream))
+        _check(st, "fge_batch_run")
+        self._keep = (Is, alphas, Fs, Bs, workspace)
+        return Fs, Bs
+
+    def capture(self, Is, alphas, Fs=None, Bs=None, workspace=None, stream=None):
+        """Capture one run with these buffers into a hipGraph; replay() launches it."""
+        Fs, Bs, workspace = self._args(Is, alphas, Fs, Bs, workspace)
+        st = _lib().fge_batch_capture(self._h, _ptr_array(Is), _ptr_array(alphas),
+                                      _ptr_array(Fs), _ptr_array(Bs), workspace.data_ptr(),
+                                      workspace.numel(), _stream_ptr(stream))
+        _check(st, "fge_batch_capture")
+        self._graph_keep = (Is, alphas, Fs, Bs, workspace)
+        return Fs, Bs
+
+    def replay(self, stream=None):
+        _check(_lib().fge_batch_replay(self._h, _stream_ptr(stream)), "fge_batch_replay")

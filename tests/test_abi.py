@@ -129,3 +129,39 @@ def test_argument_errors_before_launch(fge):
     assert _call(fge, 1024, 768, p, ws=0x100000, ws_len=need - 1) == fge.FGE_EWORKSPACE
     assert _call(fge, 1024, 768, p, ws=0x100010, ws_len=need) == fge.FGE_EWORKSPACE
     assert fge.load().fge_status_string(fge.FGE_EWORKSPACE).startswith(b"FGE_EWORKSPACE")
+
+
+def test_batch_planning_host_only(fge):
+    from paper_2006_14970_amd import synth
+    sizes = synth.batch_sizes()
+    p16 = fge.default_params(storage=fge.F16)
+    b = fge.Batch(sizes, p16)
+    n_levels = [len(fge.plan(w, h, p16).levels) for w, h in sizes]
+    n_coarse = [fge.plan(w, h, p16).n_coarse for w, h in sizes]
+    assert b.steps == max(n - c for n, c in zip(n_levels, n_coarse))
+    assert 4 <= b.launch_count <= 2 + 2 + 2 * b.steps
+    # the batch needs at least every image's own workspace
+    assert b.workspace_bytes >= sum(fge.workspace_bytes(w, h, p16) for w, h in sizes)
+    lib = fge.load()
+    n = len(sizes)
+    W = (ctypes.c_int32 * n)(*[w for w, _ in sizes])
+    H = (ctypes.c_int32 * n)(*[h for _, h in sizes])
+    assert lib.fge_batch_workspace_bytes_for(n, W, H, ctypes.byref(p16)) == b.workspace_bytes
+    b.close()
+
+
+def test_batch_argument_errors(fge):
+    with pytest.raises(fge.FgeError) as e:
+        fge.Batch([(10, 10), (0, 5)])
+    assert e.value.status == fge.FGE_EINVAL
+    with pytest.raises(fge.FgeError) as e:
+        fge.Batch([(300, 200)], fge.default_params(kernel=fge.KERNEL_NAIVE))
+    assert e.value.status == fge.FGE_EUNSUPPORTED
+    with pytest.raises(fge.FgeError) as e:
+        fge.Batch([(300, 200)], fge.default_params(coarse_max_px=-1))
+    assert e.value.status == fge.FGE_EUNSUPPORTED
+    b = fge.Batch([(300, 200), (40, 50)])
+    lib = fge.load()
+    null = (ctypes.c_void_p * 2)()
+    assert lib.fge_batch_run(b._h, null, null, null, null, None, 0, None) == fge.FGE_EINVAL
+    b.close()

@@ -1,0 +1,136 @@
+"""GPU: batched uneven-size images (persistent kernels, per-step work queues, hipGraph).
+
+Every batched image follows its own level plan through the same kernel bodies as the
+single-image path, so its F and B must be bit-identical to fge_estimate_foreground's; a few are
+also checked against the FP64 oracle.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2006_14970_amd import synth
+
+pytestmark = pytest.mark.gpu
+TOL = {"f32": 1e-4, "f16": 2e-3}
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    assert torch.cuda.is_available(), "the GPU tests need an MI355X"
+    from paper_2006_14970_amd import fge
+    fge.load()
+    return torch, fge
+
+
+def inputs(torch, fge, samples, params):
+    dt = fge.storage_dtype(params)
+    Is = [torch.from_numpy(s.I).to(dt).cuda() for s in samples]
+    As = [torch.from_numpy(s.alpha).to(dt).cuda() for s in samples]
+    return Is, As
+
+
+def single(torch, fge, I, a, params):
+    F, B = fge.estimate_foreground(I, a, params)
+    return F, B
+
+
+SIZES = [(1, 1), (3, 2), (37, 64), (64, 37), (129, 300), (300, 129), (257, 255), (700, 421),
+         (1000, 77), (16, 900), (520, 520), (128, 128)]
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_batch_bit_identical_to_single(gpu, storage):
+    torch, fge = gpu
+    p = fge.default_params(storage=fge.F16 if storage == "f16" else fge.F32)
+    samples = [synth.strands(w, h, seed=60 + i, n_strands=max(1, w * h // 3000))
+               for i, (w, h) in enumerate(SIZES)]
+    Is, As = inputs(torch, fge, samples, p)
+    b = fge.Batch(SIZES, p)
+    Fs, Bs = b.run(Is, As)
+    torch.cuda.synchronize()
+    for i in range(len(SIZES)):
+        F1, B1 = single(torch, fge, Is[i], As[i], p)
+        torch.cuda.synchronize()
+        assert torch.equal(Fs[i], F1) and torch.equal(Bs[i], B1), SIZES[i]
+    for i in (2, 5, 7):
+        s = samples[i]
+        Fo, Bo = oracle.ml(s.I, s.alpha)
+        err = max(float((Fs[i].double().cpu() - torch.from_numpy(Fo)).abs().max()),
+                  float((Bs[i].double().cpu() - torch.from_numpy(Bo)).abs().max()))
+        assert err <= TOL[storage], (SIZES[i], err)
+    b.close()
+
+
+def test_batch_run_twice_reuses_plan(gpu):
+    torch, fge = gpu
+    p = fge.default_params()
+    sizes = SIZES[:6]
+    samples = [synth.smooth(w, h, seed=80 + i) for i, (w, h) in enumerate(sizes)]
+    Is, As = inputs(torch, fge, samples, p)
+    b = fge.Batch(sizes, p)
+    Fs1, Bs1 = b.run(Is, As)
+    Is2 = [I.flip(-1).contiguous() for I in Is]
+    Fs2, Bs2 = b.run(Is2, As)
+    torch.cuda.synchronize()
+    for i in range(len(sizes)):
+        F1, B1 = single(torch, fge, Is[i], As[i], p)
+        F2, B2 = single(torch, fge, Is2[i], As[i], p)
+        torch.cuda.synchronize()
+        assert torch.equal(Fs1[i], F1) and torch.equal(Bs2[i], B2)
+    b.close()
+
+
+def test_batch_graph_replays(gpu):
+    """Capture once, replay several times with eager work and synchronisations in between; every
+    replay must reproduce the eager result (outputs are cleared before each replay)."""
+    torch, fge = gpu
+    p = fge.default_params(storage=fge.F16)
+    sizes = [(300, 200), (129, 300), (700, 421), (64, 37)]
+    samples = [synth.smooth(w, h, seed=90 + i) for i, (w, h) in enumerate(sizes)]
+    Is, As = inputs(torch, fge, samples, p)
+    b = fge.Batch(sizes, p)
+    ref = b.run(Is, As)
+    torch.cuda.synchronize()
+    ref = ([F.clone() for F in ref[0]], [B.clone() for B in ref[1]])
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        Fs, Bs = b.capture(Is, As, stream=stream)
+    torch.cuda.synchronize()
+    for rep in range(4):
+        for t in Fs + Bs:
+            t.zero_()
+        junk = torch.randn(1 << 20, device="cuda").sum()   # unrelated eager work
+        torch.cuda.synchronize()
+        b.replay(stream)
+        stream.synchronize()
+        for i in range(len(sizes)):
+            assert torch.equal(Fs[i], ref[0][i]) and torch.equal(Bs[i], ref[1][i]), (rep, i)
+        del junk
+    b.close()
+
+
+def test_uneven_batch_workload_f16(gpu):
+    """The 64-image uneven batch (W, H uniform on [256, 2048], float16 storage): a sample of
+    images bit-identical to their single-image runs, two against the oracle."""
+    torch, fge = gpu
+    p = fge.default_params(storage=fge.F16)
+    sizes = synth.batch_sizes()
+    samples = [synth.batch_image(i, w, h) for i, (w, h) in enumerate(sizes)]
+    Is, As = inputs(torch, fge, samples, p)
+    b = fge.Batch(sizes, p)
+    Fs, Bs = b.run(Is, As)
+    torch.cuda.synchronize()
+    order = sorted(range(len(sizes)), key=lambda i: sizes[i][0] * sizes[i][1])
+    for i in order[:3] + order[-3:] + [7, 31]:
+        F1, B1 = single(torch, fge, Is[i], As[i], p)
+        torch.cuda.synchronize()
+        assert torch.equal(Fs[i], F1) and torch.equal(Bs[i], B1), (i, sizes[i])
+    for i in order[:2]:
+        s = samples[i]
+        Fo, Bo = oracle.ml(s.I, s.alpha)
+        err = max(float((Fs[i].double().cpu() - torch.from_numpy(Fo)).abs().max()),
+                  float((Bs[i].double().cpu() - torch.from_numpy(Bo)).abs().max()))
+        print(f"batch image {i} {sizes[i]} f16 max-abs vs oracle {err:.2e}")
+        assert err <= TOL["f16"]
+    b.close()
