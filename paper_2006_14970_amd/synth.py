@@ -49,17 +49,23 @@ class Sample:
 def _sinusoid_field(rng: np.random.Generator, W: int, H: int, terms: int = 8) -> np.ndarray:
     """One channel: 0.05 + 0.9 * minmax(sum_k A_k sin(2 pi (fx x / W + fy y / H) + phi_k)).
 
-    Evaluated separably: sin(a + b) = sin a cos b + cos a sin b, as outer products."""
+    Evaluated separably, sin(a + b) = sin a cos b + cos a sin b, so the sum is one rank-2*terms
+    matrix product."""
     x = np.arange(W, dtype=np.float64)
     y = np.arange(H, dtype=np.float64)
-    acc = np.zeros((H, W), dtype=np.float64)
-    for _ in range(terms):
+    left = np.empty((H, 2 * terms))
+    right = np.empty((2 * terms, W))
+    for k in range(terms):
         fx, fy = rng.uniform(-3.0, 3.0, size=2)
         amp = rng.uniform(0.5, 1.0)
         phi = rng.uniform(0.0, 2.0 * math.pi)
         ax = 2.0 * math.pi * fx * x / W + phi
         by = 2.0 * math.pi * fy * y / H
-        acc += amp * (np.outer(np.cos(by), np.sin(ax)) + np.outer(np.sin(by), np.cos(ax)))
+        left[:, 2 * k] = amp * np.cos(by)
+        left[:, 2 * k + 1] = amp * np.sin(by)
+        right[2 * k] = np.sin(ax)
+        right[2 * k + 1] = np.cos(ax)
+    acc = left @ right
     lo, hi = acc.min(), acc.max()
     if hi - lo < 1e-12:
         return np.full((H, W), 0.5)
