@@ -169,6 +169,111 @@ def b_launches(fge, sizes, p):
     return n
 
 
+def run_serving(torch, fge, synth, args, single_f32_mps, check_oracle):
+    """The serving stream: requests with area log-uniform on 0.25-16 MP and aspect uniform on
+    [0.5, 2] (seed 5), smooth generator (seed 5000 + id), float16 storage, through the
+    continuous-batching server with a 64 GB budget.  Pass 1 submits every request at once
+    (saturated throughput); pass 2 submits them at Poisson arrival times at 0.8x that rate.
+    Inputs are generated into HBM before either pass; F and B land in preallocated HBM."""
+    n = args.serve_requests
+    reqs = synth.serving_requests(n=n, rate_per_s=1.0)   # unit-rate gaps, rescaled in pass 2
+    p = fge.default_params(storage=fge.F16)
+    px = np.array([r.W * r.H for r in reqs], dtype=np.int64)
+    mp = float(px.sum()) / 1e6
+    in_off = np.concatenate([[0], np.cumsum(4 * px)])
+    out_off = np.concatenate([[0], np.cumsum(6 * px)])
+    log(f"serving: generating {n} requests ({mp:.0f} MP, {20 * px.sum() / 1e9:.0f} GB of I, "
+        "alpha, F, B in float16) on the device")
+    t = time.perf_counter()
+    pool_in = torch.empty(int(in_off[-1]), dtype=torch.float16, device="cuda")
+    pool_out = torch.empty(int(out_off[-1]), dtype=torch.float16, device="cuda")
+    views = []
+    for k, r in enumerate(reqs):
+        q = int(px[k])
+        I = pool_in[in_off[k]:in_off[k] + 3 * q].view(3, r.H, r.W)
+        a = pool_in[in_off[k] + 3 * q:in_off[k + 1]].view(r.H, r.W)
+        F = pool_out[out_off[k]:out_off[k] + 3 * q].view(3, r.H, r.W)
+        B = pool_out[out_off[k] + 3 * q:out_off[k + 1]].view(3, r.H, r.W)
+        synth.smooth_device(r.W, r.H, 5000 + r.rid, "cuda", dtype=torch.float16, out_I=I, out_alpha=a)
+        views.append((I, a, F, B))
+    torch.cuda.synchronize()
+    ptrs = [(I.data_ptr(), a.data_ptr(), F.data_ptr(), B.data_ptr()) for I, a, F, B in views]
+    log(f"  generated in {time.perf_counter() - t:.1f} s")
+    budget = 64 * 10**9
+    arena = torch.empty(16 << 30, dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.Stream()
+    cfg = fge.server_config(budget_bytes=budget)
+
+    def serve(arrivals):
+        srv = fge.Server(p, cfg, arena=arena, stream=stream)
+        start = time.perf_counter()
+        k = 0
+        late = []
+        while k < n:
+            now = time.perf_counter() - start
+            while k < n and arrivals[k] <= now:
+                I, a, F, B = ptrs[k]
+                srv.submit_ptrs(k, I, a, reqs[k].W, reqs[k].H, F, B)
+                late.append(time.perf_counter() - start - arrivals[k])
+                k += 1
+        srv.drain()
+        res = srv.poll(n)
+        st = srv.stats()
+        srv.close()
+        assert len(res) == n and all(r.status == 0 for r in res)
+        lat = np.array([r.latency_ms for r in res])
+        span_ms = max(r.ready_ms for r in res) - min(r.submit_ms for r in res)
+        return {"makespan_ms": span_ms, "value": mp / (span_ms * 1e-3),
+                "requests_per_s": n / (span_ms * 1e-3),
+                "latency_ms": {"p50": float(np.percentile(lat, 50)),
+                               "p99": float(np.percentile(lat, 99)),
+                               "mean": float(lat.mean()), "max": float(lat.max())},
+                "submit_lateness_ms_p99": float(np.percentile(np.array(late), 99)) * 1e3,
+                "server": {k2: (float(v) if isinstance(v, float) else int(v)) for k2, v in st.items()}}
+
+    log("  pass 1: all requests at once (saturated)")
+    sat = serve([0.0] * n)
+    log(f"  saturated: {sat['value']:.0f} MP/s, {sat['requests_per_s']:.0f} req/s, "
+        f"mean {sat['server']['mean_active']:.1f} requests per tick")
+    rate = 0.8 * sat["requests_per_s"]
+    arrivals = [r.arrival_s / rate for r in reqs]
+    log(f"  pass 2: Poisson arrivals at {rate:.0f} req/s")
+    poi = serve(arrivals)
+    log(f"  Poisson: {poi['value']:.0f} MP/s, latency p50 {poi['latency_ms']['p50']:.3f} ms, "
+        f"p99 {poi['latency_ms']['p99']:.3f} ms")
+
+    # Parity on a sample: the served result equals the request run alone (bit for bit), and the
+    # smallest requests match the FP64 oracle at the float16 tolerance.
+    order = np.argsort(px)
+    sample = sorted(set(int(i) for i in order[:3]) | set(int(i) for i in order[-2:]) |
+                    set(range(0, n, max(1, n // 5))))
+    same = 0
+    for k in sample:
+        I, a, F, B = views[k]
+        Fa, Ba = fge.estimate_foreground(I, a, p)
+        torch.cuda.synchronize()
+        same += int(torch.equal(Fa, F) and torch.equal(Ba, B))
+    err = None
+    if check_oracle:
+        import oracle
+        err = 0.0
+        for k in order[:2]:
+            I, a, F, B = views[int(k)]
+            Fo, Bo = oracle.ml(I.double().cpu().numpy(), a.double().cpu().numpy())
+            err = max(err, float(np.abs(F.double().cpu().numpy() - Fo).max()),
+                      float(np.abs(B.double().cpu().numpy() - Bo).max()))
+    del pool_in, pool_out, arena, views
+    torch.cuda.empty_cache()
+    return {"workload": f"{n} requests, area log-uniform on 0.25-16 MP, aspect uniform on "
+                        "[0.5, 2] (seed 5), smooth generator on the device (seed 5000 + id), "
+                        "float16 storage, float32 arithmetic, 64 GB admission budget",
+            "requests": n, "megapixels": mp, "budget_bytes": budget, "unit": "MP/s",
+            "saturated": sat, "poisson_rate_per_s": rate, "poisson": poi,
+            "vs_single_image_f32": sat["value"] / single_f32_mps,
+            "alone_vs_served_bit_identical": f"{same}/{len(sample)}",
+            "max_abs_vs_oracle_2_smallest": err}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -177,6 +282,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the 64-image uneven batch (float16 storage) leg")
+    ap.add_argument("--no-serving", action="store_true",
+                    help="skip the serving-stream (continuous batching, float16 storage) leg")
+    ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 512 MiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -247,6 +355,8 @@ def main():
     s16 = summary(res["f16"], 2)
     batch = None if args.no_batch else run_batch(torch, fge, synth, args, s32["value"],
                                                    not args.no_cpu_baseline)
+    serving = None if args.no_serving else run_serving(torch, fge, synth, args, s32["value"],
+                                                         not args.no_cpu_baseline)
     out = {
         "metric": "MP/s foreground estimation @4096x3072 FP32 vs FP16-store; p50/p99 latency",
         "value": s32["value"],
@@ -269,6 +379,7 @@ def main():
         "fp16_store": s16,
         "level_ms_finest_first": s32["level_ms_finest_first"],
         "batch_fp16": batch,
+        "serving_fp16": serving,
         "cpu_baseline": cpu,
     }
     if args.copy_calibration:

@@ -49,7 +49,8 @@ typedef enum fge_status {
     FGE_ENOMEM = -2,        /* host allocation failed */
     FGE_EHIP = -3,          /* a HIP runtime call or kernel launch failed */
     FGE_EUNSUPPORTED = -4,  /* valid request this build does not implement */
-    FGE_EWORKSPACE = -5     /* workspace missing or smaller than fge_workspace_bytes */
+    FGE_EWORKSPACE = -5,    /* workspace missing or smaller than fge_workspace_bytes */
+    FGE_EBUDGET = -6        /* a request that can never fit a server's budget or arena */
 } fge_status;
 
 typedef enum fge_dtype { FGE_F32 = 0, FGE_F16 = 1 } fge_dtype;
@@ -90,7 +91,7 @@ void fge_default_params(fge_params *p);
 /* Human-readable name of a status code (static string). */
 const char *fge_status_string(int status);
 
-/* Library ABI version (increments when fge_params or a signature changes); this header is 2. */
+/* Library ABI version (increments when fge_params or a signature changes); this header is 3. */
 int32_t fge_version(void);
 
 /* ---- host-only planning (no GPU needed) ---------------------------------------------- */
@@ -173,6 +174,100 @@ fge_status fge_estimate_foreground_batch(int32_t n, const void *const *I, const 
                                          const int32_t *W, const int32_t *H, const fge_params *p,
                                          void *const *F, void *const *B, void *workspace,
                                          size_t workspace_bytes, void *stream);
+
+/* ---- serving: continuous batching of requests that arrive over time -------------------- */
+
+/* A server runs requests (one image each, Algorithm 1 as fge_estimate_foreground runs it, so a
+ * request's F and B are bit-identical to that call's) on one stream with continuous batching at
+ * level granularity.  A scheduler thread owned by the server repeats a "tick": it admits queued
+ * requests in arrival order while the HBM budget and the slot count allow, then enqueues ONE
+ * set of batched launches (the gather and coarse kernels for the requests admitted in this tick,
+ * then one persistent tile launch and one persistent streaming launch) that advances EVERY
+ * admitted request by one fine level; a new request also runs its first fine level in the tick
+ * that admits it.  So requests that arrive while others are on the device join the next tick and
+ * share its launches; each request's pyramid state (its intermediate levels' F and B and the
+ * compact input copies) stays in its own block of the server's arena from admission to
+ * completion.  Ticks are enqueued up to pipeline_depth ahead of the device.
+ *
+ * Memory.  The caller hands the server one device arena.  It holds the tick tables
+ * (fge_server_reserved_bytes) and every admitted request's workspace, carved first-fit.  The
+ * budget bounds the sum of admitted requests' footprints, fge_server_request_bytes: their I,
+ * alpha, F and B (caller buffers, held by the request until it completes) plus the workspace.
+ * A request is admitted only when both its footprint fits the budget and its workspace fits the
+ * arena; it is released when the device has finished its last level.
+ *
+ * Timing.  At creation the server records a start event on its idle stream; a request's ready
+ * time is the device timestamp of the end of its last tick, and its latency is that minus its
+ * submission time on the host's steady clock, both relative to the start event. */
+typedef struct fge_server fge_server;
+
+typedef struct fge_server_config {
+    uint32_t size;             /* sizeof(fge_server_config) */
+    int32_t max_active;        /* most requests admitted at once; 0 = 1024 */
+    int32_t pipeline_depth;    /* ticks enqueued ahead of the device (1..8); 0 = 2 */
+    int32_t reserved0;
+    uint64_t budget_bytes;     /* bound on the admitted footprints; 0 = the arena size */
+    uint64_t tick_table_bytes; /* descriptor and work-list capacity of one tick; 0 = 16 MiB */
+} fge_server_config;
+
+typedef struct fge_server_result {
+    int64_t id;                /* the id given to fge_server_submit */
+    int32_t status;            /* FGE_OK, or the error that ended the server */
+    int32_t ticks;             /* ticks the request took part in */
+    double submit_ms;          /* host submission time, ms after the start event */
+    double admit_ms;           /* host time the scheduler admitted it */
+    double ready_ms;           /* device time its F and B were complete */
+    double latency_ms;         /* ready_ms - submit_ms */
+} fge_server_result;
+
+typedef struct fge_server_stats {
+    int64_t submitted, completed, ticks, launches;
+    int64_t mixed_ticks;       /* ticks that advanced requests at two or more different levels */
+    int64_t admitted_while_busy; /* requests admitted while other requests were on the device */
+    int32_t peak_active;
+    int32_t reserved0;
+    uint64_t peak_charged_bytes; /* peak sum of admitted footprints (<= budget_bytes) */
+    uint64_t peak_arena_bytes;   /* peak arena bytes in use (tables included) */
+    double mean_active;        /* admitted requests per tick, averaged over ticks */
+} fge_server_stats;
+
+/* Fill *c with the defaults above. */
+void fge_server_default_config(fge_server_config *c);
+
+/* Footprint a W x H request is charged against the budget under *p (0 on bad arguments). */
+size_t fge_server_request_bytes(int32_t W, int32_t H, const fge_params *p);
+
+/* Arena bytes the server keeps for its tick tables under *c (the rest holds workspaces). */
+size_t fge_server_reserved_bytes(const fge_server_config *c);
+
+/* Create a server for requests under *p (NULL = defaults; the same restrictions as batches:
+ * coarse block and fused fine levels) and *c (NULL = defaults).  `arena` is a device buffer of
+ * arena_bytes (256-byte aligned start), owned by the caller, which must keep it alive and unused
+ * until fge_server_destroy returns.  `stream` (not NULL) is the hipStream_t every launch goes to.
+ * Starts the scheduler thread.  Allocates pinned host staging and events, no device memory. */
+fge_status fge_server_create(const fge_params *p, const fge_server_config *c, void *arena,
+                             size_t arena_bytes, void *stream, fge_server **out);
+
+/* Queue a request: I (3 x H x W), alpha (H x W), F and B (3 x H x W) are device buffers in
+ * p->storage type, laid out as for fge_estimate_foreground, ready when this is called (the
+ * server's stream does not wait for other streams), and left alone by the caller until the
+ * request is reported complete.  Returns at once.  FGE_EBUDGET if the request could never be
+ * admitted; FGE_EINVAL / FGE_EUNSUPPORTED on bad arguments; FGE_EHIP if the server has failed. */
+fge_status fge_server_submit(fge_server *s, int64_t id, const void *I, const void *alpha,
+                             int32_t W, int32_t H, void *F, void *B);
+
+/* Move up to `cap` completed requests (completion order) into out[]; returns how many, or a
+ * negative status if the server has failed.  Never blocks. */
+int32_t fge_server_poll(fge_server *s, fge_server_result *out, int32_t cap);
+
+/* Block until every request submitted so far has completed (results stay pollable). */
+fge_status fge_server_drain(fge_server *s);
+
+/* Counters since creation. */
+fge_status fge_server_get_stats(fge_server *s, fge_server_stats *out);
+
+/* Drain, stop the scheduler thread and free the server's host resources (not the arena). */
+void fge_server_destroy(fge_server *s);
 
 /* ---- profiling ------------------------------------------------------------------------- */
 

@@ -10,7 +10,7 @@
 
 namespace {
 
-constexpr int32_t kAbiVersion = 2;
+constexpr int32_t kAbiVersion = 3;
 
 struct ProfileRecord {
     int level;          // 0 = finest
@@ -82,6 +82,7 @@ const char *fge_status_string(int status) {
         case FGE_EHIP: return "FGE_EHIP: HIP runtime or launch error";
         case FGE_EUNSUPPORTED: return "FGE_EUNSUPPORTED: not implemented for these parameters";
         case FGE_EWORKSPACE: return "FGE_EWORKSPACE: workspace missing or too small";
+        case FGE_EBUDGET: return "FGE_EBUDGET: request larger than the server budget or arena";
         default: return "unknown fge status";
     }
 }
@@ -140,68 +141,20 @@ fge_status fge_estimate_foreground(const void *I, const void *alpha, int32_t W, 
     hipStream_t s = static_cast<hipStream_t>(stream);
     char *ws = static_cast<char *>(workspace);
     const int n = plan.n;
-    // F and B of level i (0-based): the caller's buffers for the last level, else a ping-pong
-    // workspace buffer holding F's 3 planes followed by B's.
-    auto state = [&](int i, void **f, void **b) {
-        if (i == n - 1) {
-            *f = F;
-            *b = B;
-            return;
-        }
-        const int k = (n - 2 - i) % 2;
-        char *base = ws + plan.buf_off[k];
-        *f = base;
-        *b = base + 3 * static_cast<size_t>(plan.lv[i].w) * plan.lv[i].h * plan.elem;
-    };
-
-    // I and alpha of level i: its compact copy from the gather pre-pass, or full resolution.
-    auto source = [&](int i, const void **Ii, const void **Ai, int *Wi, int *Hi) {
-        if (i < plan.ng) {
-            const char *base = ws + plan.pyr_off + plan.pyr_lv[i];
-            const size_t plane = static_cast<size_t>(plan.lv[i].w) * plan.lv[i].h * plan.elem;
-            *Ii = base;
-            *Ai = base + 3 * plane;
-            *Wi = plan.lv[i].w;
-            *Hi = plan.lv[i].h;
-        } else {
-            *Ii = I;
-            *Ai = alpha;
-            *Wi = W;
-            *Hi = H;
-        }
-    };
     if (plan.ng > 0) {
         LaunchTimer timer(n, s);   // recorded under index n_levels
         if (fge::launch_gather(plan, I, alpha, ws + plan.pyr_off, prm.storage, s)) return FGE_EHIP;
     }
     if (plan.nc > 0) {
         void *fo, *bo;
-        state(plan.nc - 1, &fo, &bo);
-        fge::LevelSrc src{};
-        for (int i = 0; i < plan.nc; ++i) source(i, &src.I[i], &src.A[i], &src.W[i], &src.H[i]);
+        fge::level_state(plan, ws, plan.nc - 1, F, B, &fo, &bo);
+        const fge::LevelSrc src = fge::coarse_src(plan, ws, I, alpha);
         LaunchTimer timer(n - plan.nc, s);
         if (fge::launch_coarse(plan, src, fo, bo, prm.omega, prm.eps_r, prm.storage, s))
             return FGE_EHIP;
     }
     for (int i = plan.nc; i < n; ++i) {
-        fge::LevelIO io{};
-        source(i, &io.I, &io.A, &io.W, &io.H);
-        if (i > 0) {
-            void *fp, *bp;
-            state(i - 1, &fp, &bp);
-            io.Fp = fp;
-            io.Bp = bp;
-            io.wp = plan.lv[i - 1].w;
-            io.hp = plan.lv[i - 1].h;
-        } else {
-            io.Fp = io.Bp = nullptr;
-            io.wp = io.hp = 1;
-        }
-        state(i, &io.Fo, &io.Bo);
-        io.w = plan.lv[i].w;
-        io.h = plan.lv[i].h;
-        io.omega = prm.omega;
-        io.eps = prm.eps_r;
+        const fge::LevelIO io = fge::level_io(plan, ws, i, I, alpha, F, B, prm.omega, prm.eps_r);
         LaunchTimer timer(n - 1 - i, s);
         int err = 0;
         switch (plan.kind[i]) {

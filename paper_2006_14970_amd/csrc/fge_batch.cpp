@@ -62,56 +62,10 @@ struct fge_batch {
 
 namespace {
 
-// Level state of image i, level j: the caller's buffers for its last level, else its ping-pong
-// workspace buffer (F planes then B planes).
-void level_state(const fge_batch &b, int i, int j, char *ws, void *const *F, void *const *B,
-                 void **f, void **bb) {
-    const fge::Plan &pl = b.plans[i];
-    if (j == pl.n - 1) {
-        *f = F[i];
-        *bb = B[i];
-        return;
-    }
-    const int k = (pl.n - 2 - j) % 2;
-    char *base = ws + b.img_off[i] + pl.buf_off[k];
-    *f = base;
-    *bb = base + 3 * static_cast<size_t>(pl.lv[j].w) * pl.lv[j].h * pl.elem;
-}
-
-void level_source(const fge_batch &b, int i, int j, char *ws, const void *const *I,
-                  const void *const *A, const void **Ii, const void **Ai, int *Wi, int *Hi) {
-    const fge::Plan &pl = b.plans[i];
-    if (j < pl.ng) {
-        const char *base = ws + b.img_off[i] + pl.pyr_off + pl.pyr_lv[j];
-        const size_t plane = static_cast<size_t>(pl.lv[j].w) * pl.lv[j].h * pl.elem;
-        *Ii = base;
-        *Ai = base + 3 * plane;
-        *Wi = pl.lv[j].w;
-        *Hi = pl.lv[j].h;
-    } else {
-        *Ii = I[i];
-        *Ai = A[i];
-        *Wi = pl.W;
-        *Hi = pl.H;
-    }
-}
-
 fge::LevelIO level_io(const fge_batch &b, int i, int j, char *ws, const void *const *I,
                       const void *const *A, void *const *F, void *const *B) {
-    fge::LevelIO io{};
-    level_source(b, i, j, ws, I, A, &io.I, &io.A, &io.W, &io.H);
-    void *fp, *bp;
-    level_state(b, i, j - 1, ws, F, B, &fp, &bp);
-    io.Fp = fp;
-    io.Bp = bp;
-    io.wp = b.plans[i].lv[j - 1].w;
-    io.hp = b.plans[i].lv[j - 1].h;
-    level_state(b, i, j, ws, F, B, &io.Fo, &io.Bo);
-    io.w = b.plans[i].lv[j].w;
-    io.h = b.plans[i].lv[j].h;
-    io.omega = b.prm.omega;
-    io.eps = b.prm.eps_r;
-    return io;
+    return fge::level_io(b.plans[i], ws + b.img_off[i], j, I[i], A[i], F[i], B[i], b.prm.omega,
+                         b.prm.eps_r);
 }
 
 // Fill the table region image (descriptors and work lists) for these pointers.
@@ -131,11 +85,10 @@ void fill_tables(const fge_batch &b, char *tab, char *ws, const void *const *I,
     for (size_t k = 0; k < b.coarse_imgs.size(); ++k) {
         const int i = b.coarse_imgs[k];
         const fge::Plan &pl = b.plans[i];
-        fge::LevelSrc src{};
-        for (int j = 0; j < pl.nc; ++j)
-            level_source(b, i, j, ws, I, A, &src.I[j], &src.A[j], &src.W[j], &src.H[j]);
+        char *iws = ws + b.img_off[i];
+        const fge::LevelSrc src = fge::coarse_src(pl, iws, I[i], A[i]);
         void *fo, *bo;
-        level_state(b, i, pl.nc - 1, ws, F, B, &fo, &bo);
+        fge::level_state(pl, iws, pl.nc - 1, F[i], B[i], &fo, &bo);
         fge::make_coarse_args(pl, src, fo, bo, b.prm.omega, b.prm.eps_r, &cd[k]);
     }
     for (const Launch &L : b.launches) {

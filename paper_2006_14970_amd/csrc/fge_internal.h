@@ -70,6 +70,21 @@ struct LevelSrc {
     int W[kMaxLevels], H[kMaxLevels];
 };
 
+// Where an image's level data lives, given its plan, its workspace `ws` (plan.ws_bytes bytes) and
+// the caller's full-resolution I, alpha, F, B.  Host-only address arithmetic.
+//   level_state:  F and B of level j (the caller's buffers for the last level, else the level's
+//                 ping-pong workspace buffer: F's 3 planes, then B's).
+//   level_source: I and alpha of level j (its compact gather copy, else full resolution) with
+//                 the size they are stored at.
+//   level_io:     the record of fine level j > 0 (source, previous state, output state).
+//   coarse_src:   level_source of every coarse level.
+void level_state(const Plan &pl, char *ws, int j, void *F, void *B, void **f, void **b);
+void level_source(const Plan &pl, const char *ws, int j, const void *I, const void *A,
+                  const void **Ij, const void **Aj, int *Wj, int *Hj);
+LevelIO level_io(const Plan &pl, char *ws, int j, const void *I, const void *A, void *F, void *B,
+                 float omega, float eps);
+LevelSrc coarse_src(const Plan &pl, const char *ws, const void *I, const void *A);
+
 int launch_gather(const Plan &plan, const void *I, const void *A, void *pyr, int storage,
                   void *stream);
 int launch_coarse(const Plan &plan, const LevelSrc &src, void *Fo, void *Bo, float omega,

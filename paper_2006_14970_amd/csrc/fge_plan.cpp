@@ -111,4 +111,61 @@ fge_status make_plan(int W, int H, const fge_params &p, Plan *out) {
     return FGE_OK;
 }
 
+void level_state(const Plan &pl, char *ws, int j, void *F, void *B, void **f, void **b) {
+    if (j == pl.n - 1) {
+        *f = F;
+        *b = B;
+        return;
+    }
+    char *base = ws + pl.buf_off[(pl.n - 2 - j) % 2];
+    *f = base;
+    *b = base + 3 * static_cast<size_t>(pl.lv[j].w) * pl.lv[j].h * pl.elem;
+}
+
+void level_source(const Plan &pl, const char *ws, int j, const void *I, const void *A,
+                  const void **Ij, const void **Aj, int *Wj, int *Hj) {
+    if (j < pl.ng) {
+        const char *base = ws + pl.pyr_off + pl.pyr_lv[j];
+        *Ij = base;
+        *Aj = base + 3 * static_cast<size_t>(pl.lv[j].w) * pl.lv[j].h * pl.elem;
+        *Wj = pl.lv[j].w;
+        *Hj = pl.lv[j].h;
+    } else {
+        *Ij = I;
+        *Aj = A;
+        *Wj = pl.W;
+        *Hj = pl.H;
+    }
+}
+
+LevelIO level_io(const Plan &pl, char *ws, int j, const void *I, const void *A, void *F, void *B,
+                 float omega, float eps) {
+    LevelIO io{};
+    level_source(pl, ws, j, I, A, &io.I, &io.A, &io.W, &io.H);
+    if (j > 0) {
+        void *fp, *bp;
+        level_state(pl, ws, j - 1, F, B, &fp, &bp);
+        io.Fp = fp;
+        io.Bp = bp;
+        io.wp = pl.lv[j - 1].w;
+        io.hp = pl.lv[j - 1].h;
+    } else {
+        io.Fp = io.Bp = nullptr;
+        io.wp = io.hp = 1;
+    }
+    level_state(pl, ws, j, F, B, &io.Fo, &io.Bo);
+    io.w = pl.lv[j].w;
+    io.h = pl.lv[j].h;
+    io.omega = omega;
+    io.eps = eps;
+    return io;
+}
+
+LevelSrc coarse_src(const Plan &pl, const char *ws, const void *I, const void *A) {
+    LevelSrc src{};
+    for (int j = 0; j < pl.nc; ++j)
+        level_source(pl, ws, j, I, A, &src.I[j], &src.A[j], &src.W[j], &src.H[j]);
+    return src;
+}
+
 }  // namespace fge

@@ -17,6 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libfge.so")
 
 FGE_OK, FGE_EINVAL, FGE_ENOMEM, FGE_EHIP, FGE_EUNSUPPORTED, FGE_EWORKSPACE = 0, -1, -2, -3, -4, -5
+FGE_EBUDGET = -6
 F32, F16 = 0, 1
 REDBLACK = 0
 KERNEL_AUTO, KERNEL_FUSED, KERNEL_NAIVE = 0, 1, 2
@@ -44,6 +45,45 @@ class Params(ctypes.Structure):
         ("strip_rows", ctypes.c_int32),
         ("coarse_max_px", ctypes.c_int32),
         ("tile_max_px", ctypes.c_int32),
+    ]
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [
+        ("size", ctypes.c_uint32),
+        ("max_active", ctypes.c_int32),
+        ("pipeline_depth", ctypes.c_int32),
+        ("reserved0", ctypes.c_int32),
+        ("budget_bytes", ctypes.c_uint64),
+        ("tick_table_bytes", ctypes.c_uint64),
+    ]
+
+
+class ServerResult(ctypes.Structure):
+    _fields_ = [
+        ("id", ctypes.c_int64),
+        ("status", ctypes.c_int32),
+        ("ticks", ctypes.c_int32),
+        ("submit_ms", ctypes.c_double),
+        ("admit_ms", ctypes.c_double),
+        ("ready_ms", ctypes.c_double),
+        ("latency_ms", ctypes.c_double),
+    ]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [
+        ("submitted", ctypes.c_int64),
+        ("completed", ctypes.c_int64),
+        ("ticks", ctypes.c_int64),
+        ("launches", ctypes.c_int64),
+        ("mixed_ticks", ctypes.c_int64),
+        ("admitted_while_busy", ctypes.c_int64),
+        ("peak_active", ctypes.c_int32),
+        ("reserved0", ctypes.c_int32),
+        ("peak_charged_bytes", ctypes.c_uint64),
+        ("peak_arena_bytes", ctypes.c_uint64),
+        ("mean_active", ctypes.c_double),
     ]
 
 
@@ -104,6 +144,25 @@ def _lib():
     lib.fge_profile_start.restype = ctypes.c_int
     lib.fge_profile_stop.argtypes = [ctypes.POINTER(ctypes.c_double), ip, i32]
     lib.fge_profile_stop.restype = ctypes.c_int
+    cp = ctypes.POINTER(ServerConfig)
+    lib.fge_server_default_config.argtypes = [cp]
+    lib.fge_server_default_config.restype = None
+    lib.fge_server_request_bytes.argtypes = [i32, i32, pp]
+    lib.fge_server_request_bytes.restype = sz
+    lib.fge_server_reserved_bytes.argtypes = [cp]
+    lib.fge_server_reserved_bytes.restype = sz
+    lib.fge_server_create.argtypes = [pp, cp, vp, sz, vp, ctypes.POINTER(ctypes.c_void_p)]
+    lib.fge_server_create.restype = ctypes.c_int
+    lib.fge_server_submit.argtypes = [vp, ctypes.c_int64, vp, vp, i32, i32, vp, vp]
+    lib.fge_server_submit.restype = ctypes.c_int
+    lib.fge_server_poll.argtypes = [vp, ctypes.POINTER(ServerResult), i32]
+    lib.fge_server_poll.restype = i32
+    lib.fge_server_drain.argtypes = [vp]
+    lib.fge_server_drain.restype = ctypes.c_int
+    lib.fge_server_get_stats.argtypes = [vp, ctypes.POINTER(ServerStats)]
+    lib.fge_server_get_stats.restype = ctypes.c_int
+    lib.fge_server_destroy.argtypes = [vp]
+    lib.fge_server_destroy.restype = None
     _LIB = lib
     return lib
 
@@ -304,3 +363,104 @@ class Batch:
 
     def replay(self, stream=None):
         _check(_lib().fge_batch_replay(self._h, _stream_ptr(stream)), "fge_batch_replay")
+
+
+def server_config(**overrides) -> ServerConfig:
+    """fge_server_default_config with optional overrides, e.g. ``server_config(max_active=8)``."""
+    c = ServerConfig()
+    _lib().fge_server_default_config(ctypes.byref(c))
+    for k, v in overrides.items():
+        if not hasattr(c, k):
+            raise KeyError(k)
+        setattr(c, k, v)
+    return c
+
+
+def server_request_bytes(W: int, H: int, params: Params | None = None) -> int:
+    """Footprint a W x H request is charged against a server's budget."""
+    return _lib().fge_server_request_bytes(W, H, ctypes.byref(params) if params else None)
+
+
+def server_reserved_bytes(config: ServerConfig | None = None) -> int:
+    return _lib().fge_server_reserved_bytes(ctypes.byref(config) if config else None)
+
+
+class Server:
+    """Continuous-batching request server (fge_server_*).  `arena` is a CUDA uint8 tensor the
+    server carves its tick tables and the requests' workspaces from; `stream` the torch stream
+    every launch goes to.  Inputs must be complete on the device before they are submitted."""
+
+    def __init__(self, params: Params | None = None, config: ServerConfig | None = None,
+                 arena=None, arena_bytes: int | None = None, stream=None):
+        import torch
+        self.params = params if params is not None else default_params()
+        self.config = config if config is not None else server_config()
+        if arena is None:
+            if arena_bytes is None:
+                raise ValueError("give an arena tensor or arena_bytes")
+            arena = torch.empty(arena_bytes, dtype=torch.uint8, device="cuda")
+        if not arena.is_cuda or arena.dtype != torch.uint8 or not arena.is_contiguous():
+            raise ValueError("arena must be a contiguous CUDA uint8 tensor")
+        self.stream = stream if stream is not None else torch.cuda.Stream()
+        self.arena = arena
+        handle = ctypes.c_void_p()
+        _check(_lib().fge_server_create(ctypes.byref(self.params), ctypes.byref(self.config),
+                                        arena.data_ptr(), arena.numel(),
+                                        ctypes.c_void_p(self.stream.cuda_stream),
+                                        ctypes.byref(handle)), "fge_server_create")
+        self._h = handle
+        self._held = {}
+
+    def submit(self, rid: int, I, alpha, F=None, B=None):
+        """Queue request `rid` with tensors I (3, H, W) and alpha (H, W); returns (F, B), which
+        hold the result once poll() has reported the request."""
+        import torch
+        dt = storage_dtype(self.params)
+        if I.dim() != 3 or I.shape[0] != 3:
+            raise ValueError("I must be (3, H, W)")
+        _, H, W = I.shape
+        if F is None:
+            F = torch.empty((3, H, W), dtype=dt, device=I.device)
+        if B is None:
+            B = torch.empty((3, H, W), dtype=dt, device=I.device)
+        for name, t, shp in (("I", I, (3, H, W)), ("alpha", alpha, (H, W)), ("F", F, (3, H, W)),
+                             ("B", B, (3, H, W))):
+            if tuple(t.shape) != shp or t.dtype != dt or not t.is_cuda or not t.is_contiguous():
+                raise ValueError(f"{name} must be a contiguous CUDA tensor {shp} of dtype {dt}")
+        self.submit_ptrs(rid, I.data_ptr(), alpha.data_ptr(), W, H, F.data_ptr(), B.data_ptr())
+        self._held[rid] = (I, alpha, F, B)
+        return F, B
+
+    def submit_ptrs(self, rid: int, I: int, alpha: int, W: int, H: int, F: int, B: int):
+        """Raw form: device addresses the caller keeps alive until the request completes."""
+        _check(_lib().fge_server_submit(self._h, rid, I, alpha, W, H, F, B), "fge_server_submit")
+
+    def poll(self, cap: int = 4096):
+        """Completed requests since the last poll: a list of ServerResult records."""
+        buf = (ServerResult * cap)()
+        n = _lib().fge_server_poll(self._h, buf, cap)
+        if n < 0:
+            raise FgeError(n, "fge_server_poll")
+        out = [buf[i] for i in range(n)]
+        for r in out:
+            self._held.pop(r.id, None)
+        return out
+
+    def drain(self):
+        _check(_lib().fge_server_drain(self._h), "fge_server_drain")
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(_lib().fge_server_get_stats(self._h, ctypes.byref(st)), "fge_server_get_stats")
+        return {k: getattr(st, k) for k, _ in ServerStats._fields_ if k != "reserved0"}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib().fge_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -251,3 +251,62 @@ def serving_requests(n: int = 2000, rate_per_s: float = 100.0, seed: int = 5,
 def request_image(req: Request) -> Sample:
     """Image of a serving request: smooth generator with seed 5000 + request id."""
     return smooth(req.W, req.H, seed=5000 + req.rid)
+
+
+# --- the smooth generator evaluated with torch on a device -------------------------------------
+
+def _sinusoid_params(rng: np.random.Generator, terms: int = 8):
+    """The draws of one _sinusoid_field call, in the same order."""
+    out = []
+    for _ in range(terms):
+        fx, fy = rng.uniform(-3.0, 3.0, size=2)
+        amp = rng.uniform(0.5, 1.0)
+        phi = rng.uniform(0.0, 2.0 * math.pi)
+        out.append((fx, fy, amp, phi))
+    return out
+
+
+def smooth_device(W: int, H: int, seed: int, device, dtype=None, out_I=None, out_alpha=None,
+                  noise: float = NOISE_SIGMA, return_fields: bool = False):
+    """``smooth`` evaluated with torch in float32 on `device` (for workloads of thousands of
+    megapixels, which NumPy would take minutes to draw).  The sinusoid parameters come from the
+    same PCG64(seed) draws as ``smooth``, so F, B and alpha agree with it to float32 rounding;
+    the noise is drawn from torch's generator seeded with `seed` (a different stream).  Writes
+    I (3, H, W) and alpha (H, W), converted to `dtype`, into out_I / out_alpha when given."""
+    import torch
+    dtype = dtype or torch.float32
+    rng = np.random.Generator(np.random.PCG64(seed))
+    x = torch.arange(W, device=device, dtype=torch.float32)
+    y = torch.arange(H, device=device, dtype=torch.float32)
+
+    def field(params):
+        fx, fy, amp, phi = (torch.tensor(v, device=device, dtype=torch.float32)
+                            for v in zip(*params))
+        ax = 2.0 * math.pi * fx[:, None] * x[None, :] / W + phi[:, None]       # (terms, W)
+        by = 2.0 * math.pi * fy[:, None] * y[None, :] / H                      # (terms, H)
+        left = torch.cat([amp[:, None] * torch.cos(by), amp[:, None] * torch.sin(by)]).T
+        right = torch.cat([torch.sin(ax), torch.cos(ax)])
+        acc = left @ right
+        lo, hi = acc.min(), acc.max()
+        return 0.05 + 0.9 * (acc - lo) / torch.clamp(hi - lo, min=1e-12)
+
+    F = torch.stack([field(_sinusoid_params(rng)) for _ in range(3)])
+    B = torch.stack([field(_sinusoid_params(rng)) for _ in range(3)])
+    R = 0.3 * min(W, H)
+    r = torch.sqrt((x[None, :] - (W - 1) / 2.0) ** 2 + (y[:, None] - (H - 1) / 2.0) ** 2)
+    alpha = torch.clamp(0.5 + (R - r) / 12.0, 0.0, 1.0)
+    I = alpha[None] * F + (1.0 - alpha[None]) * B
+    if noise > 0:
+        gen = torch.Generator(device=device)
+        gen.manual_seed(seed)
+        I = I + noise * torch.randn(I.shape, generator=gen, device=device, dtype=torch.float32)
+    I = torch.clamp(I, 0.0, 1.0)
+    if out_I is None:
+        out_I = torch.empty((3, H, W), dtype=dtype, device=device)
+    if out_alpha is None:
+        out_alpha = torch.empty((H, W), dtype=dtype, device=device)
+    out_I.copy_(I)
+    out_alpha.copy_(alpha)
+    if return_fields:
+        return out_I, out_alpha, F, B
+    return out_I, out_alpha

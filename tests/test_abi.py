@@ -44,7 +44,7 @@ def test_params_layout_and_defaults(fge):
     assert abs(p.omega - 0.1) < 1e-7 and abs(p.eps_r - 5e-3) < 1e-9
     assert (p.small_size, p.iters_small, p.iters_big) == (32, 10, 2)
     assert (p.storage, p.order, p.kernel, p.strip_rows, p.coarse_max_px, p.tile_max_px) == (0,) * 6
-    assert fge.load().fge_version() == 2
+    assert fge.load().fge_version() == 3
 
 
 def test_plan_matches_golden(fge):
@@ -165,3 +165,46 @@ def test_batch_argument_errors(fge):
     null = (ctypes.c_void_p * 2)()
     assert lib.fge_batch_run(b._h, null, null, null, null, None, 0, None) == fge.FGE_EINVAL
     b.close()
+
+
+def test_server_host_functions(fge):
+    """Server configuration, footprints and argument errors (no device call is reached)."""
+    assert ctypes.sizeof(fge.ServerConfig) == 32
+    assert ctypes.sizeof(fge.ServerResult) == 48
+    assert ctypes.sizeof(fge.ServerStats) == 80
+    c = fge.server_config()
+    assert (c.size, c.max_active, c.pipeline_depth, c.budget_bytes, c.tick_table_bytes) == \
+        (32, 1024, 2, 0, 16 << 20)
+    assert fge.server_reserved_bytes(c) == 2 * (16 << 20)
+    assert fge.server_reserved_bytes(fge.server_config(pipeline_depth=3)) == 3 * (16 << 20)
+    p16 = fge.default_params(storage=fge.F16)
+    for (W, H) in ((4096, 3072), (300, 7), (1, 1), (1920, 1080)):
+        ws = fge.workspace_bytes(W, H, p16)
+        assert fge.server_request_bytes(W, H, p16) == 20 * W * H + (ws + 255) // 256 * 256
+        assert fge.server_request_bytes(W, H) == 40 * W * H + \
+            (fge.workspace_bytes(W, H) + 255) // 256 * 256
+    assert fge.server_request_bytes(0, 5) == 0
+    lib = fge.load()
+    h = ctypes.c_void_p()
+    big = 1 << 30
+
+    def create(p=None, cfg=None, arena=0x100000, nbytes=big, stream=0x10):
+        return lib.fge_server_create(ctypes.byref(p) if p else None,
+                                     ctypes.byref(cfg) if cfg else None, arena, nbytes, stream,
+                                     ctypes.byref(h))
+
+    assert create(arena=None) == fge.FGE_EINVAL
+    assert create(stream=None) == fge.FGE_EINVAL
+    assert create(arena=0x100010) == fge.FGE_EINVAL
+    assert create(nbytes=32 << 20) == fge.FGE_EWORKSPACE
+    assert create(cfg=fge.server_config(pipeline_depth=9)) == fge.FGE_EINVAL
+    assert create(cfg=fge.server_config(max_active=-1)) == fge.FGE_EINVAL
+    assert create(cfg=fge.server_config(tick_table_bytes=1024)) == fge.FGE_EINVAL
+    bad = fge.server_config()
+    bad.size = 8
+    assert create(cfg=bad) == fge.FGE_EINVAL
+    assert create(p=fge.default_params(kernel=fge.KERNEL_NAIVE)) == fge.FGE_EUNSUPPORTED
+    assert create(p=fge.default_params(coarse_max_px=-1)) == fge.FGE_EUNSUPPORTED
+    assert create(p=fge.default_params(eps_r=0.0)) == fge.FGE_EINVAL
+    assert not h.value
+    assert fge.load().fge_status_string(fge.FGE_EBUDGET).startswith(b"FGE_EBUDGET")
