@@ -175,6 +175,44 @@ fge_status fge_estimate_foreground_batch(int32_t n, const void *const *I, const 
                                          void *const *F, void *const *B, void *workspace,
                                          size_t workspace_bytes, void *stream);
 
+/* ---- autotuner ------------------------------------------------------------------------- */
+
+/* The autotuner times candidate execution settings of one workload on the device and returns
+ * the fastest as a full fge_params (the caller's other fields kept).  It searches the two
+ * settings that change how the work is cut, never what is computed: strip_rows (the streaming
+ * kernel's strip height, i.e. how many output rows share the halo of the two fused sweeps; 0 is
+ * the automatic choice) over {0, 16, 24, 32, 48, 64, 96}, and tile_max_px (the largest level on
+ * the LDS tile kernel) over {0 (2^18), 2^16, 2^20}: fge_tune_candidates() settings.  Each runs
+ * once untimed, then `reps` times (0 = 3) between two events on `stream`; the call blocks until
+ * the search is done.  F and B hold the last candidate's result (all candidates agree to the
+ * parity tolerance).  entries[k] (k < max_entries) receives each candidate's strip_rows,
+ * tile_max_px, mean milliseconds and status; *n_entries the number of candidates run.  The
+ * workspace must hold fge_tune_workspace_bytes (the largest of the candidates' needs).  Callers
+ * keep the result (e.g. keyed by device, sizes and storage) and pass it to later calls. */
+typedef struct fge_tune_entry {
+    int32_t strip_rows;
+    int32_t tile_max_px;
+    float ms;
+    int32_t status;
+} fge_tune_entry;
+
+int32_t fge_tune_candidates(void);
+size_t fge_tune_workspace_bytes(int32_t W, int32_t H, const fge_params *p);
+fge_status fge_autotune(const void *I, const void *alpha, int32_t W, int32_t H, const fge_params *p,
+                        void *F, void *B, void *workspace, size_t workspace_bytes, void *stream,
+                        int32_t reps, fge_params *best, fge_tune_entry *entries,
+                        int32_t max_entries, int32_t *n_entries);
+
+/* The same search for a batch: each candidate is a batch plan (fge_batch_create) run with
+ * fge_batch_run.  The workspace must hold fge_batch_tune_workspace_bytes. */
+size_t fge_batch_tune_workspace_bytes(int32_t n, const int32_t *W, const int32_t *H,
+                                      const fge_params *p);
+fge_status fge_batch_autotune(int32_t n, const void *const *I, const void *const *alpha,
+                              const int32_t *W, const int32_t *H, const fge_params *p,
+                              void *const *F, void *const *B, void *workspace,
+                              size_t workspace_bytes, void *stream, int32_t reps, fge_params *best,
+                              fge_tune_entry *entries, int32_t max_entries, int32_t *n_entries);
+
 /* ---- serving: continuous batching of requests that arrive over time -------------------- */
 
 /* A server runs requests (one image each, Algorithm 1 as fge_estimate_foreground runs it, so a

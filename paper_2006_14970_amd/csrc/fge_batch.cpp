@@ -31,6 +31,7 @@ struct Launch {
     size_t desc_off = 0, item_off = 0;     // byte offsets in the table region
     int nitems = 0;
     int counter = 0;
+    int rows = 0;        // streaming strip height (0: each level's automatic height)
 };
 
 }  // namespace
@@ -103,7 +104,7 @@ void fill_tables(const fge_batch &b, char *tab, char *ws, const void *const *I,
                 units = fge::tile_units(td[d]);
             } else {
                 auto *fd = reinterpret_cast<fge::FineArgs *>(tab + L.desc_off);
-                fge::make_fine_args(io, b.prm.strip_rows, &fd[d]);
+                fge::make_fine_args(io, L.rows, &fd[d]);
                 units = fge::fine_units(fd[d]);
             }
             for (int u = 0; u < units; ++u) items[m++] = fge::WorkItem{static_cast<int>(d), u};
@@ -236,6 +237,18 @@ fge_status fge_batch_create(int32_t n, const int32_t *W, const int32_t *H, const
     }
     int counter = 0;
     for (Launch &L : b->launches) {
+        if (L.kind == fge::kKindStream) {
+            if (prm.strip_rows > 0) {
+                L.rows = prm.strip_rows;
+            } else {
+                std::vector<int> ws, hs;
+                for (const auto &iv : L.lv) {
+                    ws.push_back(b->plans[iv.first].lv[iv.second].w);
+                    hs.push_back(b->plans[iv.first].lv[iv.second].h);
+                }
+                L.rows = fge::launch_strip_rows(ws.data(), hs.data(), static_cast<int>(ws.size()));
+            }
+        }
         L.desc_off = t;
         const size_t dsz = L.kind == fge::kKindTile ? sizeof(fge::TileArgs) : sizeof(fge::FineArgs);
         t = align256(t + L.lv.size() * dsz);
@@ -252,7 +265,7 @@ fge_status fge_batch_create(int32_t n, const int32_t *W, const int32_t *H, const
                 units += fge::tile_units(a);
             } else {
                 fge::FineArgs a;
-                fge::make_fine_args(io, prm.strip_rows, &a);
+                fge::make_fine_args(io, L.rows, &a);
                 units += fge::fine_units(a);
             }
         }

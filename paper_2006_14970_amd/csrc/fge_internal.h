@@ -158,6 +158,9 @@ struct WorkItem {
 void make_fine_args(const LevelIO &io, int strip_rows, FineArgs *a);
 void make_tile_args(const LevelIO &io, TileArgs *a);
 int fine_units(const FineArgs &a);
+// Strip height for one batched streaming launch over levels of sizes w[k] x h[k]; 0 = none
+// fits (too little work in the launch: each level takes its own automatic height).
+int launch_strip_rows(const int *w, const int *h, int n);
 int tile_units(const TileArgs &a);
 void make_coarse_args(const Plan &plan, const LevelSrc &src, void *Fo, void *Bo, float omega,
                       float eps, CoarseArgs *a);

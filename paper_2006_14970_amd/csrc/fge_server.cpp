@@ -144,8 +144,10 @@ size_t footprint(const fge::Plan &pl) {
 }
 
 // Table bytes one tick needs for this request at its largest step (its first tick, coarse block
-// plus first fine level, or a later fine level), alignment included.
+// plus first fine level, or a later fine level), alignment included.  Strip counts are taken at
+// the lowest strip height a tick can use (8 rows), an upper bound for every height.
 size_t max_tick_bytes(const fge::Plan &pl, int strip_rows) {
+    if (strip_rows <= 0) strip_rows = 8;
     size_t worst = 0;
     for (int j = pl.nc; j < pl.n; ++j) {
         size_t b = pl.kind[j] == fge::kKindTile
@@ -276,7 +278,20 @@ fge_status enqueue_tick(fge_server *s) {
     const int si = s->free_slots.back();
     Slot &sl = s->slots[si];
     const size_t cap = s->cfg.tick_table_bytes;
-    const int strip_rows = s->prm.strip_rows;
+    // Strip height of this tick's streaming launch: the caller's, else one for all the streaming
+    // levels the admitted requests run next.
+    int strip_rows = s->prm.strip_rows;
+    if (strip_rows <= 0) {
+        std::vector<int> ws, hs;
+        for (Request *r : s->active) {
+            const int j = r->next < 0 ? r->plan.nc : r->next;
+            if (j < r->plan.n && r->plan.kind[j] == fge::kKindStream) {
+                ws.push_back(r->plan.lv[j].w);
+                hs.push_back(r->plan.lv[j].h);
+            }
+        }
+        strip_rows = fge::launch_strip_rows(ws.data(), hs.data(), static_cast<int>(ws.size()));
+    }
 
     // Select the requests that fit the slot's tables, in admission order.
     std::vector<Request *> fresh;      // run the gather pre-pass and the coarse block

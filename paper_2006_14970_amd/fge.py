@@ -48,6 +48,15 @@ class Params(ctypes.Structure):
     ]
 
 
+class TuneEntry(ctypes.Structure):
+    _fields_ = [
+        ("strip_rows", ctypes.c_int32),
+        ("tile_max_px", ctypes.c_int32),
+        ("ms", ctypes.c_float),
+        ("status", ctypes.c_int32),
+    ]
+
+
 class ServerConfig(ctypes.Structure):
     _fields_ = [
         ("size", ctypes.c_uint32),
@@ -144,6 +153,18 @@ def _lib():
     lib.fge_profile_start.restype = ctypes.c_int
     lib.fge_profile_stop.argtypes = [ctypes.POINTER(ctypes.c_double), ip, i32]
     lib.fge_profile_stop.restype = ctypes.c_int
+    tp = ctypes.POINTER(TuneEntry)
+    lib.fge_tune_candidates.argtypes = []
+    lib.fge_tune_candidates.restype = i32
+    lib.fge_tune_workspace_bytes.argtypes = [i32, i32, pp]
+    lib.fge_tune_workspace_bytes.restype = sz
+    lib.fge_autotune.argtypes = [vp, vp, i32, i32, pp, vp, vp, vp, sz, vp, i32, pp, tp, i32, ip]
+    lib.fge_autotune.restype = ctypes.c_int
+    lib.fge_batch_tune_workspace_bytes.argtypes = [i32, ip, ip, pp]
+    lib.fge_batch_tune_workspace_bytes.restype = sz
+    lib.fge_batch_autotune.argtypes = [i32, vpp, vpp, ip, ip, pp, vpp, vpp, vp, sz, vp, i32, pp,
+                                       tp, i32, ip]
+    lib.fge_batch_autotune.restype = ctypes.c_int
     cp = ctypes.POINTER(ServerConfig)
     lib.fge_server_default_config.argtypes = [cp]
     lib.fge_server_default_config.restype = None
@@ -464,3 +485,114 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+# ---- autotuner ---------------------------------------------------------------------------------
+
+def _tune_key(kind: str, params: Params, sizes) -> str:
+    import hashlib
+    import torch
+    fields = {k: getattr(params, k) for k, _ in Params._fields_
+              if k not in ("strip_rows", "tile_max_px")}
+    h = hashlib.sha1(repr((kind, sorted(fields.items()), list(sizes))).encode()).hexdigest()[:16]
+    return f"{torch.cuda.get_device_name()}|{kind}|{h}"
+
+
+def _cache_get(cache_path, key):
+    import json
+    if not cache_path or not os.path.exists(cache_path):
+        return None
+    with open(cache_path) as f:
+        return json.load(f).get(key)
+
+
+def _cache_put(cache_path, key, value):
+    import json
+    if not cache_path:
+        return
+    data = {}
+    if os.path.exists(cache_path):
+        with open(cache_path) as f:
+            data = json.load(f)
+    data[key] = value
+    tmp = cache_path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+    os.replace(tmp, cache_path)
+
+
+def _tuned(params: Params, strip_rows: int, tile_max_px: int) -> Params:
+    q = Params()
+    ctypes.pointer(q)[0] = params
+    q.strip_rows = strip_rows
+    q.tile_max_px = tile_max_px
+    return q
+
+
+def _entries(buf, n):
+    return [{"strip_rows": buf[i].strip_rows, "tile_max_px": buf[i].tile_max_px,
+             "ms": buf[i].ms, "status": buf[i].status} for i in range(n)]
+
+
+def autotune(I, alpha, params: Params | None = None, reps: int = 3, stream=None,
+             cache_path: str | None = None):
+    """Search strip height and tile threshold for this image size on the device (fge_autotune).
+    Returns (best_params, entries); with `cache_path`, a JSON file keyed by device, parameters and
+    size answers repeated calls without running anything."""
+    import torch
+    p = params if params is not None else default_params()
+    _, H, W = I.shape
+    key = _tune_key("single", p, [(W, H)])
+    hit = _cache_get(cache_path, key)
+    if hit is not None:
+        return _tuned(p, hit["strip_rows"], hit["tile_max_px"]), hit.get("entries", [])
+    dt = storage_dtype(p)
+    F = torch.empty((3, H, W), dtype=dt, device=I.device)
+    B = torch.empty_like(F)
+    need = _lib().fge_tune_workspace_bytes(W, H, ctypes.byref(p))
+    ws = torch.empty(max(1, need), dtype=torch.uint8, device=I.device)
+    nc = _lib().fge_tune_candidates()
+    buf = (TuneEntry * nc)()
+    n = ctypes.c_int32()
+    best = Params()
+    _check(_lib().fge_autotune(I.data_ptr(), alpha.data_ptr(), W, H, ctypes.byref(p), F.data_ptr(),
+                               B.data_ptr(), ws.data_ptr(), ws.numel(), _stream_ptr(stream), reps,
+                               ctypes.byref(best), buf, nc, ctypes.byref(n)), "fge_autotune")
+    ent = _entries(buf, n.value)
+    _cache_put(cache_path, key, {"strip_rows": best.strip_rows, "tile_max_px": best.tile_max_px,
+                                 "entries": ent})
+    return best, ent
+
+
+def autotune_batch(sizes, Is, alphas, params: Params | None = None, reps: int = 3, stream=None,
+                   cache_path: str | None = None):
+    """The same search for a batch of sizes [(W, H), ...] (fge_batch_autotune)."""
+    import torch
+    p = params if params is not None else default_params()
+    sizes = [(int(w), int(h)) for w, h in sizes]
+    key = _tune_key("batch", p, sizes)
+    hit = _cache_get(cache_path, key)
+    if hit is not None:
+        return _tuned(p, hit["strip_rows"], hit["tile_max_px"]), hit.get("entries", [])
+    n = len(sizes)
+    W = (ctypes.c_int32 * n)(*[w for w, _ in sizes])
+    H = (ctypes.c_int32 * n)(*[h for _, h in sizes])
+    dt = storage_dtype(p)
+    Fs = [torch.empty((3, h, w), dtype=dt, device=Is[0].device) for w, h in sizes]
+    Bs = [torch.empty_like(f) for f in Fs]
+    need = _lib().fge_batch_tune_workspace_bytes(n, W, H, ctypes.byref(p))
+    if need == 0:
+        raise FgeError(FGE_EINVAL, "fge_batch_tune_workspace_bytes")
+    ws = torch.empty(need, dtype=torch.uint8, device=Is[0].device)
+    nc = _lib().fge_tune_candidates()
+    buf = (TuneEntry * nc)()
+    cnt = ctypes.c_int32()
+    best = Params()
+    _check(_lib().fge_batch_autotune(n, _ptr_array(Is), _ptr_array(alphas), W, H, ctypes.byref(p),
+                                     _ptr_array(Fs), _ptr_array(Bs), ws.data_ptr(), ws.numel(),
+                                     _stream_ptr(stream), reps, ctypes.byref(best), buf, nc,
+                                     ctypes.byref(cnt)), "fge_batch_autotune")
+    ent = _entries(buf, cnt.value)
+    _cache_put(cache_path, key, {"strip_rows": best.strip_rows, "tile_max_px": best.tile_max_px,
+                                 "entries": ent})
+    return best, ent

@@ -208,3 +208,29 @@ def test_server_host_functions(fge):
     assert create(p=fge.default_params(eps_r=0.0)) == fge.FGE_EINVAL
     assert not h.value
     assert fge.load().fge_status_string(fge.FGE_EBUDGET).startswith(b"FGE_EBUDGET")
+
+
+def test_autotuner_host_side(fge):
+    lib = fge.load()
+    assert lib.fge_tune_candidates() == 21
+    for (W, H) in ((4096, 3072), (1024, 768), (300, 7)):
+        need = lib.fge_tune_workspace_bytes(W, H, None)
+        assert need >= fge.workspace_bytes(W, H)
+        for t in (0, 1 << 16, 1 << 20):
+            assert need >= fge.workspace_bytes(W, H, fge.default_params(tile_max_px=t))
+    sizes = [(300, 200), (1024, 768), (77, 900)]
+    W = (ctypes.c_int32 * 3)(*[w for w, _ in sizes])
+    H = (ctypes.c_int32 * 3)(*[h for _, h in sizes])
+    assert lib.fge_batch_tune_workspace_bytes(3, W, H, None) >= \
+        lib.fge_batch_workspace_bytes_for(3, W, H, None)
+    best = fge.Params()
+    # argument errors are reported before anything touches the device
+    assert lib.fge_autotune(None, 0x2000, 64, 64, None, 0x3000, 0x4000, None, 0, None, 3,
+                            ctypes.byref(best), None, 0, None) == fge.FGE_EINVAL
+    assert lib.fge_autotune(0x1000, 0x2000, 64, 64, None, 0x3000, 0x4000, None, 0, None, 3,
+                            None, None, 0, None) == fge.FGE_EINVAL
+    assert lib.fge_autotune(0x1000, 0x2000, 1024, 768, None, 0x3000, 0x4000, None, 0, None, 3,
+                            ctypes.byref(best), None, 0, None) == fge.FGE_EWORKSPACE
+    null = (ctypes.c_void_p * 3)()
+    assert lib.fge_batch_autotune(3, null, null, W, H, None, null, null, None, 0, None, 3,
+                                  ctypes.byref(best), None, 0, None) == fge.FGE_EWORKSPACE
