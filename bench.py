@@ -31,6 +31,25 @@ HBM_PEAK_GBS = 8000.0
 W_IMG, H_IMG = 4096, 3072
 
 
+def profiled_traffic(kernel):
+    """HBM bytes per launch of `kernel` at 4096x3072 from the committed rocprofv3 counter summary
+    (FETCH_SIZE and WRITE_SIZE runs, scaled by a plain copy's readings), or None when the kernel
+    source has changed since the counters were taken."""
+    import hashlib
+    root = os.path.dirname(os.path.abspath(__file__))
+    path = os.path.join(root, "profiles", "fine_kernel_4096x3072_hbm_bytes.txt")
+    src = os.path.join(root, "paper_2006_14970_amd", "csrc", "fge_kernels.hip")
+    if not os.path.exists(path):
+        return None
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    for line in open(path):
+        f = line.split()
+        if len(f) == 5 and f[0] == "TRAFFIC" and f[1] == kernel and f[2] == "4096x3072":
+            if f[4] == f"sha={sha}":
+                return int(f[3].split("=")[1])
+    return None
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -350,6 +369,7 @@ def main():
 
     def summary(r, elem):
         lb = level_bytes(plan.levels, elem)
+        traffic = profiled_traffic("fge::fine_kernel<float>" if elem == 4 else "fge::fine_kernel<_Float16>")
         fin_ms = r["level_ms"][0]
         achieved = lb[-1] / (fin_ms * 1e-3) / 1e9
         return {
@@ -359,7 +379,7 @@ def main():
                            "p99": float(np.percentile(r["lat_ms"], 99))},
             "max_abs_vs_oracle": r["max_abs_vs_oracle"],
             "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                         "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                          "kernel": "fine_kernel, finest level 4096x3072",
                          "kernel_ms": fin_ms, "algorithmic_bytes": lb[-1]},
             "level_ms_finest_first": [round(x, 5) if x is not None else None

@@ -39,11 +39,11 @@ struct LaunchTimer {
         if (p.on && p.used < p.recs.size()) {
             rec = &p.recs[p.used++];
             rec->level = level_from_finest;
-            hipEventRecord(rec->start, s);
+            (void)hipEventRecord(rec->start, s);
         }
     }
     ~LaunchTimer() {
-        if (rec) hipEventRecord(rec->stop, s);
+        if (rec) (void)hipEventRecord(rec->stop, s);
     }
 };
 
@@ -172,8 +172,8 @@ fge_status fge_profile_start(int32_t capacity) {
     Profiler &p = profiler();
     std::lock_guard<std::mutex> g(p.mu);
     for (auto &r : p.recs) {
-        hipEventDestroy(r.start);
-        hipEventDestroy(r.stop);
+        (void)hipEventDestroy(r.start);
+        (void)hipEventDestroy(r.stop);
     }
     p.recs.clear();
     p.used = 0;
@@ -209,8 +209,8 @@ fge_status fge_profile_stop(double *level_ms, int32_t *level_launches, int32_t m
         }
     }
     for (auto &r : p.recs) {
-        hipEventDestroy(r.start);
-        hipEventDestroy(r.stop);
+        (void)hipEventDestroy(r.start);
+        (void)hipEventDestroy(r.stop);
     }
     p.recs.clear();
     p.used = 0;

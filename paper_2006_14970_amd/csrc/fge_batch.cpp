@@ -288,13 +288,13 @@ fge_status fge_batch_create(int32_t n, const int32_t *W, const int32_t *H, const
 void fge_batch_destroy(fge_batch *b) {
     if (!b) return;
     if (b->staged) {
-        if (b->staged_pending) hipEventSynchronize(b->staged);
-        hipEventDestroy(b->staged);
+        if (b->staged_pending) (void)hipEventSynchronize(b->staged);
+        (void)hipEventDestroy(b->staged);
     }
-    if (b->exec) hipGraphExecDestroy(b->exec);
-    if (b->graph) hipGraphDestroy(b->graph);
-    if (b->staging) hipHostFree(b->staging);
-    if (b->graph_staging) hipHostFree(b->graph_staging);
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->staging) (void)hipHostFree(b->staging);
+    if (b->graph_staging) (void)hipHostFree(b->graph_staging);
     delete b;
 }
 
@@ -334,11 +334,11 @@ fge_status fge_batch_capture(fge_batch *b, const void *const *I, const void *con
     const fge_status st = check_ptrs(*b, I, alpha, F, B, workspace, workspace_bytes);
     if (st != FGE_OK) return st;
     if (b->exec) {
-        hipGraphExecDestroy(b->exec);
+        (void)hipGraphExecDestroy(b->exec);
         b->exec = nullptr;
     }
     if (b->graph) {
-        hipGraphDestroy(b->graph);
+        (void)hipGraphDestroy(b->graph);
         b->graph = nullptr;
     }
     if (!b->graph_staging &&
@@ -351,7 +351,7 @@ fge_status fge_batch_capture(fge_batch *b, const void *const *I, const void *con
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(s, &g);
     if (est != FGE_OK || e != hipSuccess || !g) {
-        if (g) hipGraphDestroy(g);
+        if (g) (void)hipGraphDestroy(g);
         return est != FGE_OK ? est : FGE_EHIP;
     }
     b->graph = g;

@@ -471,7 +471,7 @@ void fail_all(fge_server *s, int err) {
         out.push_back(res);
         delete r;
     };
-    hipStreamSynchronize(s->stream);
+    (void)hipStreamSynchronize(s->stream);
     for (int si : s->inflight) {
         for (Request *r : s->slots[si].finishing) fail(r);
         s->slots[si].finishing.clear();
@@ -492,7 +492,12 @@ void fail_all(fge_server *s, int err) {
 }
 
 void worker_main(fge_server *s) {
-    hipSetDevice(s->device);
+    if (hipSetDevice(s->device) != hipSuccess) {
+        fail_all(s, FGE_EHIP);
+        std::unique_lock<std::mutex> g(s->mu);
+        s->cv_work.wait(g, [&] { return s->stop; });
+        return;
+    }
     for (;;) {
         {
             std::lock_guard<std::mutex> g(s->mu);
@@ -614,8 +619,8 @@ fge_status fge_server_create(const fge_params *p, const fge_server_config *c, vo
     }
     // Time origin: the start event on the idle stream, and the host clock right after it.
     ok = ok && hipStreamSynchronize(s->stream) == hipSuccess &&
-         hipEventRecord(s->start_ev, s->stream) == hipSuccess &&
-         hipEventSynchronize(s->start_ev) == hipSuccess;
+         (void)hipEventRecord(s->start_ev, s->stream) == hipSuccess &&
+         (void)hipEventSynchronize(s->start_ev) == hipSuccess;
     if (!ok) {
         fge_server_destroy(s);
         return FGE_EHIP;
@@ -702,10 +707,10 @@ void fge_server_destroy(fge_server *s) {
         s->worker.join();
     }
     for (Slot &sl : s->slots) {
-        if (sl.done) hipEventDestroy(sl.done);
-        if (sl.staging) hipHostFree(sl.staging);
+        if (sl.done) (void)hipEventDestroy(sl.done);
+        if (sl.staging) (void)hipHostFree(sl.staging);
     }
-    if (s->start_ev) hipEventDestroy(s->start_ev);
+    if (s->start_ev) (void)hipEventDestroy(s->start_ev);
     delete s;
 }
 

@@ -58,7 +58,7 @@ fge_status search(const fge_params &base, int reps, void *stream, Run run_with, 
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
-        if (e0) hipEventDestroy(e0);
+        if (e0) (void)hipEventDestroy(e0);
         return FGE_EHIP;
     }
     float best_ms = -1.0f;
@@ -81,8 +81,8 @@ fge_status search(const fge_params &base, int reps, void *stream, Run run_with, 
         }
     }
     if (n_entries) *n_entries = k;
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     if (result == FGE_OK && best_ms < 0.0f) result = FGE_EUNSUPPORTED;
     return result;
 }
