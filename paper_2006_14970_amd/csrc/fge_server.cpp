@@ -619,8 +619,8 @@ fge_status fge_server_create(const fge_params *p, const fge_server_config *c, vo
     }
     // Time origin: the start event on the idle stream, and the host clock right after it.
     ok = ok && hipStreamSynchronize(s->stream) == hipSuccess &&
-         (void)hipEventRecord(s->start_ev, s->stream) == hipSuccess &&
-         (void)hipEventSynchronize(s->start_ev) == hipSuccess;
+         hipEventRecord(s->start_ev, s->stream) == hipSuccess &&
+         hipEventSynchronize(s->start_ev) == hipSuccess;
     if (!ok) {
         fge_server_destroy(s);
         return FGE_EHIP;
