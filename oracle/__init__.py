@@ -68,6 +68,11 @@ def _load():
     lib.fgo_ml.restype = i32
     lib.fgo_energy.argtypes = [dp, dp, dp, dp, i32, i32, f64, f64]
     lib.fgo_energy.restype = f64
+    ip = ctypes.POINTER(ctypes.c_int)
+    lib.fgo_ml_schedule.argtypes = [dp, dp, i32, i32, f64, f64, i32, ip, dp, dp]
+    lib.fgo_ml_schedule.restype = i32
+    lib.fgo_ml_converge.argtypes = [dp, dp, i32, i32, f64, f64, i32, f64, i32, ip, dp, dp]
+    lib.fgo_ml_converge.restype = i32
     _lib = lib
     return lib
 
@@ -156,3 +161,36 @@ def energy(F: np.ndarray, B: np.ndarray, I: np.ndarray, alpha: np.ndarray, omega
     F, B, I, a = _f64c(F), _f64c(B), _f64c(I), _f64c(alpha)
     _, h, w = I.shape
     return _load().fgo_energy(_ptr(F), _ptr(B), _ptr(I), _ptr(a), w, h, float(omega), float(eps))
+
+
+def ml_schedule(I: np.ndarray, alpha: np.ndarray, sweeps, omega: float = 0.1, eps: float = 5e-3,
+                order: str = "redblack") -> tuple[np.ndarray, np.ndarray]:
+    """Algorithm 1 with sweeps[l-1] sweeps at level l (replays a given schedule)."""
+    I = _f64c(I)
+    a = _f64c(alpha)
+    _, H, W = I.shape
+    n = num_levels(W, H)
+    sw = (ctypes.c_int * n)(*[int(k) for k in sweeps])
+    if len(sweeps) != n:
+        raise ValueError(f"{n} levels, {len(sweeps)} sweep counts")
+    F = np.empty((3, H, W), dtype=np.float64)
+    B = np.empty((3, H, W), dtype=np.float64)
+    _load().fgo_ml_schedule(_ptr(I), _ptr(a), W, H, float(omega), float(eps), ORDERS[order], sw,
+                            _ptr(F), _ptr(B))
+    return F, B
+
+
+def ml_converge(I: np.ndarray, alpha: np.ndarray, tol: float, max_sweeps: int,
+                omega: float = 0.1, eps: float = 5e-3, order: str = "redblack"):
+    """Algorithm 1's "while not converged" form: per level, sweep until the level energy changes
+    by at most tol (relative) or max_sweeps sweeps.  Returns (F, B, sweeps per level)."""
+    I = _f64c(I)
+    a = _f64c(alpha)
+    _, H, W = I.shape
+    n = num_levels(W, H)
+    sw = (ctypes.c_int * n)()
+    F = np.empty((3, H, W), dtype=np.float64)
+    B = np.empty((3, H, W), dtype=np.float64)
+    _load().fgo_ml_converge(_ptr(I), _ptr(a), W, H, float(omega), float(eps), ORDERS[order],
+                            float(tol), int(max_sweeps), sw, _ptr(F), _ptr(B))
+    return F, B, list(sw)

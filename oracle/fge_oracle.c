@@ -267,3 +267,97 @@ double fgo_energy(const double *F, const double *B, const double *I, const doubl
     }
     return e;
 }
+
+/*
+ * Algorithm 1 with a given number of sweeps per level: level l runs sweeps[l-1] sweeps (fgo_ml's
+ * fixed rule is the schedule 10 / 2).  Replays a schedule decided elsewhere.  Returns the number
+ * of levels.
+ */
+int fgo_ml_schedule(const double *I, const double *a, int W, int H, double omega, double eps,
+                    int order, const int *sweeps, double *F, double *B)
+{
+    const int n = fgo_num_levels(W, H);
+    int wp = 1, hp = 1;
+    double *Fp = (double *)calloc(3, sizeof(double));
+    double *Bp = (double *)calloc(3, sizeof(double));
+    for (int l = 1; l <= n; l++) {
+        int w = fgo_level_size(W, l, n);
+        int h = fgo_level_size(H, l, n);
+        size_t plane = (size_t)w * h;
+        double *Il = (double *)malloc(3 * plane * sizeof(double));
+        double *al = (double *)malloc(plane * sizeof(double));
+        double *Fl = (double *)malloc(3 * plane * sizeof(double));
+        double *Bl = (double *)malloc(3 * plane * sizeof(double));
+        fgo_resize_nearest(I, W, H, 3, Il, w, h);
+        fgo_resize_nearest(a, W, H, 1, al, w, h);
+        fgo_resize_nearest(Fp, wp, hp, 3, Fl, w, h);
+        fgo_resize_nearest(Bp, wp, hp, 3, Bl, w, h);
+        for (int it = 0; it < sweeps[l - 1]; it++)
+            fgo_sweep(Fl, Bl, Il, al, w, h, omega, eps, order);
+        free(Il);
+        free(al);
+        free(Fp);
+        free(Bp);
+        Fp = Fl;
+        Bp = Bl;
+        wp = w;
+        hp = h;
+    }
+    memcpy(F, Fp, 3 * (size_t)W * H * sizeof(double));
+    memcpy(B, Bp, 3 * (size_t)W * H * sizeof(double));
+    free(Fp);
+    free(Bp);
+    return n;
+}
+
+/*
+ * Algorithm 1's "while not converged" form: at every level, after the resize, sweep until the
+ * level's energy (fgo_energy of the level's F, B against its resized image and matte) changes by
+ * at most tol times its value before the sweep, or until max_sweeps sweeps have run; at least one
+ * sweep runs.  E before the first sweep is the energy of the resized start.  sweeps_out[l-1]
+ * receives the sweeps level l ran.  Returns the number of levels.
+ */
+int fgo_ml_converge(const double *I, const double *a, int W, int H, double omega, double eps,
+                    int order, double tol, int max_sweeps, int *sweeps_out, double *F, double *B)
+{
+    const int n = fgo_num_levels(W, H);
+    int wp = 1, hp = 1;
+    double *Fp = (double *)calloc(3, sizeof(double));
+    double *Bp = (double *)calloc(3, sizeof(double));
+    for (int l = 1; l <= n; l++) {
+        int w = fgo_level_size(W, l, n);
+        int h = fgo_level_size(H, l, n);
+        size_t plane = (size_t)w * h;
+        double *Il = (double *)malloc(3 * plane * sizeof(double));
+        double *al = (double *)malloc(plane * sizeof(double));
+        double *Fl = (double *)malloc(3 * plane * sizeof(double));
+        double *Bl = (double *)malloc(3 * plane * sizeof(double));
+        fgo_resize_nearest(I, W, H, 3, Il, w, h);
+        fgo_resize_nearest(a, W, H, 1, al, w, h);
+        fgo_resize_nearest(Fp, wp, hp, 3, Fl, w, h);
+        fgo_resize_nearest(Bp, wp, hp, 3, Bl, w, h);
+        double e_prev = fgo_energy(Fl, Bl, Il, al, w, h, omega, eps);
+        int k = 0;
+        for (;;) {
+            fgo_sweep(Fl, Bl, Il, al, w, h, omega, eps, order);
+            k++;
+            double e = fgo_energy(Fl, Bl, Il, al, w, h, omega, eps);
+            if (fabs(e_prev - e) <= tol * e_prev || k >= max_sweeps) break;
+            e_prev = e;
+        }
+        sweeps_out[l - 1] = k;
+        free(Il);
+        free(al);
+        free(Fp);
+        free(Bp);
+        Fp = Fl;
+        Bp = Bl;
+        wp = w;
+        hp = h;
+    }
+    memcpy(F, Fp, 3 * (size_t)W * H * sizeof(double));
+    memcpy(B, Bp, 3 * (size_t)W * H * sizeof(double));
+    free(Fp);
+    free(Bp);
+    return n;
+}

@@ -313,3 +313,68 @@ def test_orderings_reach_similar_energy(oracle_mod):
         F, B = oracle_mod.ml(s.I, s.alpha, order=order)
         e[order] = oracle_mod.energy(F, B, s.I, s.alpha)
     assert abs(e["raster"] - e["redblack"]) < 0.02 * e["raster"]
+
+
+# --- "while not converged": per-level schedules and the convergence loop ------------------
+
+@pytest.mark.parametrize("order", ["raster", "redblack", "jacobi"])
+@pytest.mark.parametrize("wh", [(1, 1), (5, 3), (40, 30), (70, 65)])
+def test_schedule_generalises_fixed_rule(oracle_mod, order, wh):
+    W, H = wh
+    rng = np.random.default_rng(W * 7 + H)
+    I = rng.uniform(0, 1, (3, H, W))
+    a = rng.uniform(0, 1, (H, W))
+    plan = [it for _, _, it in oracle_mod.level_plan(W, H)]
+    F, B = oracle_mod.ml(I, a, order=order)
+    F2, B2 = oracle_mod.ml_schedule(I, a, plan, order=order)
+    assert np.array_equal(F, F2) and np.array_equal(B, B2)
+
+
+@pytest.mark.parametrize("order", ["raster", "redblack", "jacobi"])
+def test_converge_reaches_direct_minimiser(oracle_mod, order):
+    """With a vanishing tolerance the last (full-resolution) level runs to the minimiser of the
+    global energy, which a sparse direct solve gives independently."""
+    w, h = 9, 7
+    I, a = _interior_problem(17, w, h)
+    Fd, Bd = bf.direct_minimiser(I, a, OMEGA, EPS)
+    assert Fd.min() > 0.01 and Fd.max() < 0.99 and Bd.min() > 0.01 and Bd.max() < 0.99
+    F, B, sw = oracle_mod.ml_converge(I, a, 1e-15, 20000, OMEGA, EPS, order)
+    assert len(sw) == oracle_mod.num_levels(w, h) and sw[-1] > 50
+    # the energy is quadratic in the distance to the minimiser, so an energy change of 1e-15
+    # (relative) leaves F, B about 1e-7 away from it
+    np.testing.assert_allclose(F, Fd, atol=1e-6)
+    np.testing.assert_allclose(B, Bd, atol=1e-6)
+
+
+@pytest.mark.parametrize("order", ["redblack", "jacobi"])
+def test_converge_stopping_rule(oracle_mod, order):
+    """The last level's sweep count is the first k with |E_(k-1) - E_k| <= tol E_(k-1), found here
+    by running the pinned single-level sweep and energy by hand from the level's start."""
+    from paper_2006_14970_amd import synth
+    s = synth.smooth(37, 29, seed=8)
+    tol = 1e-5
+    F, B, sw = oracle_mod.ml_converge(s.I, s.alpha, tol, 500, order=order)
+    F0, B0 = oracle_mod.ml_schedule(s.I, s.alpha, sw[:-1] + [0], order=order)   # level start
+    e_prev = oracle_mod.energy(F0, B0, s.I, s.alpha)
+    Fk, Bk, k = F0, B0, 0
+    while True:
+        Fk, Bk = oracle_mod.sweep(Fk, Bk, s.I, s.alpha, order=order)
+        k += 1
+        e = oracle_mod.energy(Fk, Bk, s.I, s.alpha)
+        if abs(e_prev - e) <= tol * e_prev or k >= 500:
+            break
+        e_prev = e
+    assert k == sw[-1]
+    assert np.array_equal(Fk, F) and np.array_equal(Bk, B)
+
+
+def test_converge_limits(oracle_mod):
+    from paper_2006_14970_amd import synth
+    s = synth.smooth(50, 40, seed=9)
+    n = oracle_mod.num_levels(50, 40)
+    _, _, sw = oracle_mod.ml_converge(s.I, s.alpha, 1e-12, 3)
+    assert sw == [3] * n                       # the cap
+    F, B, sw = oracle_mod.ml_converge(s.I, s.alpha, 1.0, 100)
+    assert sw == [1] * n                       # |dE| <= E always holds for a descent
+    F1, B1 = oracle_mod.ml_schedule(s.I, s.alpha, [1] * n)
+    assert np.array_equal(F, F1) and np.array_equal(B, B1)
