@@ -53,11 +53,15 @@ typedef enum fge_status {
     FGE_EBUDGET = -6        /* a request that can never fit a server's budget or arena */
 } fge_status;
 
-typedef enum fge_dtype { FGE_F32 = 0, FGE_F16 = 1 } fge_dtype;
+/* Element types.  F32 and F16 are storage types of the estimator; U8 (values 0..255 standing
+ * for [0, 1]) appears only in the layout conversions below. */
+typedef enum fge_dtype { FGE_F32 = 0, FGE_F16 = 1, FGE_U8 = 2 } fge_dtype;
 
-/* Sweep order on the device.  Only red-black is implemented; the paper's sequential raster
- * order exists in the CPU oracle only. */
-typedef enum fge_order { FGE_REDBLACK = 0 } fge_order;
+/* Sweep order on the device.  Red-black (pixels with (x + y) even, then odd, each in place) runs
+ * on every kernel.  Jacobi (every pixel from the previous sweep's values) runs on per-level
+ * kernels only (no coarse block, no fused levels; not in batches or the server).  The paper's
+ * sequential raster order exists in the CPU oracle only. */
+typedef enum fge_order { FGE_REDBLACK = 0, FGE_JACOBI = 1 } fge_order;
 
 /* Kernel family for the levels above the LDS-resident coarse block. */
 typedef enum fge_kernel {
@@ -126,6 +130,22 @@ fge_status fge_estimate_foreground(const void *I, const void *alpha, int32_t W, 
                                    const fge_params *p, void *F, void *B, void *workspace,
                                    size_t workspace_bytes, void *stream);
 
+/* Algorithm 1's level loop in its "while not converged" form: at every level, after the resize,
+ * sweep (in p->order) until the level's energy -- fge_energy's quadratic on the level's F, B
+ * against its nearest-resized image and matte -- changes by at most tol times its value before
+ * the sweep, or until max_sweeps sweeps (1..100000) have run; at least one sweep runs.  The
+ * energy is reduced and the decision taken on the device after every sweep: the call enqueues
+ * max_sweeps sweeps per level and returns at once, and the launches after convergence do nothing.
+ * tol < 0 runs the fixed counts of the iteration rule instead (max_sweeps ignored).  sweeps_out
+ * (DEVICE int array of >= n_levels entries, or NULL) receives the sweeps each level ran (in the
+ * tol >= 0 form).  Every level runs on per-level kernels (no coarse block, no fused levels), so
+ * this is a quality mode, not the fast path.  Workspace: fge_converge_workspace_bytes. */
+size_t fge_converge_workspace_bytes(int32_t W, int32_t H, const fge_params *p);
+fge_status fge_estimate_foreground_converge(const void *I, const void *alpha, int32_t W, int32_t H,
+                                            const fge_params *p, double tol, int32_t max_sweeps,
+                                            void *F, void *B, int32_t *sweeps_out, void *workspace,
+                                            size_t workspace_bytes, void *stream);
+
 /* ---- batches of images of different sizes ---------------------------------------------- */
 
 /* A batch plan: every image follows its own level plan (so its F and B are bit-identical to
@@ -174,6 +194,34 @@ fge_status fge_estimate_foreground_batch(int32_t n, const void *const *I, const 
                                          const int32_t *W, const int32_t *H, const fge_params *p,
                                          void *const *F, void *const *B, void *workspace,
                                          size_t workspace_bytes, void *stream);
+
+/* ---- reporting and layout ------------------------------------------------------------- */
+
+/* Energy of a result, reduced on the device in float64 (deterministic order):
+ *   E = sum_i sum_c (a_i F_i^c + (1 - a_i) B_i^c - I_i^c)^2
+ *     + sum over undirected in-bounds 4-neighbour edges {i,j}, each once, of
+ *       (eps_r + omega |a_i - a_j|) sum_c [(F_i^c - F_j^c)^2 + (B_i^c - B_j^c)^2],
+ * the quadratic whose per-pixel stationarity conditions are the systems of eq. 9 (eq. 3's local
+ * costs with each edge counted once), plus the compositing residual |aF + (1-a)B - I| (eq. 1) over
+ * the fractional pixels 0 < a < 1.  All buffers are device buffers in p->storage type (W x H
+ * planes as for fge_estimate_foreground); p supplies omega, eps_r and the storage type (NULL =
+ * defaults).  `out` is a DEVICE array of 6 doubles: E, the data term, the smoothness term, the mean
+ * and the max |residual| over fractional pixels, and their count.  The workspace (256-byte
+ * aligned) holds fge_energy_workspace_bytes(W, H) bytes of partial sums.  Asynchronous. */
+size_t fge_energy_workspace_bytes(int32_t W, int32_t H);
+fge_status fge_energy(const void *I, const void *alpha, const void *F, const void *B, int32_t W,
+                      int32_t H, const fge_params *p, double *out, void *workspace,
+                      size_t workspace_bytes, void *stream);
+
+/* Interleaved H x W x C images (C = 3: RGB, or 4: RGBA) to planar: 3 colour planes into `planes`
+ * and, for C = 4, the fourth channel into `alpha` (one plane).  Element types are fge_dtype
+ * values: U8 maps v to v / 255 (float32 division); a float maps to U8 as
+ * round-half-even(clamp(v, 0, 1) * 255); F32 -> F16 rounds to nearest even.  Device buffers. */
+fge_status fge_hwc_to_planar(const void *src, int32_t src_dtype, int32_t channels, int32_t W,
+                             int32_t H, void *planes, void *alpha, int32_t dst_dtype, void *stream);
+/* Planar 3 x H x W to interleaved H x W x 3, with the same conversions. */
+fge_status fge_planar_to_hwc(const void *planes, int32_t src_dtype, int32_t W, int32_t H,
+                             void *dst, int32_t dst_dtype, void *stream);
 
 /* ---- autotuner ------------------------------------------------------------------------- */
 

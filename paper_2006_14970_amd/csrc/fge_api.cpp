@@ -122,7 +122,9 @@ fge_status fge_plan(int32_t W, int32_t H, const fge_params *p, int32_t max_level
 size_t fge_workspace_bytes(int32_t W, int32_t H, const fge_params *p) {
     fge_params tmp;
     fge::Plan plan;
-    if (fge::make_plan(W, H, resolve(p, tmp), &plan) != FGE_OK) return 0;
+    const fge_params &prm = resolve(p, tmp);
+    if (fge::make_plan(W, H, prm, &plan) != FGE_OK) return 0;
+    if (prm.order == FGE_JACOBI) return fge::converge_workspace_bytes(W, H, prm);
     return plan.ws_bytes;
 }
 
@@ -135,6 +137,9 @@ fge_status fge_estimate_foreground(const void *I, const void *alpha, int32_t W, 
     const fge_status st = fge::make_plan(W, H, prm, &plan);
     if (st != FGE_OK) return st;
     if (!I || !alpha || !F || !B || F == B) return FGE_EINVAL;
+    if (prm.order == FGE_JACOBI)   // fixed counts on the per-level Jacobi kernels
+        return fge::estimate_converge(I, alpha, W, H, prm, -1.0, 0, F, B, nullptr, workspace,
+                                      workspace_bytes, stream);
     if (plan.ws_bytes > 0 && (!workspace || workspace_bytes < plan.ws_bytes)) return FGE_EWORKSPACE;
     if (workspace && (reinterpret_cast<uintptr_t>(workspace) & 255)) return FGE_EWORKSPACE;
 

@@ -1,0 +1,333 @@
+// The level loop of Algorithm 1 in its "while not converged" form, and the Jacobi sweep order,
+// on the device (C ABI in include/fge.h).
+//
+// Per level: resize F and B from the previous level (nearest), then sweep.  With a tolerance
+// tol >= 0 the level's energy (fge_energy's quadratic on the level's F, B against its resized
+// image and matte) is reduced on the device after every sweep and a one-thread check kernel
+// compares it with the energy before the sweep: when |E_prev - E| <= tol E_prev, or after
+// max_sweeps sweeps, it raises a stop flag that turns every later launch of the level into a
+// no-op (grid-stride kernels with capped grids, so a stopped launch retires quickly).  The host
+// enqueues max_sweeps guarded sweeps without waiting; the decision never leaves the device.
+// With tol < 0 every level runs the fixed counts of the iteration rule (10 / 2), unguarded.
+//
+// Orders: red-black (two half-sweeps in place, (x + y) even first) or Jacobi (every pixel from
+// the previous sweep's values: sweep into a temporary, copy back).  The per-pixel update is the
+// 2x2 solve of eq. 9 in the same Sherman-Morrison form as the other kernels.  A level sweeps on
+// float32 working buffers and its state is converted to the storage type once, when the level is
+// written (so binary16 storage rounds once per level, as on the fused path).
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "fge_internal.h"
+
+namespace fge {
+namespace {
+
+constexpr int kCvThreads = 256;
+constexpr int kCvBlocksMax = 4096;
+constexpr int kCvMaxSweeps = 100000;
+
+template <typename T>
+__device__ __forceinline__ float ldv(const T *p, size_t i) { return static_cast<float>(p[i]); }
+template <typename T>
+__device__ __forceinline__ void stv(T *p, size_t i, float v) { p[i] = static_cast<T>(v); }
+__device__ __forceinline__ float clamp_unit(float v) { return fminf(fmaxf(v, 0.0f), 1.0f); }
+__device__ __forceinline__ bool stopped(const int *stop) { return stop && *stop; }
+
+unsigned blocks_for(size_t n) {
+    const size_t b = (n + kCvThreads - 1) / kCvThreads;
+    return static_cast<unsigned>(b < static_cast<size_t>(kCvBlocksMax) ? b : kCvBlocksMax);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kCvThreads) void cv_upsample_kernel(const T *Fp, const T *Bp, int wp,
+                                                                 int hp, float *Fo, float *Bo, int w,
+                                                                 int h) {
+    const size_t n = static_cast<size_t>(w) * h, np = static_cast<size_t>(wp) * hp;
+    for (size_t p = static_cast<size_t>(blockIdx.x) * kCvThreads + threadIdx.x; p < n;
+         p += static_cast<size_t>(gridDim.x) * kCvThreads) {
+        const int y = static_cast<int>(p / w), x = static_cast<int>(p - static_cast<size_t>(y) * w);
+        const size_t q = static_cast<size_t>(y * hp / h) * wp + x * wp / w;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            stv(Fo, c * n + p, Fp ? ldv(Fp, c * np + q) : 0.0f);
+            stv(Bo, c * n + p, Bp ? ldv(Bp, c * np + q) : 0.0f);
+        }
+    }
+}
+
+// The update of pixel (x, y) of a w x h level from the state (F, B), with I and alpha read from
+// W x H through the nearest map.
+template <typename T>
+__device__ __forceinline__ void cv_solve(const T *I, const T *A, int W, int H, const float *F,
+                                         const float *B, int w, int h, int x, int y, float omega,
+                                         float eps, float fo[3], float bo[3]) {
+    const size_t n = static_cast<size_t>(w) * h, nI = static_cast<size_t>(W) * H;
+    auto alpha_at = [&](int xx, int yy) {
+        return ldv(A, static_cast<size_t>(yy * H / h) * W + xx * W / w);
+    };
+    const float a = alpha_at(x, y), b = 1.0f - a;
+    const int xs[4] = {x > 0 ? x - 1 : 0, x < w - 1 ? x + 1 : w - 1, x, x};
+    const int ys[4] = {y, y, y > 0 ? y - 1 : 0, y < h - 1 ? y + 1 : h - 1};
+    float s[4], S = 0.0f;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        s[j] = fmaf(omega, fabsf(a - alpha_at(xs[j], ys[j])), eps);
+        S += s[j];
+    }
+    const float iS = 1.0f / S;
+    const float k = 1.0f / (S + fmaf(a, a, b * b));
+    const size_t src = static_cast<size_t>(y * H / h) * W + x * W / w;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        float P = 0.0f, Q = 0.0f;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const size_t nj = c * n + static_cast<size_t>(ys[j]) * w + xs[j];
+            P = fmaf(s[j], ldv(F, nj), P);
+            Q = fmaf(s[j], ldv(B, nj), Q);
+        }
+        const float fb = P * iS, bb = Q * iS;
+        const float r = ldv(I, c * nI + src) - a * fb - b * bb;
+        fo[c] = clamp_unit(fmaf(a * k, r, fb));
+        bo[c] = clamp_unit(fmaf(b * k, r, bb));
+    }
+}
+
+// Red-black half-sweep in place: every pixel with (x + y) % 2 == colour.
+template <typename T>
+__global__ __launch_bounds__(kCvThreads) void cv_halfsweep_kernel(const T *I, const T *A, int W,
+                                                                  int H, float *F, float *B, int w,
+                                                                  int h,
+                                                                  int colour, float omega,
+                                                                  float eps, const int *stop) {
+    if (stopped(stop)) return;
+    const int pw = (w + 1) >> 1;
+    const size_t npairs = static_cast<size_t>(pw) * h, n = static_cast<size_t>(w) * h;
+    for (size_t q = static_cast<size_t>(blockIdx.x) * kCvThreads + threadIdx.x; q < npairs;
+         q += static_cast<size_t>(gridDim.x) * kCvThreads) {
+        const int y = static_cast<int>(q / pw);
+        const int x = 2 * static_cast<int>(q - static_cast<size_t>(y) * pw) + ((y + colour) & 1);
+        if (x >= w) continue;
+        float fo[3], bo[3];
+        cv_solve(I, A, W, H, F, B, w, h, x, y, omega, eps, fo, bo);
+        const size_t i = static_cast<size_t>(y) * w + x;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            stv(F, c * n + i, fo[c]);
+            stv(B, c * n + i, bo[c]);
+        }
+    }
+}
+
+// Jacobi sweep: every pixel from the previous state (F, B) into (Fo, Bo).
+template <typename T>
+__global__ __launch_bounds__(kCvThreads) void cv_jacobi_kernel(const T *I, const T *A, int W, int H,
+                                                               const float *F, const float *B,
+                                                               float *Fo, float *Bo, int w, int h,
+                                                               float omega,
+                                                               float eps, const int *stop) {
+    if (stopped(stop)) return;
+    const size_t n = static_cast<size_t>(w) * h;
+    for (size_t p = static_cast<size_t>(blockIdx.x) * kCvThreads + threadIdx.x; p < n;
+         p += static_cast<size_t>(gridDim.x) * kCvThreads) {
+        const int y = static_cast<int>(p / w), x = static_cast<int>(p - static_cast<size_t>(y) * w);
+        float fo[3], bo[3];
+        cv_solve(I, A, W, H, F, B, w, h, x, y, omega, eps, fo, bo);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            stv(Fo, c * n + p, fo[c]);
+            stv(Bo, c * n + p, bo[c]);
+        }
+    }
+}
+
+// Copy of the 3 planes of F and of B, converted to the destination type: back from the Jacobi
+// temporary (guarded), and the level's working state into its stored state (unguarded).
+template <typename TD>
+__global__ __launch_bounds__(kCvThreads) void cv_copy_kernel(const float *Fs, const float *Bs,
+                                                             TD *F, TD *B, size_t n,
+                                                             const int *stop) {
+    if (stopped(stop)) return;
+    for (size_t p = static_cast<size_t>(blockIdx.x) * kCvThreads + threadIdx.x; p < 3 * n;
+         p += static_cast<size_t>(gridDim.x) * kCvThreads) {
+        F[p] = static_cast<TD>(Fs[p]);
+        B[p] = static_cast<TD>(Bs[p]);
+    }
+}
+
+__global__ void cv_begin_kernel(int *stop, int *count) {
+    if (threadIdx.x == 0) {
+        stop[0] = 0;
+        count[0] = 0;
+    }
+}
+
+// After sweep k of a level (k = 0: the resized start): record the count and decide.
+__global__ void cv_check_kernel(const double *enow, double *eprev, int *stop, int *count,
+                                double tol, int k, int kmax) {
+    if (threadIdx.x != 0 || stop[0]) return;
+    const double e = enow[0];
+    if (k > 0) {
+        count[0] = k;
+        if (fabs(eprev[0] - e) <= tol * eprev[0] || k >= kmax) stop[0] = 1;
+    }
+    eprev[0] = e;
+}
+
+// Workspace: the naive plan's ping-pong level buffers (storage type), the float32 working state
+// and the float32 Jacobi temporary (6 planes at full size each), the energy partial sums, and a
+// small block of scalars.
+struct CvLayout {
+    size_t work = 0, temp = 0, part = 0, scal = 0, total = 0;
+};
+
+size_t a256(size_t v) { return (v + 255) & ~static_cast<size_t>(255); }
+
+CvLayout cv_layout(const Plan &pl, bool jacobi) {
+    CvLayout L;
+    size_t off = a256(pl.ws_bytes);
+    const size_t planes6 = a256(6 * static_cast<size_t>(pl.W) * pl.H * sizeof(float));
+    L.work = off;
+    off += planes6;
+    L.temp = off;
+    off += jacobi ? planes6 : 0;
+    L.part = off;
+    off += a256(static_cast<size_t>(energy_blocks(pl.W, pl.H)) * 5 * sizeof(double));
+    L.scal = off;
+    off += 256 + a256(kMaxLevels * sizeof(int));
+    L.total = off;
+    return L;
+}
+
+// The plan of the level loop: every level on per-level kernels (no coarse block, no fused levels).
+fge_status cv_plan(int W, int H, const fge_params &p, Plan *pl) {
+    fge_params q = p;
+    q.kernel = FGE_KERNEL_NAIVE;
+    q.coarse_max_px = -1;
+    return make_plan(W, H, q, pl);
+}
+
+template <typename T>
+fge_status cv_run(const Plan &pl, const fge_params &p, const void *Iv, const void *Av, void *Fv,
+                  void *Bv, double tol, int max_sweeps, int32_t *sweeps_out, char *ws,
+                  hipStream_t s) {
+    const bool conv = tol >= 0.0;
+    const bool jac = p.order == FGE_JACOBI;
+    const CvLayout L = cv_layout(pl, jac);
+    double *part = reinterpret_cast<double *>(ws + L.part);
+    double *enow = reinterpret_cast<double *>(ws + L.scal);          // 6 doubles
+    double *eprev = enow + 6;
+    int *stop = reinterpret_cast<int *>(ws + L.scal + 64);
+    int *counts = sweeps_out ? sweeps_out : reinterpret_cast<int *>(ws + L.scal + 256);
+    const T *I = static_cast<const T *>(Iv);
+    const T *A = static_cast<const T *>(Av);
+    for (int j = 0; j < pl.n; ++j) {
+        const LevelIO io = level_io(pl, ws, j, Iv, Av, Fv, Bv, p.omega, p.eps_r);
+        const int w = io.w, h = io.h;
+        const size_t n = static_cast<size_t>(w) * h;
+        float *Fo = reinterpret_cast<float *>(ws + L.work);   // working state of the level
+        float *Bo = Fo + 3 * n;
+        float *Ft = reinterpret_cast<float *>(ws + L.temp);
+        float *Bt = Ft + 3 * n;
+        hipLaunchKernelGGL(cv_upsample_kernel<T>, dim3(blocks_for(n)), dim3(kCvThreads), 0, s,
+                           static_cast<const T *>(io.Fp), static_cast<const T *>(io.Bp), io.wp,
+                           io.hp, Fo, Bo, w, h);
+        if (hipGetLastError() != hipSuccess) return FGE_EHIP;
+        const int kmax = conv ? max_sweeps : pl.lv[j].iters;
+        const int *guard = conv ? stop : nullptr;
+        if (conv) {
+            hipLaunchKernelGGL(cv_begin_kernel, dim3(1), dim3(64), 0, s, stop, counts + j);
+            if (launch_energy(Iv, Av, pl.W, pl.H, Fo, Bo, w, h, p.omega, p.eps_r, p.storage,
+                              FGE_F32, stop, part, enow, s))
+                return FGE_EHIP;
+            hipLaunchKernelGGL(cv_check_kernel, dim3(1), dim3(64), 0, s, enow, eprev, stop,
+                               counts + j, tol, 0, kmax);
+            if (hipGetLastError() != hipSuccess) return FGE_EHIP;
+        }
+        for (int k = 1; k <= kmax; ++k) {
+            if (jac) {
+                hipLaunchKernelGGL(cv_jacobi_kernel<T>, dim3(blocks_for(n)), dim3(kCvThreads), 0, s,
+                                   I, A, pl.W, pl.H, Fo, Bo, Ft, Bt, w, h, p.omega, p.eps_r, guard);
+                hipLaunchKernelGGL(cv_copy_kernel<float>, dim3(blocks_for(3 * n)), dim3(kCvThreads),
+                                   0, s, Ft, Bt, Fo, Bo, n, guard);
+            } else {
+                const size_t npairs = static_cast<size_t>((w + 1) >> 1) * h;
+                for (int colour = 0; colour < 2; ++colour)
+                    hipLaunchKernelGGL(cv_halfsweep_kernel<T>, dim3(blocks_for(npairs)),
+                                       dim3(kCvThreads), 0, s, I, A, pl.W, pl.H, Fo, Bo, w, h,
+                                       colour, p.omega, p.eps_r, guard);
+            }
+            if (hipGetLastError() != hipSuccess) return FGE_EHIP;
+            if (conv) {
+                if (launch_energy(Iv, Av, pl.W, pl.H, Fo, Bo, w, h, p.omega, p.eps_r, p.storage,
+                                  FGE_F32, stop, part, enow, s))
+                    return FGE_EHIP;
+                hipLaunchKernelGGL(cv_check_kernel, dim3(1), dim3(64), 0, s, enow, eprev, stop,
+                                   counts + j, tol, k, kmax);
+                if (hipGetLastError() != hipSuccess) return FGE_EHIP;
+            }
+        }
+        // the level's state, in the storage type
+        hipLaunchKernelGGL(cv_copy_kernel<T>, dim3(blocks_for(3 * n)), dim3(kCvThreads), 0, s, Fo,
+                           Bo, static_cast<T *>(io.Fo), static_cast<T *>(io.Bo), n, nullptr);
+        if (hipGetLastError() != hipSuccess) return FGE_EHIP;
+    }
+    return FGE_OK;
+}
+
+}  // namespace
+
+size_t converge_workspace_bytes(int W, int H, const fge_params &p) {
+    Plan pl;
+    if (cv_plan(W, H, p, &pl) != FGE_OK) return 0;
+    return cv_layout(pl, p.order == FGE_JACOBI).total;
+}
+
+fge_status estimate_converge(const void *I, const void *A, int W, int H, const fge_params &p,
+                             double tol, int max_sweeps, void *F, void *B, int32_t *sweeps_out,
+                             void *workspace, size_t workspace_bytes, void *stream) {
+    Plan pl;
+    const fge_status st = cv_plan(W, H, p, &pl);
+    if (st != FGE_OK) return st;
+    if (!I || !A || !F || !B || F == B) return FGE_EINVAL;
+    if (tol >= 0.0 && (max_sweeps < 1 || max_sweeps > kCvMaxSweeps)) return FGE_EINVAL;
+    if (!(tol == tol)) return FGE_EINVAL;   // NaN
+    const size_t need = cv_layout(pl, p.order == FGE_JACOBI).total;
+    if (!workspace || workspace_bytes < need || (reinterpret_cast<uintptr_t>(workspace) & 255))
+        return FGE_EWORKSPACE;
+    char *ws = static_cast<char *>(workspace);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (p.storage == FGE_F16)
+        return cv_run<_Float16>(pl, p, I, A, F, B, tol, max_sweeps, sweeps_out, ws, s);
+    return cv_run<float>(pl, p, I, A, F, B, tol, max_sweeps, sweeps_out, ws, s);
+}
+
+}  // namespace fge
+
+extern "C" {
+
+size_t fge_converge_workspace_bytes(int32_t W, int32_t H, const fge_params *p) {
+    fge_params tmp;
+    if (!p) {
+        fge_default_params(&tmp);
+        p = &tmp;
+    }
+    return fge::converge_workspace_bytes(W, H, *p);
+}
+
+fge_status fge_estimate_foreground_converge(const void *I, const void *alpha, int32_t W, int32_t H,
+                                            const fge_params *p, double tol, int32_t max_sweeps,
+                                            void *F, void *B, int32_t *sweeps_out, void *workspace,
+                                            size_t workspace_bytes, void *stream) {
+    fge_params tmp;
+    if (!p) {
+        fge_default_params(&tmp);
+        p = &tmp;
+    }
+    return fge::estimate_converge(I, alpha, W, H, *p, tol, max_sweeps, F, B, sweeps_out, workspace,
+                                  workspace_bytes, stream);
+}
+
+}  // extern "C"

@@ -167,6 +167,22 @@ void make_coarse_args(const Plan &plan, const LevelSrc &src, void *Fo, void *Bo,
 void make_gather_args(const Plan &plan, const void *I, const void *A, void *pyr, GatherArgs *a);
 long long gather_units(const GatherArgs &a);
 
+// Energy of (F, B) (w x h, element type state_storage) against I, alpha (W x H, element type
+// storage, read through the level's nearest map) into out[0..5] (fge_energy's layout); `part`
+// holds energy_blocks(w, h) * 5 doubles.  A non-null `stop` holding a non-zero value makes both
+// launches no-ops.
+int energy_blocks(int w, int h);
+int launch_energy(const void *I, const void *A, int W, int H, const void *F, const void *B, int w,
+                  int h, float omega, float eps, int storage, int state_storage, const int *stop,
+                  double *part, double *out, void *stream);
+
+// Level loop with the convergence stop or the Jacobi order (fge_converge.hip); tol < 0 runs the
+// fixed counts.
+size_t converge_workspace_bytes(int W, int H, const fge_params &p);
+fge_status estimate_converge(const void *I, const void *A, int W, int H, const fge_params &p,
+                             double tol, int max_sweeps, void *F, void *B, int32_t *sweeps_out,
+                             void *workspace, size_t workspace_bytes, void *stream);
+
 // Batched launches: descriptor tables, work lists and counters are device pointers.
 int launch_zero(int *d, int n, void *stream);
 int launch_gather_batch(const GatherArgs *descs, const long long *first, int n, long long total,

@@ -30,7 +30,7 @@ bool params_valid(const fge_params &p) {
     if (p.small_size < 0 || p.iters_small < 0 || p.iters_big < 0) return false;
     if (p.iters_small > 1000 || p.iters_big > 1000) return false;
     if (p.storage != FGE_F32 && p.storage != FGE_F16) return false;
-    if (p.order != FGE_REDBLACK) return false;
+    if (p.order != FGE_REDBLACK && p.order != FGE_JACOBI) return false;
     if (p.kernel < FGE_KERNEL_AUTO || p.kernel > FGE_KERNEL_NAIVE) return false;
     if (p.strip_rows < 0 || p.strip_rows > 1 << 20) return false;
     if (p.coarse_max_px < -1 || p.coarse_max_px > kCoarseMaxPx) return false;
@@ -55,7 +55,11 @@ fge_status make_plan(int W, int H, const fge_params &p, Plan *out) {
         pl.lv[i] = {w, h, small ? p.iters_small : p.iters_big};
     }
     // Coarse block: the longest prefix of levels with w*h <= limit (sizes grow with l).
-    const int limit = p.coarse_max_px == 0 ? kCoarseMaxPx : p.coarse_max_px;
+    // The coarse block and the fused fine kernels sweep in red-black order; the Jacobi order
+    // runs every level on per-level kernels.
+    const bool jacobi = p.order == FGE_JACOBI;
+    if (jacobi && p.kernel == FGE_KERNEL_FUSED) return FGE_EUNSUPPORTED;
+    const int limit = jacobi ? -1 : (p.coarse_max_px == 0 ? kCoarseMaxPx : p.coarse_max_px);
     pl.nc = 0;
     // A coarse level must also have at most kCoarseMaxPairs pairs of columns (thin levels of
     // odd width can exceed that while still having <= 4096 pixels).
@@ -71,7 +75,7 @@ fge_status make_plan(int W, int H, const fge_params &p, Plan *out) {
     for (int i = pl.nc; i < pl.n; ++i) {
         const bool can_fuse = pl.lv[i].iters == 2 && i > 0;
         if (p.kernel == FGE_KERNEL_FUSED && !can_fuse) return FGE_EUNSUPPORTED;
-        if (p.kernel == FGE_KERNEL_NAIVE || !can_fuse)
+        if (p.kernel == FGE_KERNEL_NAIVE || jacobi || !can_fuse)
             pl.kind[i] = kKindNaive;
         else if (static_cast<long>(pl.lv[i].w) * pl.lv[i].h <= tile_max ||
                  3 * static_cast<long long>(W) * H * pl.elem >= (1LL << 32))

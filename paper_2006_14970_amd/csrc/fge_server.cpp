@@ -579,7 +579,8 @@ fge_status fge_server_create(const fge_params *p, const fge_server_config *c, vo
     fge_params prm;
     if (p) prm = *p; else fge_default_params(&prm);
     if (!fge::params_valid(prm)) return FGE_EINVAL;
-    if (prm.kernel == FGE_KERNEL_NAIVE || prm.coarse_max_px < 0 || prm.iters_big != 2)
+    if (prm.kernel == FGE_KERNEL_NAIVE || prm.coarse_max_px < 0 || prm.iters_big != 2 ||
+        prm.order != FGE_REDBLACK)
         return FGE_EUNSUPPORTED;
     fge_server_config cfg;
     if (c) cfg = *c; else fge_server_default_config(&cfg);

@@ -1,0 +1,321 @@
+// Reporting and layout kernels (C ABI in include/fge.h): the energy of a result and its
+// compositing residual, reduced on the device, and conversions between interleaved 8-bit or
+// float images and the planar storage the estimator works on.
+//
+// Energy (the quadratic whose per-pixel stationarity conditions are the 2x2 systems of eq. 9):
+//   E = sum_i sum_c (a_i F_i^c + (1 - a_i) B_i^c - I_i^c)^2
+//     + sum over undirected in-bounds 4-neighbour edges {i, j}, each once, of
+//       (eps_r + omega |a_i - a_j|) sum_c [(F_i^c - F_j^c)^2 + (B_i^c - B_j^c)^2].
+// Every pixel adds its data term and the edges to its right and lower neighbours.  Terms are
+// formed and summed in float64: per thread, per block (fixed tree order in LDS), then over the
+// blocks' partial sums by one workgroup in a fixed order, so the result is deterministic.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "fge_internal.h"
+
+namespace fge {
+namespace {
+
+constexpr int kRedThreads = 256;
+constexpr int kRedBlocksMax = 2048;
+
+template <typename T>
+__device__ __forceinline__ double ld(const T *p, size_t i) {
+    return static_cast<double>(static_cast<float>(p[i]));
+}
+
+// Partial sums of one block: [0] data term, [1] smoothness term, [2] sum of |residual| over
+// fractional pixels (0 < a < 1), [3] number of fractional pixels, [4] max |residual| there.
+// F and B are w x h; I and alpha are W x H and are read through the nearest map of a level
+// (source index (x W / w, y H / h); the identity when the sizes agree).  A non-null `stop` that
+// holds a non-zero value turns the launch into a no-op.
+template <typename T, typename TF>
+__global__ __launch_bounds__(kRedThreads) void energy_partial_kernel(
+    const T *I, const T *A, int W, int H, const TF *F, const TF *B, int w, int h, float omega,
+    float eps, const int *stop, double *part) {
+    if (stop && *stop) return;
+    const size_t n = static_cast<size_t>(w) * h, nI = static_cast<size_t>(W) * H;
+    const bool same = W == w && H == h;
+    auto src = [&](int xx, int yy) {
+        return same ? static_cast<size_t>(yy) * w + xx
+                    : static_cast<size_t>(yy * H / h) * W + xx * W / w;
+    };
+    double data = 0.0, smooth = 0.0, rsum = 0.0, rcnt = 0.0, rmax = 0.0;
+    const size_t stride = static_cast<size_t>(gridDim.x) * kRedThreads;
+    for (size_t p = static_cast<size_t>(blockIdx.x) * kRedThreads + threadIdx.x; p < n; p += stride) {
+        const int y = static_cast<int>(p / w), x = static_cast<int>(p - static_cast<size_t>(y) * w);
+        const size_t ps = src(x, y);
+        const double a = ld(A, ps);
+        const bool frac = a > 0.0 && a < 1.0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const size_t q = c * n + p;
+            const double r = a * ld(F, q) + (1.0 - a) * ld(B, q) - ld(I, c * nI + ps);
+            data += r * r;
+            if (frac) {
+                rsum += fabs(r);
+                rmax = fmax(rmax, fabs(r));
+            }
+        }
+        if (frac) rcnt += 1.0;
+        if (x + 1 < w) {
+            const double s = static_cast<double>(eps) + static_cast<double>(omega) * fabs(a - ld(A, src(x + 1, y)));
+            double d = 0.0;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const size_t q = c * n + p;
+                const double df = ld(F, q) - ld(F, q + 1), db = ld(B, q) - ld(B, q + 1);
+                d += df * df + db * db;
+            }
+            smooth += s * d;
+        }
+        if (y + 1 < h) {
+            const double s = static_cast<double>(eps) + static_cast<double>(omega) * fabs(a - ld(A, src(x, y + 1)));
+            double d = 0.0;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const size_t q = c * n + p;
+                const double df = ld(F, q) - ld(F, q + w), db = ld(B, q) - ld(B, q + w);
+                d += df * df + db * db;
+            }
+            smooth += s * d;
+        }
+    }
+    __shared__ double red[5][kRedThreads];
+    red[0][threadIdx.x] = data;
+    red[1][threadIdx.x] = smooth;
+    red[2][threadIdx.x] = rsum;
+    red[3][threadIdx.x] = rcnt;
+    red[4][threadIdx.x] = rmax;
+    __syncthreads();
+    for (int half = kRedThreads / 2; half > 0; half >>= 1) {
+        if (threadIdx.x < half) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + half];
+            red[4][threadIdx.x] = fmax(red[4][threadIdx.x], red[4][threadIdx.x + half]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 5) part[static_cast<size_t>(blockIdx.x) * 5 + threadIdx.x] = red[threadIdx.x][0];
+}
+
+// out[0] = E, [1] data term, [2] smoothness term, [3] mean |residual| over fractional pixels,
+// [4] max |residual| there, [5] number of fractional pixels.
+__global__ __launch_bounds__(kRedThreads) void energy_final_kernel(const double *part, int nb,
+                                                                   const int *stop, double *out) {
+    if (stop && *stop) return;
+    __shared__ double red[5][kRedThreads];
+    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int b = threadIdx.x; b < nb; b += kRedThreads) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) acc[k] += part[static_cast<size_t>(b) * 5 + k];
+        acc[4] = fmax(acc[4], part[static_cast<size_t>(b) * 5 + 4]);
+    }
+#pragma unroll
+    for (int k = 0; k < 5; ++k) red[k][threadIdx.x] = acc[k];
+    __syncthreads();
+    for (int half = kRedThreads / 2; half > 0; half >>= 1) {
+        if (threadIdx.x < half) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + half];
+            red[4][threadIdx.x] = fmax(red[4][threadIdx.x], red[4][threadIdx.x + half]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[0] = red[0][0] + red[1][0];
+        out[1] = red[0][0];
+        out[2] = red[1][0];
+        out[3] = red[3][0] > 0.0 ? red[2][0] / red[3][0] : 0.0;
+        out[4] = red[4][0];
+        out[5] = red[3][0];
+    }
+}
+
+// ---- layout --------------------------------------------------------------------------------
+
+template <typename S>
+__device__ __forceinline__ float to_unit(S v) {
+    if constexpr (sizeof(S) == 1) return static_cast<float>(v) / 255.0f;
+    else return static_cast<float>(v);
+}
+
+template <typename D>
+__device__ __forceinline__ D from_unit(float v) {
+    if constexpr (sizeof(D) == 1) {
+        const float c = fminf(fmaxf(v, 0.0f), 1.0f) * 255.0f;
+        return static_cast<D>(__float2int_rn(c));
+    } else {
+        return static_cast<D>(v);
+    }
+}
+
+// Interleaved H x W x C (C = 3 or 4) -> planes: 3 colour planes, and the 4th channel as alpha.
+template <typename S, typename D>
+__global__ __launch_bounds__(256) void hwc_to_planar_kernel(const S *src, int C, size_t n,
+                                                            D *planes, D *alpha) {
+    const size_t p = static_cast<size_t>(blockIdx.x) * 256 + threadIdx.x;
+    if (p >= n) return;
+    const S *px = src + p * C;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) planes[c * n + p] = from_unit<D>(to_unit(px[c]));
+    if (C == 4 && alpha) alpha[p] = from_unit<D>(to_unit(px[3]));
+}
+
+template <typename S, typename D>
+__global__ __launch_bounds__(256) void planar_to_hwc_kernel(const S *planes, size_t n, D *dst) {
+    const size_t p = static_cast<size_t>(blockIdx.x) * 256 + threadIdx.x;
+    if (p >= n) return;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) dst[p * 3 + c] = from_unit<D>(to_unit(planes[c * n + p]));
+}
+
+template <typename S>
+int launch_h2p_src(const void *src, int C, size_t n, int dst_dtype, void *planes, void *alpha,
+                   hipStream_t s) {
+    const dim3 grid(static_cast<unsigned>((n + 255) / 256));
+    const S *sp = static_cast<const S *>(src);
+    switch (dst_dtype) {
+        case FGE_F32:
+            hipLaunchKernelGGL((hwc_to_planar_kernel<S, float>), grid, dim3(256), 0, s, sp, C, n,
+                               static_cast<float *>(planes), static_cast<float *>(alpha));
+            break;
+        case FGE_F16:
+            hipLaunchKernelGGL((hwc_to_planar_kernel<S, _Float16>), grid, dim3(256), 0, s, sp, C, n,
+                               static_cast<_Float16 *>(planes), static_cast<_Float16 *>(alpha));
+            break;
+        default:
+            hipLaunchKernelGGL((hwc_to_planar_kernel<S, uint8_t>), grid, dim3(256), 0, s, sp, C, n,
+                               static_cast<uint8_t *>(planes), static_cast<uint8_t *>(alpha));
+            break;
+    }
+    return static_cast<int>(hipGetLastError());
+}
+
+template <typename S>
+int launch_p2h_src(const void *src, size_t n, int dst_dtype, void *dst, hipStream_t s) {
+    const dim3 grid(static_cast<unsigned>((n + 255) / 256));
+    const S *sp = static_cast<const S *>(src);
+    switch (dst_dtype) {
+        case FGE_F32:
+            hipLaunchKernelGGL((planar_to_hwc_kernel<S, float>), grid, dim3(256), 0, s, sp, n,
+                               static_cast<float *>(dst));
+            break;
+        case FGE_F16:
+            hipLaunchKernelGGL((planar_to_hwc_kernel<S, _Float16>), grid, dim3(256), 0, s, sp, n,
+                               static_cast<_Float16 *>(dst));
+            break;
+        default:
+            hipLaunchKernelGGL((planar_to_hwc_kernel<S, uint8_t>), grid, dim3(256), 0, s, sp, n,
+                               static_cast<uint8_t *>(dst));
+            break;
+    }
+    return static_cast<int>(hipGetLastError());
+}
+
+bool dtype_ok(int d) { return d == FGE_F32 || d == FGE_F16 || d == FGE_U8; }
+
+}  // namespace
+
+int energy_blocks(int w, int h) {
+    const size_t n = static_cast<size_t>(w) * h;
+    const size_t b = (n + kRedThreads - 1) / kRedThreads;
+    return static_cast<int>(b < static_cast<size_t>(kRedBlocksMax) ? b : kRedBlocksMax);
+}
+
+template <typename T, typename TF>
+void launch_energy_t(const void *I, const void *A, int W, int H, const void *F, const void *B,
+                     int w, int h, float omega, float eps, const int *stop, double *part, int nb,
+                     hipStream_t s) {
+    hipLaunchKernelGGL((energy_partial_kernel<T, TF>), dim3(nb), dim3(kRedThreads), 0, s,
+                       static_cast<const T *>(I), static_cast<const T *>(A), W, H,
+                       static_cast<const TF *>(F), static_cast<const TF *>(B), w, h, omega, eps,
+                       stop, part);
+}
+
+int launch_energy(const void *I, const void *A, int W, int H, const void *F, const void *B, int w,
+                  int h, float omega, float eps, int storage, int state_storage, const int *stop,
+                  double *part, double *out, void *stream) {
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int nb = energy_blocks(w, h);
+    const bool i16 = storage == FGE_F16, f16 = state_storage == FGE_F16;
+    if (i16 && f16)
+        launch_energy_t<_Float16, _Float16>(I, A, W, H, F, B, w, h, omega, eps, stop, part, nb, s);
+    else if (i16)
+        launch_energy_t<_Float16, float>(I, A, W, H, F, B, w, h, omega, eps, stop, part, nb, s);
+    else if (f16)
+        launch_energy_t<float, _Float16>(I, A, W, H, F, B, w, h, omega, eps, stop, part, nb, s);
+    else
+        launch_energy_t<float, float>(I, A, W, H, F, B, w, h, omega, eps, stop, part, nb, s);
+    int err = static_cast<int>(hipGetLastError());
+    if (err) return err;
+    hipLaunchKernelGGL(energy_final_kernel, dim3(1), dim3(kRedThreads), 0, s, part, nb, stop, out);
+    return static_cast<int>(hipGetLastError());
+}
+
+}  // namespace fge
+
+extern "C" {
+
+size_t fge_energy_workspace_bytes(int32_t W, int32_t H) {
+    if (W < 1 || H < 1 || W > fge::kMaxSide || H > fge::kMaxSide) return 0;
+    return (static_cast<size_t>(fge::energy_blocks(W, H)) * 5 * sizeof(double) + 255) & ~static_cast<size_t>(255);
+}
+
+fge_status fge_energy(const void *I, const void *alpha, const void *F, const void *B, int32_t W,
+                      int32_t H, const fge_params *p, double *out, void *workspace,
+                      size_t workspace_bytes, void *stream) {
+    fge_params tmp;
+    if (!p) {
+        fge_default_params(&tmp);
+        p = &tmp;
+    }
+    if (!fge::params_valid(*p)) return FGE_EINVAL;
+    if (W < 1 || H < 1 || W > fge::kMaxSide || H > fge::kMaxSide) return FGE_EINVAL;
+    if (!I || !alpha || !F || !B || !out) return FGE_EINVAL;
+    const size_t need = fge_energy_workspace_bytes(W, H);
+    if (!workspace || workspace_bytes < need || (reinterpret_cast<uintptr_t>(workspace) & 255))
+        return FGE_EWORKSPACE;
+    return fge::launch_energy(I, alpha, W, H, F, B, W, H, p->omega, p->eps_r, p->storage,
+                              p->storage, nullptr, static_cast<double *>(workspace), out, stream)
+               ? FGE_EHIP
+               : FGE_OK;
+}
+
+fge_status fge_hwc_to_planar(const void *src, int32_t src_dtype, int32_t channels, int32_t W,
+                             int32_t H, void *planes, void *alpha, int32_t dst_dtype,
+                             void *stream) {
+    if (!src || !planes || W < 1 || H < 1 || W > fge::kMaxSide || H > fge::kMaxSide) return FGE_EINVAL;
+    if (channels != 3 && channels != 4) return FGE_EINVAL;
+    if (channels == 4 && !alpha) return FGE_EINVAL;
+    if (!fge::dtype_ok(src_dtype) || !fge::dtype_ok(dst_dtype)) return FGE_EINVAL;
+    const size_t n = static_cast<size_t>(W) * H;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    void *al = channels == 4 ? alpha : nullptr;
+    int err;
+    switch (src_dtype) {
+        case FGE_F32: err = fge::launch_h2p_src<float>(src, channels, n, dst_dtype, planes, al, s); break;
+        case FGE_F16: err = fge::launch_h2p_src<_Float16>(src, channels, n, dst_dtype, planes, al, s); break;
+        default: err = fge::launch_h2p_src<uint8_t>(src, channels, n, dst_dtype, planes, al, s); break;
+    }
+    return err ? FGE_EHIP : FGE_OK;
+}
+
+fge_status fge_planar_to_hwc(const void *planes, int32_t src_dtype, int32_t W, int32_t H,
+                             void *dst, int32_t dst_dtype, void *stream) {
+    if (!planes || !dst || W < 1 || H < 1 || W > fge::kMaxSide || H > fge::kMaxSide) return FGE_EINVAL;
+    if (!fge::dtype_ok(src_dtype) || !fge::dtype_ok(dst_dtype)) return FGE_EINVAL;
+    const size_t n = static_cast<size_t>(W) * H;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int err;
+    switch (src_dtype) {
+        case FGE_F32: err = fge::launch_p2h_src<float>(planes, n, dst_dtype, dst, s); break;
+        case FGE_F16: err = fge::launch_p2h_src<_Float16>(planes, n, dst_dtype, dst, s); break;
+        default: err = fge::launch_p2h_src<uint8_t>(planes, n, dst_dtype, dst, s); break;
+    }
+    return err ? FGE_EHIP : FGE_OK;
+}
+
+}  // extern "C"

@@ -18,8 +18,8 @@ LIB_PATH = os.path.join(_HERE, "libfge.so")
 
 FGE_OK, FGE_EINVAL, FGE_ENOMEM, FGE_EHIP, FGE_EUNSUPPORTED, FGE_EWORKSPACE = 0, -1, -2, -3, -4, -5
 FGE_EBUDGET = -6
-F32, F16 = 0, 1
-REDBLACK = 0
+F32, F16, U8 = 0, 1, 2
+REDBLACK, JACOBI = 0, 1
 KERNEL_AUTO, KERNEL_FUSED, KERNEL_NAIVE = 0, 1, 2
 MAX_LEVELS = 16
 
@@ -153,6 +153,19 @@ def _lib():
     lib.fge_profile_start.restype = ctypes.c_int
     lib.fge_profile_stop.argtypes = [ctypes.POINTER(ctypes.c_double), ip, i32]
     lib.fge_profile_stop.restype = ctypes.c_int
+    lib.fge_energy_workspace_bytes.argtypes = [i32, i32]
+    lib.fge_energy_workspace_bytes.restype = sz
+    lib.fge_energy.argtypes = [vp, vp, vp, vp, i32, i32, pp, vp, vp, sz, vp]
+    lib.fge_energy.restype = ctypes.c_int
+    lib.fge_hwc_to_planar.argtypes = [vp, i32, i32, i32, i32, vp, vp, i32, vp]
+    lib.fge_hwc_to_planar.restype = ctypes.c_int
+    lib.fge_planar_to_hwc.argtypes = [vp, i32, i32, i32, vp, i32, vp]
+    lib.fge_planar_to_hwc.restype = ctypes.c_int
+    lib.fge_converge_workspace_bytes.argtypes = [i32, i32, pp]
+    lib.fge_converge_workspace_bytes.restype = sz
+    lib.fge_estimate_foreground_converge.argtypes = [vp, vp, i32, i32, pp, ctypes.c_double, i32,
+                                                     vp, vp, vp, vp, sz, vp]
+    lib.fge_estimate_foreground_converge.restype = ctypes.c_int
     tp = ctypes.POINTER(TuneEntry)
     lib.fge_tune_candidates.argtypes = []
     lib.fge_tune_candidates.restype = i32
@@ -596,3 +609,99 @@ def autotune_batch(sizes, Is, alphas, params: Params | None = None, reps: int = 
     _cache_put(cache_path, key, {"strip_rows": best.strip_rows, "tile_max_px": best.tile_max_px,
                                  "entries": ent})
     return best, ent
+
+
+# ---- reporting and layout ----------------------------------------------------------------------
+
+def _dtype_code(dt):
+    import torch
+    codes = {torch.float32: F32, torch.float16: F16, torch.uint8: U8}
+    if dt not in codes:
+        raise ValueError(f"unsupported dtype {dt}")
+    return codes[dt]
+
+
+def _torch_dtype(code):
+    import torch
+    return {F32: torch.float32, F16: torch.float16, U8: torch.uint8}[code]
+
+
+def energy(I, alpha, F, B, params: Params | None = None, stream=None, out=None):
+    """Energy E of (F, B) and the compositing residual, reduced on the device (fge_energy).
+    Returns a float64 CUDA tensor of 6: E, data term, smoothness term, mean and max |residual|
+    over fractional pixels, their count.  Does not synchronise."""
+    import torch
+    p = params if params is not None else default_params()
+    _, H, W = I.shape
+    dt = storage_dtype(p)
+    for name, t, shp in (("I", I, (3, H, W)), ("alpha", alpha, (H, W)), ("F", F, (3, H, W)),
+                         ("B", B, (3, H, W))):
+        if tuple(t.shape) != shp or t.dtype != dt or not t.is_cuda or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous CUDA tensor {shp} of dtype {dt}")
+    if out is None:
+        out = torch.empty(6, dtype=torch.float64, device=I.device)
+    ws = torch.empty(_lib().fge_energy_workspace_bytes(W, H), dtype=torch.uint8, device=I.device)
+    _check(_lib().fge_energy(I.data_ptr(), alpha.data_ptr(), F.data_ptr(), B.data_ptr(), W, H,
+                             ctypes.byref(p), out.data_ptr(), ws.data_ptr(), ws.numel(),
+                             _stream_ptr(stream)), "fge_energy")
+    return out
+
+
+def hwc_to_planar(img, dtype=None, stream=None):
+    """(H, W, 3|4) CUDA tensor (uint8, float32 or float16) -> (I (3, H, W), alpha (H, W) or None)
+    in `dtype` (default float32); uint8 maps to v / 255 (fge_hwc_to_planar)."""
+    import torch
+    dtype = dtype or torch.float32
+    if img.dim() != 3 or img.shape[2] not in (3, 4) or not img.is_cuda or not img.is_contiguous():
+        raise ValueError("img must be a contiguous CUDA tensor (H, W, 3|4)")
+    H, W, C = img.shape
+    I = torch.empty((3, H, W), dtype=dtype, device=img.device)
+    a = torch.empty((H, W), dtype=dtype, device=img.device) if C == 4 else None
+    _check(_lib().fge_hwc_to_planar(img.data_ptr(), _dtype_code(img.dtype), C, W, H, I.data_ptr(),
+                                    a.data_ptr() if a is not None else None, _dtype_code(dtype),
+                                    _stream_ptr(stream)), "fge_hwc_to_planar")
+    return I, a
+
+
+def planar_to_hwc(planes, dtype=None, stream=None):
+    """(3, H, W) CUDA tensor -> (H, W, 3) in `dtype` (default uint8: round(clamp(v) * 255))."""
+    import torch
+    dtype = dtype or torch.uint8
+    if planes.dim() != 3 or planes.shape[0] != 3 or not planes.is_cuda or not planes.is_contiguous():
+        raise ValueError("planes must be a contiguous CUDA tensor (3, H, W)")
+    _, H, W = planes.shape
+    out = torch.empty((H, W, 3), dtype=dtype, device=planes.device)
+    _check(_lib().fge_planar_to_hwc(planes.data_ptr(), _dtype_code(planes.dtype), W, H,
+                                    out.data_ptr(), _dtype_code(dtype), _stream_ptr(stream)),
+           "fge_planar_to_hwc")
+    return out
+
+
+def estimate_foreground_converge(I, alpha, params: Params | None = None, tol: float = 1e-4,
+                                 max_sweeps: int = 100, F=None, B=None, stream=None):
+    """Algorithm 1's "while not converged" level loop on the device (fge_estimate_foreground_converge):
+    per level, sweep until the level energy changes by at most `tol` (relative) or `max_sweeps`.
+    Returns (F, B, sweeps), sweeps an int32 CUDA tensor of the per-level counts.  tol < 0 runs the
+    fixed counts.  Does not synchronise."""
+    import torch
+    p = params if params is not None else default_params()
+    dt = storage_dtype(p)
+    _, H, W = I.shape
+    for name, t in (("I", I), ("alpha", alpha)):
+        if not t.is_cuda or t.dtype != dt or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous CUDA tensor of dtype {dt}")
+    if tuple(alpha.shape) != (H, W):
+        raise ValueError("alpha must be (H, W) matching I")
+    if F is None:
+        F = torch.empty((3, H, W), dtype=dt, device=I.device)
+    if B is None:
+        B = torch.empty((3, H, W), dtype=dt, device=I.device)
+    n = num_levels(W, H)
+    sweeps = torch.zeros(max(1, n), dtype=torch.int32, device=I.device)
+    need = _lib().fge_converge_workspace_bytes(W, H, ctypes.byref(p))
+    ws = torch.empty(max(1, need), dtype=torch.uint8, device=I.device)
+    _check(_lib().fge_estimate_foreground_converge(
+        I.data_ptr(), alpha.data_ptr(), W, H, ctypes.byref(p), float(tol), int(max_sweeps),
+        F.data_ptr(), B.data_ptr(), sweeps.data_ptr(), ws.data_ptr(), ws.numel(),
+        _stream_ptr(stream)), "fge_estimate_foreground_converge")
+    return F, B, sweeps[:n]

@@ -234,3 +234,53 @@ def test_autotuner_host_side(fge):
     null = (ctypes.c_void_p * 3)()
     assert lib.fge_batch_autotune(3, null, null, W, H, None, null, null, None, 0, None, 3,
                                   ctypes.byref(best), None, 0, None) == fge.FGE_EWORKSPACE
+
+
+def test_reporting_and_layout_argument_errors(fge):
+    lib = fge.load()
+    assert lib.fge_energy_workspace_bytes(4096, 3072) == 2048 * 5 * 8
+    assert lib.fge_energy_workspace_bytes(10, 10) == 256
+    assert lib.fge_energy_workspace_bytes(0, 10) == 0
+    a = 0x100000
+    assert lib.fge_energy(a, a, a, a, 64, 64, None, None, a, 256, None) == fge.FGE_EINVAL
+    assert lib.fge_energy(a, a, a, a, 64, 64, None, a, None, 0, None) == fge.FGE_EWORKSPACE
+    assert lib.fge_energy(a, a, a, a, 64, 64, None, a, a + 16, 256, None) == fge.FGE_EWORKSPACE
+    assert lib.fge_energy(a, a, a, a, 0, 64, None, a, a, 256, None) == fge.FGE_EINVAL
+    assert lib.fge_hwc_to_planar(a, fge.U8, 5, 8, 8, a, a, fge.F32, None) == fge.FGE_EINVAL
+    assert lib.fge_hwc_to_planar(a, fge.U8, 4, 8, 8, a, None, fge.F32, None) == fge.FGE_EINVAL
+    assert lib.fge_hwc_to_planar(a, 7, 3, 8, 8, a, None, fge.F32, None) == fge.FGE_EINVAL
+    assert lib.fge_planar_to_hwc(a, fge.F32, 8, 8, a, 9, None) == fge.FGE_EINVAL
+    assert lib.fge_planar_to_hwc(None, fge.F32, 8, 8, a, fge.U8, None) == fge.FGE_EINVAL
+
+
+def test_jacobi_and_converge_host_side(fge):
+    lib = fge.load()
+    pj = fge.default_params(order=fge.JACOBI)
+    info = fge.plan(1024, 768, pj)
+    assert info.n_coarse == 0 and [it for _, _, it in info.levels] == \
+        [it for _, _, it in fge.plan(1024, 768).levels]
+    need = lib.fge_converge_workspace_bytes(1024, 768, ctypes.byref(pj))
+    # Jacobi temporary (6 planes at full size) on top of the level buffers
+    assert need >= 6 * 4 * 1024 * 768 and fge.workspace_bytes(1024, 768, pj) == need
+    with pytest.raises(fge.FgeError) as e:
+        fge.plan(1024, 768, fge.default_params(order=fge.JACOBI, kernel=fge.KERNEL_FUSED))
+    assert e.value.status == fge.FGE_EUNSUPPORTED
+    with pytest.raises(fge.FgeError) as e:
+        fge.Batch([(300, 200)], pj)
+    assert e.value.status == fge.FGE_EUNSUPPORTED
+    a = 0x100000
+    p = fge.default_params()
+    nw = lib.fge_converge_workspace_bytes(64, 64, ctypes.byref(p))
+
+    def conv(tol, ms, ws=a, nbytes=nw, I=a):
+        return lib.fge_estimate_foreground_converge(I, a + 0x1000, 64, 64, ctypes.byref(p), tol, ms,
+                                                    a + 0x2000, a + 0x3000, None, ws, nbytes, None)
+    assert conv(1e-4, 0) == fge.FGE_EINVAL
+    assert conv(1e-4, 100001) == fge.FGE_EINVAL
+    assert conv(float("nan"), 10) == fge.FGE_EINVAL
+    assert conv(1e-4, 10, I=None) == fge.FGE_EINVAL
+    assert conv(1e-4, 10, nbytes=nw - 1) == fge.FGE_EWORKSPACE
+    assert conv(1e-4, 10, ws=None) == fge.FGE_EWORKSPACE
+    h = ctypes.c_void_p()
+    assert lib.fge_server_create(ctypes.byref(pj), None, 0x100000, 1 << 30, 0x10,
+                                 ctypes.byref(h)) == fge.FGE_EUNSUPPORTED
