@@ -111,13 +111,62 @@ def run_storage(torch, fge, sample, storage, steps, warmup, oracle_F=None, oracl
         step(k)
     torch.cuda.synchronize()
     lvl_ms, lvl_n = fge.profile_stop()
+
+    # quality of the result against the generator's ground-truth foreground (the paper's SAD, MSE
+    # and GRAD over the translucent pixels, weighted by the ground-truth alpha), on the device
+    I, a, F, B, ws = sets[0]
+    G = torch.from_numpy(sample.F).to(dt).to(dev).contiguous()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    q = fge.quality(F, G, a, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    q = q.cpu().numpy()
     return {
         "ms_per_step": wall / steps * 1e3,
         "lat_ms": lat,
         "level_ms": [lvl_ms[i] / lvl_n[i] if lvl_n[i] else None for i in range(len(lvl_ms))],
         "max_abs_vs_oracle": err,
         "params": p,
+        "quality": {"SAD": float(q[0]), "MSE": float(q[1]), "GRAD": float(q[2]),
+                    "translucent_px": int(q[3]), "device_ms": e0.elapsed_time(e1)},
     }
+
+
+def run_converge(torch, fge, sample, oracle_F=None):
+    """The convergence form of the level loop (tol 1e-4, at most 200 sweeps per level, red-black
+    and Jacobi, float16 storage) on the 4096x3072 image: time, sweeps per level, and quality
+    against the ground truth next to the fixed counts."""
+    dev = torch.device("cuda:0")
+    out = {}
+    G = None
+    for order_name, order in (("redblack", fge.REDBLACK), ("jacobi", fge.JACOBI)):
+        p = fge.default_params(storage=fge.F16, order=order)
+        I = torch.from_numpy(sample.I).half().to(dev).contiguous()
+        a = torch.from_numpy(sample.alpha).half().to(dev).contiguous()
+        G = torch.from_numpy(sample.F).half().to(dev).contiguous()
+        fge.estimate_foreground_converge(I, a, p, tol=1e-4, max_sweeps=200)
+        torch.cuda.synchronize()
+        reps = 3
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            F, B, sw = fge.estimate_foreground_converge(I, a, p, tol=1e-4, max_sweeps=200)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / reps * 1e3
+        q = fge.quality(F, G, a).cpu().numpy()
+        Ff, Bf = fge.estimate_foreground(I, a, p)
+        qf = fge.quality(Ff, G, a).cpu().numpy()
+        torch.cuda.synchronize()
+        out[order_name] = {"ms": ms, "value": W_IMG * H_IMG / 1e6 / (ms * 1e-3),
+                           "sweeps_per_level": sw.cpu().tolist(),
+                           "quality": {"SAD": float(q[0]), "MSE": float(q[1]), "GRAD": float(q[2])},
+                           "fixed_counts_quality": {"SAD": float(qf[0]), "MSE": float(qf[1]),
+                                                    "GRAD": float(qf[2])}}
+        log(f"  converge {order_name}: {ms:.1f} ms, sweeps {sw.cpu().tolist()}, SAD {q[0]:.1f} "
+            f"(fixed counts {qf[0]:.1f})")
+    return {"workload": "4096x3072 strands image, float16 storage, level loop until the level "
+                        "energy changes by at most 1e-4 (relative), at most 200 sweeps per level",
+            "unit": "MP/s", **out}
 
 
 def time_batch(torch, fge, sizes, p, Is, As, steps, warmup, stream):
@@ -319,6 +368,8 @@ def main():
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the serving-stream (continuous batching, float16 storage) leg")
     ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--no-converge", action="store_true",
+                    help="skip the convergence-form (while not converged) leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 512 MiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -388,6 +439,12 @@ def main():
 
     s32 = summary(res["f32"], 4)
     s16 = summary(res["f16"], 2)
+    s32["quality_vs_ground_truth"] = res["f32"]["quality"]
+    s16["quality_vs_ground_truth"] = res["f16"]["quality"]
+    converge = None
+    if not args.no_converge:
+        log("convergence form of the level loop (float16 storage)")
+        converge = run_converge(torch, fge, sample)
     batch = None if args.no_batch else run_batch(torch, fge, synth, args, s32["value"],
                                                    not args.no_cpu_baseline)
     serving = None if args.no_serving else run_serving(torch, fge, synth, args, s32["value"],
@@ -413,6 +470,8 @@ def main():
         "roofline": s32["roofline"],
         "fp16_store": s16,
         "level_ms_finest_first": s32["level_ms_finest_first"],
+        "quality_vs_ground_truth": s32["quality_vs_ground_truth"],
+        "converge_fp16": converge,
         "batch_fp16": batch,
         "serving_fp16": serving,
         "cpu_baseline": cpu,

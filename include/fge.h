@@ -213,6 +213,27 @@ fge_status fge_energy(const void *I, const void *alpha, const void *F, const voi
                       int32_t H, const fge_params *p, double *out, void *workspace,
                       size_t workspace_bytes, void *stream);
 
+/* The paper's error measures of a foreground estimate F against a reference G (Section V): over
+ * the translucent pixels 0 < a_i < 1 of the reference matte `alpha`, each weighted by a_i,
+ *   SAD = sum a_i |F_i - G_i|_1,  MSE = sum a_i |F_i - G_i|_2^2,
+ *   GRAD = sum a_i |grad F_i - grad G_i|_2^2,
+ * gradients from first-order Gaussian derivative filters of standard deviation `sigma` (the
+ * paper's 1.4): the sampled Gaussian of radius int(4 sigma + 0.5) <= 16, normalised to sum 1,
+ * times x / sigma^2 along the derivative axis, with mirrored borders, for x and y and every
+ * channel.  F, G (3 planes) and alpha (1 plane) are W x H device buffers of type dtype (F32 or
+ * F16).  `out` is a DEVICE array of 4 doubles: SAD, MSE, GRAD and the number of translucent
+ * pixels.  All arithmetic in float64; the reduction order is fixed.  Workspace:
+ * fge_quality_workspace_bytes (256-byte aligned). */
+size_t fge_quality_workspace_bytes(int32_t W, int32_t H);
+fge_status fge_quality(const void *F, const void *G, const void *alpha, int32_t W, int32_t H,
+                       int32_t dtype, double sigma, double *out, void *workspace,
+                       size_t workspace_bytes, void *stream);
+
+/* Composite onto a new background (eq. 1 used forward): C = alpha F + (1 - alpha) B, computed in
+ * float64 (each product and the sum rounded once) and rounded to dtype.  Planar device buffers. */
+fge_status fge_composite(const void *F, const void *alpha, const void *B, int32_t W, int32_t H,
+                         int32_t dtype, void *C, void *stream);
+
 /* Interleaved H x W x C images (C = 3: RGB, or 4: RGBA) to planar: 3 colour planes into `planes`
  * and, for C = 4, the fourth channel into `alpha` (one plane).  Element types are fge_dtype
  * values: U8 maps v to v / 255 (float32 division); a float maps to U8 as

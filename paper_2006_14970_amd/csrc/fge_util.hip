@@ -11,6 +11,7 @@
 // blocks' partial sums by one workgroup in a fixed order, so the result is deterministic.
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstdint>
 
 #include "fge_internal.h"
@@ -131,6 +132,120 @@ __global__ __launch_bounds__(kRedThreads) void energy_final_kernel(const double 
         out[3] = red[3][0] > 0.0 ? red[2][0] / red[3][0] : 0.0;
         out[4] = red[4][0];
         out[5] = red[3][0];
+    }
+}
+
+// ---- quality measures and compositing -------------------------------------------------------
+//
+// The paper's error measures of a foreground estimate F against a reference G (Section V): over
+// the translucent pixels 0 < a_i < 1 of the reference matte, weighted by a_i, SAD = sum a_i
+// |F_i - G_i|_1, MSE = sum a_i |F_i - G_i|_2^2 and GRAD = sum a_i |grad F_i - grad G_i|_2^2, the
+// gradients from first-order Gaussian derivative filters.  The filter is the sampled Gaussian of
+// radius int(4 sigma + 0.5) normalised to sum 1; the x derivative at pixel (x, y) is
+// sum_a phi(a) sum_b (b / sigma^2) phi(b) D(x + b, y + a), the y derivative likewise with the
+// roles swapped, D = F - G (the filters are linear), with mirrored borders (d c b a | a b c d).
+// Everything in float64.
+
+constexpr int kGradMaxR = 16;
+
+struct GradFilter {
+    int r;
+    double phi[2 * kGradMaxR + 1];   // phi[r + j]: normalised Gaussian at offset j
+    double der[2 * kGradMaxR + 1];   // der[r + j] = (j / sigma^2) phi[r + j]
+};
+
+__device__ __forceinline__ int mirror(int i, int n) {
+    const int p = 2 * n;
+    int m = i % p;
+    if (m < 0) m += p;
+    return m < n ? m : p - 1 - m;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kRedThreads) void quality_partial_kernel(const T *F, const T *G,
+                                                                      const T *A, int w, int h,
+                                                                      GradFilter K, double *part) {
+    const size_t n = static_cast<size_t>(w) * h;
+    double sad = 0.0, mse = 0.0, grad = 0.0, cnt = 0.0;
+    const int r = K.r;
+    for (size_t p = static_cast<size_t>(blockIdx.x) * kRedThreads + threadIdx.x; p < n;
+         p += static_cast<size_t>(gridDim.x) * kRedThreads) {
+        const double a = ld(A, p);
+        if (!(a > 0.0 && a < 1.0)) continue;
+        const int y = static_cast<int>(p / w), x = static_cast<int>(p - static_cast<size_t>(y) * w);
+        double s1 = 0.0, s2 = 0.0, g2 = 0.0;
+        for (int c = 0; c < 3; ++c) {
+            const T *Fc = F + c * n, *Gc = G + c * n;
+            const double d = ld(Fc, p) - ld(Gc, p);
+            s1 += fabs(d);
+            s2 += d * d;
+            double gx = 0.0, gy = 0.0;
+            for (int dy = -r; dy <= r; ++dy) {
+                const size_t row = static_cast<size_t>(mirror(y + dy, h)) * w;
+                double sx = 0.0, ss = 0.0;
+                for (int dx = -r; dx <= r; ++dx) {
+                    const size_t q = row + mirror(x + dx, w);
+                    const double v = ld(Fc, q) - ld(Gc, q);
+                    sx += K.der[r + dx] * v;
+                    ss += K.phi[r + dx] * v;
+                }
+                gx += K.phi[r + dy] * sx;
+                gy += K.der[r + dy] * ss;
+            }
+            g2 += gx * gx + gy * gy;
+        }
+        sad += a * s1;
+        mse += a * s2;
+        grad += a * g2;
+        cnt += 1.0;
+    }
+    __shared__ double red[4][kRedThreads];
+    red[0][threadIdx.x] = sad;
+    red[1][threadIdx.x] = mse;
+    red[2][threadIdx.x] = grad;
+    red[3][threadIdx.x] = cnt;
+    __syncthreads();
+    for (int half = kRedThreads / 2; half > 0; half >>= 1) {
+        if (threadIdx.x < half)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + half];
+        __syncthreads();
+    }
+    if (threadIdx.x < 4) part[static_cast<size_t>(blockIdx.x) * 4 + threadIdx.x] = red[threadIdx.x][0];
+}
+
+__global__ __launch_bounds__(kRedThreads) void quality_final_kernel(const double *part, int nb,
+                                                                    double *out) {
+    __shared__ double red[4][kRedThreads];
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int b = threadIdx.x; b < nb; b += kRedThreads)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) acc[k] += part[static_cast<size_t>(b) * 4 + k];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) red[k][threadIdx.x] = acc[k];
+    __syncthreads();
+    for (int half = kRedThreads / 2; half > 0; half >>= 1) {
+        if (threadIdx.x < half)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + half];
+        __syncthreads();
+    }
+    if (threadIdx.x < 4) out[threadIdx.x] = red[threadIdx.x][0];
+}
+
+// C = a F + (1 - a) B in float64, each product and the sum rounded once (no contraction), then
+// converted to T.
+template <typename T>
+__global__ __launch_bounds__(256) void composite_kernel(const T *F, const T *A, const T *B, T *C,
+                                                        size_t n) {
+    const size_t p = static_cast<size_t>(blockIdx.x) * 256 + threadIdx.x;
+    if (p >= n) return;
+    const double a = ld(A, p);
+    const double b = __dadd_rn(1.0, -a);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const double v = __dadd_rn(__dmul_rn(a, ld(F, c * n + p)), __dmul_rn(b, ld(B, c * n + p)));
+        C[c * n + p] = static_cast<T>(v);
     }
 }
 
@@ -282,6 +397,65 @@ fge_status fge_energy(const void *I, const void *alpha, const void *F, const voi
                               p->storage, nullptr, static_cast<double *>(workspace), out, stream)
                ? FGE_EHIP
                : FGE_OK;
+}
+
+size_t fge_quality_workspace_bytes(int32_t W, int32_t H) {
+    if (W < 1 || H < 1 || W > fge::kMaxSide || H > fge::kMaxSide) return 0;
+    return (static_cast<size_t>(fge::energy_blocks(W, H)) * 4 * sizeof(double) + 255) & ~static_cast<size_t>(255);
+}
+
+fge_status fge_quality(const void *F, const void *G, const void *alpha, int32_t W, int32_t H,
+                       int32_t dtype, double sigma, double *out, void *workspace,
+                       size_t workspace_bytes, void *stream) {
+    if (!F || !G || !alpha || !out || W < 1 || H < 1 || W > fge::kMaxSide || H > fge::kMaxSide)
+        return FGE_EINVAL;
+    if (dtype != FGE_F32 && dtype != FGE_F16) return FGE_EINVAL;
+    const int r = static_cast<int>(4.0 * sigma + 0.5);
+    if (!(sigma > 0.0) || r < 1 || r > fge::kGradMaxR) return FGE_EINVAL;
+    const size_t need = fge_quality_workspace_bytes(W, H);
+    if (!workspace || workspace_bytes < need || (reinterpret_cast<uintptr_t>(workspace) & 255))
+        return FGE_EWORKSPACE;
+    fge::GradFilter K{};
+    K.r = r;
+    double sum = 0.0;
+    for (int j = -r; j <= r; ++j) sum += (K.phi[r + j] = std::exp(-0.5 * j * j / (sigma * sigma)));
+    for (int j = -r; j <= r; ++j) {
+        K.phi[r + j] /= sum;
+        K.der[r + j] = j / (sigma * sigma) * K.phi[r + j];
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    double *part = static_cast<double *>(workspace);
+    const int nb = fge::energy_blocks(W, H);
+    if (dtype == FGE_F16)
+        hipLaunchKernelGGL(fge::quality_partial_kernel<_Float16>, dim3(nb), dim3(fge::kRedThreads),
+                           0, s, static_cast<const _Float16 *>(F), static_cast<const _Float16 *>(G),
+                           static_cast<const _Float16 *>(alpha), W, H, K, part);
+    else
+        hipLaunchKernelGGL(fge::quality_partial_kernel<float>, dim3(nb), dim3(fge::kRedThreads), 0,
+                           s, static_cast<const float *>(F), static_cast<const float *>(G),
+                           static_cast<const float *>(alpha), W, H, K, part);
+    if (hipGetLastError() != hipSuccess) return FGE_EHIP;
+    hipLaunchKernelGGL(fge::quality_final_kernel, dim3(1), dim3(fge::kRedThreads), 0, s, part, nb, out);
+    return hipGetLastError() == hipSuccess ? FGE_OK : FGE_EHIP;
+}
+
+fge_status fge_composite(const void *F, const void *alpha, const void *B, int32_t W, int32_t H,
+                         int32_t dtype, void *C, void *stream) {
+    if (!F || !alpha || !B || !C || W < 1 || H < 1 || W > fge::kMaxSide || H > fge::kMaxSide)
+        return FGE_EINVAL;
+    if (dtype != FGE_F32 && dtype != FGE_F16) return FGE_EINVAL;
+    const size_t n = static_cast<size_t>(W) * H;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const dim3 grid(static_cast<unsigned>((n + 255) / 256));
+    if (dtype == FGE_F16)
+        hipLaunchKernelGGL(fge::composite_kernel<_Float16>, grid, dim3(256), 0, s,
+                           static_cast<const _Float16 *>(F), static_cast<const _Float16 *>(alpha),
+                           static_cast<const _Float16 *>(B), static_cast<_Float16 *>(C), n);
+    else
+        hipLaunchKernelGGL(fge::composite_kernel<float>, grid, dim3(256), 0, s,
+                           static_cast<const float *>(F), static_cast<const float *>(alpha),
+                           static_cast<const float *>(B), static_cast<float *>(C), n);
+    return hipGetLastError() == hipSuccess ? FGE_OK : FGE_EHIP;
 }
 
 fge_status fge_hwc_to_planar(const void *src, int32_t src_dtype, int32_t channels, int32_t W,

@@ -157,6 +157,12 @@ def _lib():
     lib.fge_energy_workspace_bytes.restype = sz
     lib.fge_energy.argtypes = [vp, vp, vp, vp, i32, i32, pp, vp, vp, sz, vp]
     lib.fge_energy.restype = ctypes.c_int
+    lib.fge_quality_workspace_bytes.argtypes = [i32, i32]
+    lib.fge_quality_workspace_bytes.restype = sz
+    lib.fge_quality.argtypes = [vp, vp, vp, i32, i32, i32, ctypes.c_double, vp, vp, sz, vp]
+    lib.fge_quality.restype = ctypes.c_int
+    lib.fge_composite.argtypes = [vp, vp, vp, i32, i32, i32, vp, vp]
+    lib.fge_composite.restype = ctypes.c_int
     lib.fge_hwc_to_planar.argtypes = [vp, i32, i32, i32, i32, vp, vp, i32, vp]
     lib.fge_hwc_to_planar.restype = ctypes.c_int
     lib.fge_planar_to_hwc.argtypes = [vp, i32, i32, i32, vp, i32, vp]
@@ -705,3 +711,38 @@ def estimate_foreground_converge(I, alpha, params: Params | None = None, tol: fl
         F.data_ptr(), B.data_ptr(), sweeps.data_ptr(), ws.data_ptr(), ws.numel(),
         _stream_ptr(stream)), "fge_estimate_foreground_converge")
     return F, B, sweeps[:n]
+
+
+def quality(F, G, alpha, sigma: float = 1.4, stream=None, out=None):
+    """The paper's error measures of F against the reference G over the translucent pixels of
+    `alpha`, weighted by alpha (fge_quality): a float64 CUDA tensor [SAD, MSE, GRAD, count]."""
+    import torch
+    if F.dim() != 3 or F.shape[0] != 3:
+        raise ValueError("F must be (3, H, W)")
+    _, H, W = F.shape
+    for name, t, shp in (("F", F, (3, H, W)), ("G", G, (3, H, W)), ("alpha", alpha, (H, W))):
+        if tuple(t.shape) != shp or t.dtype != F.dtype or not t.is_cuda or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous CUDA tensor {shp} of dtype {F.dtype}")
+    if out is None:
+        out = torch.empty(4, dtype=torch.float64, device=F.device)
+    ws = torch.empty(_lib().fge_quality_workspace_bytes(W, H), dtype=torch.uint8, device=F.device)
+    _check(_lib().fge_quality(F.data_ptr(), G.data_ptr(), alpha.data_ptr(), W, H,
+                              _dtype_code(F.dtype), float(sigma), out.data_ptr(), ws.data_ptr(),
+                              ws.numel(), _stream_ptr(stream)), "fge_quality")
+    return out
+
+
+def composite(F, alpha, B, stream=None):
+    """alpha F + (1 - alpha) B on the device (fge_composite)."""
+    import torch
+    if F.dim() != 3 or F.shape[0] != 3:
+        raise ValueError("F must be (3, H, W)")
+    _, H, W = F.shape
+    for name, t, shp in (("F", F, (3, H, W)), ("alpha", alpha, (H, W)), ("B", B, (3, H, W))):
+        if tuple(t.shape) != shp or t.dtype != F.dtype or not t.is_cuda or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous CUDA tensor {shp} of dtype {F.dtype}")
+    C = torch.empty_like(F)
+    _check(_lib().fge_composite(F.data_ptr(), alpha.data_ptr(), B.data_ptr(), W, H,
+                                _dtype_code(F.dtype), C.data_ptr(), _stream_ptr(stream)),
+           "fge_composite")
+    return C

@@ -284,3 +284,17 @@ def test_jacobi_and_converge_host_side(fge):
     h = ctypes.c_void_p()
     assert lib.fge_server_create(ctypes.byref(pj), None, 0x100000, 1 << 30, 0x10,
                                  ctypes.byref(h)) == fge.FGE_EUNSUPPORTED
+
+
+def test_quality_argument_errors(fge):
+    lib = fge.load()
+    a = 0x100000
+    nw = lib.fge_quality_workspace_bytes(64, 64)
+    assert nw == 16 * 4 * 8          # 16 blocks of 256 pixels, 4 partial sums each
+    assert lib.fge_quality(a, a, a, 64, 64, fge.U8, 1.4, a, a, nw, None) == fge.FGE_EINVAL
+    assert lib.fge_quality(a, a, a, 64, 64, fge.F32, 0.0, a, a, nw, None) == fge.FGE_EINVAL
+    assert lib.fge_quality(a, a, a, 64, 64, fge.F32, 5.0, a, a, nw, None) == fge.FGE_EINVAL
+    assert lib.fge_quality(a, a, a, 64, 64, fge.F32, 1.4, a, None, 0, None) == fge.FGE_EWORKSPACE
+    assert lib.fge_quality(None, a, a, 64, 64, fge.F32, 1.4, a, a, nw, None) == fge.FGE_EINVAL
+    assert lib.fge_composite(a, a, a, 64, 64, fge.U8, a, None) == fge.FGE_EINVAL
+    assert lib.fge_composite(a, a, a, 0, 64, fge.F32, a, None) == fge.FGE_EINVAL

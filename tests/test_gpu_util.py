@@ -74,3 +74,40 @@ def test_layout_conversions_bit_exact(gpu):
     # the round trip of 8-bit values is exact
     rt = fge.planar_to_hwc(I).cpu().numpy()
     assert np.array_equal(rt, u8[..., :3])
+
+
+@pytest.mark.parametrize("wh", [(1, 1), (3, 2), (19, 13), (300, 200), (1024, 768)])
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_quality_matches_oracle(gpu, wh, storage):
+    torch, fge = gpu
+    from oracle import metrics
+    W, H = wh
+    dt = torch.float16 if storage == "f16" else torch.float32
+    s = synth.strands(W, H, seed=W + 2 * H, n_strands=max(1, W * H // 4000))
+    rng = np.random.default_rng(W * H)
+    a = torch.from_numpy(np.clip(s.alpha + rng.uniform(-0.05, 0.05, s.alpha.shape), 0, 1)).to(dt).cuda()
+    G = torch.from_numpy(s.F).to(dt).cuda()
+    F = torch.from_numpy(np.clip(s.F + rng.normal(0, 0.05, s.F.shape), 0, 1)).to(dt).cuda()
+    out = fge.quality(F, G, a).cpu().numpy()
+    sad, mse, grad, n = metrics.quality(F.double().cpu().numpy(), G.double().cpu().numpy(),
+                                        a.double().cpu().numpy())
+    print(f"{W}x{H} {storage}: SAD {out[0]:.6g} MSE {out[1]:.6g} GRAD {out[2]:.6g} n {out[3]:.0f}")
+    assert out[3] == n
+    for got, want in ((out[0], sad), (out[1], mse), (out[2], grad)):
+        assert abs(got - want) <= 1e-10 * max(1e-30, abs(want)), (got, want)
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_composite_bit_exact(gpu, storage):
+    torch, fge = gpu
+    from oracle import metrics
+    dt = torch.float16 if storage == "f16" else torch.float32
+    rng = np.random.default_rng(12)
+    H, W = 77, 131
+    F = torch.from_numpy(rng.uniform(0, 1, (3, H, W))).to(dt).cuda()
+    a = torch.from_numpy(rng.uniform(0, 1, (H, W))).to(dt).cuda()
+    B = torch.from_numpy(rng.uniform(0, 1, (3, H, W))).to(dt).cuda()
+    C = fge.composite(F, a, B).cpu().numpy()
+    want = metrics.composite(F.double().cpu().numpy(), a.double().cpu().numpy(),
+                             B.double().cpu().numpy()).astype(np.float16 if storage == "f16" else np.float32)
+    assert np.array_equal(C, want)
