@@ -83,7 +83,9 @@ typedef struct fge_params {
     int32_t kernel;         /* fge_kernel */
     int32_t strip_rows;     /* fused kernel: output rows per wave strip; 0 = automatic */
     int32_t coarse_max_px;  /* levels with w*h <= this (and all smaller ones) run in the
-                               LDS-resident coarse kernel; 0 = automatic (4096), -1 = never */
+                               LDS-resident coarse kernel (at most 4096); 0 = automatic (the
+                               levels up to 1024 px and every level whose sweep count is not 2),
+                               -1 = never */
     int32_t tile_max_px;    /* fine levels with w*h <= this use the LDS tile kernel, larger ones
                                the streaming kernel; 0 = automatic (2^18), -1 = never */
 } fge_params;

@@ -11,6 +11,7 @@ namespace fge {
 constexpr int kMaxLevels = 16;         // 32767 needs 15 levels
 constexpr int kMaxSide = 32767;        // keeps x * w_src inside int32
 constexpr int kCoarseMaxPx = 4096;     // LDS-resident coarse levels: 2 float4 per pixel = 128 KB
+constexpr int kCoarseAutoPx = 1024;    // automatic coarse limit (plus all low-resolution levels)
 constexpr int kCoarseThreads = 512;
 constexpr int kCoarsePairsPerThread = 4;   // a coarse level has at most 2048 pixel pairs
 constexpr int kCoarseMaxPairs = kCoarseThreads * kCoarsePairsPerThread;

@@ -72,6 +72,17 @@ __device__ __forceinline__ float from_right(float v, float self) {
                                                       0x130, 0xF, 0xF, false));
 }
 
+// floor(num / den) for 0 <= num < 2^30 and 1 <= den <= 32767 with a quotient below 32768 (every
+// nearest-neighbour map and index split here).  gfx950 has no integer divide; the float estimate
+// num * rcp(den) is within 0.01 of num / den (input rounding 2^-24 and rcp 1 ulp, times a
+// quotient below 2^15), so one correction step each way makes it exact.  rden = rcp(den).
+__device__ __forceinline__ int fdiv(int num, int den, float rden) {
+    int q = static_cast<int>(static_cast<float>(num) * rden);
+    const int r = num - q * den;
+    q += r < 0 ? -1 : (r >= den ? 1 : 0);
+    return q;
+}
+
 __device__ __forceinline__ float weight(float a, float b, float omega, float eps) {
     return fmaf(omega, fabsf(a - b), eps);
 }
@@ -97,13 +108,16 @@ __device__ __forceinline__ void coarse_gather_inputs(const CoarseArgs &args, int
     const T *A = static_cast<const T *>(args.src.A[l]);
     const int W = args.src.W[l], H = args.src.H[l];
     const size_t planeI = static_cast<size_t>(W) * H;
+    const bool same = W == w && H == h;   // a compact copy of the level: identity map
+    const float rw = rcp(static_cast<float>(w)), rh = rcp(static_cast<float>(h));
 #pragma unroll
     for (int k = 0; k < kCoarsePairsPerThread; ++k) {
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
             const bool ok = s == 0 ? pr[k].valid0 : pr[k].valid1;
             const int x = ok ? pr[k].x0 + s : 0, y = ok ? pr[k].y : 0;
-            const size_t src = static_cast<size_t>(y * H / h) * W + x * W / w;
+            const size_t src = same ? static_cast<size_t>(y) * W + x
+                                    : static_cast<size_t>(fdiv(y * H, h, rh)) * W + fdiv(x * W, w, rw);
             na[k][s] = ldf(A + src);
 #pragma unroll
             for (int c = 0; c < 3; ++c) ni[k][s][c] = ldf(I + c * planeI + src);
@@ -114,10 +128,11 @@ __device__ __forceinline__ void coarse_gather_inputs(const CoarseArgs &args, int
 __device__ __forceinline__ void coarse_pairs(int tid, int w, int h,
                                              CoarsePair (&pr)[kCoarsePairsPerThread]) {
     const int pw = (w + 1) >> 1;
+    const float rpw = rcp(static_cast<float>(pw));
 #pragma unroll
     for (int k = 0; k < kCoarsePairsPerThread; ++k) {
         const int q = tid + k * kCoarseThreads;
-        const int y = q / pw;
+        const int y = fdiv(q, pw, rpw);
         const int j = q - y * pw;
         pr[k].y = y;
         pr[k].x0 = 2 * j;
@@ -141,15 +156,21 @@ __device__ __forceinline__ void coarse_body(const CoarseArgs &args, CoarseLds &l
     const int tid = threadIdx.x;
     const float omega = args.omega, eps = args.eps;
 
+    const int wave_q0 = uniform(tid & ~63);   // first pair index of this wave in slot 0
     CoarsePair pr[kCoarsePairsPerThread];
     float iv[kCoarsePairsPerThread][2][3], av[kCoarsePairsPerThread][2];
     float ni[kCoarsePairsPerThread][2][3], na[kCoarsePairsPerThread][2];
     coarse_pairs(tid, args.lw[0], args.lh[0], pr);
     coarse_gather_inputs<T>(args, 0, args.lw[0], args.lh[0], pr, ni, na);
 
+    // A pair slot k is live in a wave when some lane of the wave owns a pair of the level there;
+    // the LDS stores, the per-level constants and the sweeps of dead slots are skipped as a
+    // whole (a uniform test).  (Skipping the resize reads and the input gathers too would spill.)
     int wp = 1, hp = 1;
     for (int l = 0; l < args.nc; ++l) {
         const int w = args.lw[l], h = args.lh[l], iters = args.lit[l];
+        const int npairs = ((w + 1) >> 1) * h;
+        auto live = [&](int k) { return k * kCoarseThreads + wave_q0 < npairs; };
 #pragma unroll
         for (int k = 0; k < kCoarsePairsPerThread; ++k)
 #pragma unroll
@@ -161,14 +182,15 @@ __device__ __forceinline__ void coarse_body(const CoarseArgs &args, CoarseLds &l
         // Resize F and B from the previous level (the 1x1 zero start before level 0): gather
         // into registers, then overwrite LDS with the new level.
         float4 rf[kCoarsePairsPerThread][2], rb[kCoarsePairsPerThread][2];
+        const float rw = rcp(static_cast<float>(w)), rh = rcp(static_cast<float>(h));
 #pragma unroll
-        for (int k = 0; k < kCoarsePairsPerThread; ++k)
+        for (int k = 0; k < kCoarsePairsPerThread; ++k) {
 #pragma unroll
             for (int s = 0; s < 2; ++s) {
                 rf[k][s] = make_float4(0.f, 0.f, 0.f, av[k][s]);
                 rb[k][s] = make_float4(0.f, 0.f, 0.f, 0.f);
                 const bool ok = (s == 0 ? pr[k].valid0 : pr[k].valid1) && l > 0;
-                const int q = ok ? (pr[k].y * hp / h) * wp + (pr[k].x0 + s) * wp / w : 0;
+                const int q = ok ? fdiv(pr[k].y * hp, h, rh) * wp + fdiv((pr[k].x0 + s) * wp, w, rw) : 0;
                 const float4 f = sFA[q];
                 const float4 g = sB[q];
                 if (ok) {
@@ -176,9 +198,11 @@ __device__ __forceinline__ void coarse_body(const CoarseArgs &args, CoarseLds &l
                     rb[k][s] = g;
                 }
             }
+        }
         lds_sync();
 #pragma unroll
-        for (int k = 0; k < kCoarsePairsPerThread; ++k)
+        for (int k = 0; k < kCoarsePairsPerThread; ++k) {
+            if (!live(k)) continue;
 #pragma unroll
             for (int s = 0; s < 2; ++s) {
                 const bool ok = s == 0 ? pr[k].valid0 : pr[k].valid1;
@@ -187,6 +211,7 @@ __device__ __forceinline__ void coarse_body(const CoarseArgs &args, CoarseLds &l
                     sB[pr[k].p0 + s] = rb[k][s];
                 }
             }
+        }
         // Start the next level's input gather now; it completes during this level's sweeps.
         CoarsePair nx[kCoarsePairsPerThread];
         if (l + 1 < args.nc) {
@@ -203,6 +228,7 @@ __device__ __forceinline__ void coarse_body(const CoarseArgs &args, CoarseLds &l
         float ca[kCoarsePairsPerThread][2], ci[kCoarsePairsPerThread][2][3];
 #pragma unroll
         for (int k = 0; k < kCoarsePairsPerThread; ++k) {
+            if (!live(k)) continue;
             int tnb[2][4];
             float tw[2][4], tka[2], tkb[2];
 #pragma unroll
@@ -251,14 +277,7 @@ __device__ __forceinline__ void coarse_body(const CoarseArgs &args, CoarseLds &l
         // lane of the wave uses are skipped as a whole (a uniform test); inside a slot the
         // reads and the arithmetic are unconditional (indices are clamped), only the store is
         // guarded, so the slot's LDS reads are all in flight together.
-        const int npairs = ((w + 1) >> 1) * h;
-        const int wave_q0 = uniform(tid & ~63);   // first pair index of this wave in slot 0
-        for (int it = 0; it < iters; ++it) {
-#pragma unroll
-            for (int c = 0; c < 2; ++c) {
-#pragma unroll
-                for (int k = 0; k < kCoarsePairsPerThread; ++k) {
-                    if (k * kCoarseThreads + wave_q0 < npairs) {   // uniform: this wave has work
+        auto update = [&](int k, int c) {
                         float fb[3] = {0.f, 0.f, 0.f}, bb[3] = {0.f, 0.f, 0.f};
 #pragma unroll
                         for (int j = 0; j < 4; ++j) {
@@ -284,9 +303,32 @@ __device__ __forceinline__ void coarse_body(const CoarseArgs &args, CoarseLds &l
                             sFA[cpix[k][c]] = make_float4(fo[0], fo[1], fo[2], a);
                             sB[cpix[k][c]] = make_float4(bo[0], bo[1], bo[2], 0.0f);
                         }
+        };
+        if (npairs <= 64) {
+            // The whole level is slot 0 of wave 0.  A wave's LDS operations execute in order, so
+            // its half-sweeps need no workgroup barrier, only an ordering point for the compiler;
+            // the other waves wait at the barrier that ends the level.
+            if (uniform(tid >> 6) == 0) {
+                for (int it = 0; it < iters; ++it) {
+#pragma unroll
+                    for (int c = 0; c < 2; ++c) {
+                        update(0, c);
+                        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+                        __builtin_amdgcn_wave_barrier();
+                        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
                     }
                 }
-                lds_sync();
+            }
+            lds_sync();
+        } else {
+            for (int it = 0; it < iters; ++it) {
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+#pragma unroll
+                    for (int k = 0; k < kCoarsePairsPerThread; ++k)
+                        if (live(k)) update(k, c);
+                    lds_sync();
+                }
             }
         }
         if (l + 1 < args.nc) {
@@ -372,6 +414,9 @@ __device__ __forceinline__ void tile_body(const TileArgs &args, int tile, TileLd
     const int rw = min(w, cx1 + kTileHalo) - rx0, rh = min(h, cy1 + kTileHalo) - ry0;
     const int pw = (rw + 1) >> 1;
     const int npairs = pw * rh;
+    const float rpw = rcp(static_cast<float>(pw));
+    const float rcw = rcp(static_cast<float>(w)), rch = rcp(static_cast<float>(h));
+    const bool same = args.W == w && args.H == h;   // compact copy or the full-size level
 
     // Owned pairs: q = tid + k * threads covers region columns (2j, 2j+1) of region row y.
     // All global gathers are issued before any LDS store, so they are in flight together.
@@ -382,7 +427,7 @@ __device__ __forceinline__ void tile_body(const TileArgs &args, int tile, TileLd
 #pragma unroll
     for (int k = 0; k < kTilePairsPerThread; ++k) {
         const int q = tid + k * kTileThreads;
-        const int y = q / pw;
+        const int y = fdiv(q, pw, rpw);
         qy[k] = y;
         qx[k] = 2 * (q - y * pw);
         qv0[k] = q < npairs;
@@ -391,8 +436,11 @@ __device__ __forceinline__ void tile_body(const TileArgs &args, int tile, TileLd
         for (int s = 0; s < 2; ++s) {
             const bool ok = s ? qv1[k] : qv0[k];
             const int gx = rx0 + (ok ? qx[k] + s : 0), gy = ry0 + (ok ? y : 0);
-            const size_t src = static_cast<size_t>(gy * args.H / h) * args.W + gx * args.W / w;
-            const size_t prv = static_cast<size_t>(gy * args.hp / h) * args.wp + gx * args.wp / w;
+            const size_t src = same ? static_cast<size_t>(gy) * w + gx
+                                    : static_cast<size_t>(fdiv(gy * args.H, h, rch)) * args.W +
+                                          fdiv(gx * args.W, w, rcw);
+            const size_t prv = static_cast<size_t>(fdiv(gy * args.hp, h, rch)) * args.wp +
+                               fdiv(gx * args.wp, w, rcw);
             const float a = ldf(A + src);
 #pragma unroll
             for (int c = 0; c < 3; ++c) iv[k][s][c] = ldf(I + c * planeI + src);
@@ -508,8 +556,9 @@ __device__ __forceinline__ void tile_body(const TileArgs &args, int tile, TileLd
     T *Bo = static_cast<T *>(args.Bo);
     const size_t planeO = static_cast<size_t>(w) * h;
     const int cw_ = cx1 - cx0, ch_ = cy1 - cy0;
+    const float rcw_ = rcp(static_cast<float>(cw_));
     for (int p = tid; p < cw_ * ch_; p += kTileThreads) {
-        const int yy = p / cw_, xx = p - yy * cw_;
+        const int yy = fdiv(p, cw_, rcw_), xx = p - yy * cw_;
         const int gx = cx0 + xx, gy = cy0 + yy;
         const int li = (gy - ry0) * rw + (gx - rx0);
         const float4 f = sFA[li], g = sB[li];
@@ -1189,9 +1238,10 @@ __device__ __forceinline__ void gather_body(const GatherArgs &args, long long p)
     while (l + 1 < args.ng && p >= args.first[l + 1]) ++l;
     const int w = args.lw[l], h = args.lh[l];
     const int q = static_cast<int>(p - args.first[l]);
-    const int y = q / w, x = q - y * w;
+    const float rw = rcp(static_cast<float>(w)), rh = rcp(static_cast<float>(h));
+    const int y = fdiv(q, w, rw), x = q - y * w;
     const size_t planeI = static_cast<size_t>(args.W) * args.H;
-    const size_t src = static_cast<size_t>(y * args.H / h) * args.W + x * args.W / w;
+    const size_t src = static_cast<size_t>(fdiv(y * args.H, h, rh)) * args.W + fdiv(x * args.W, w, rw);
     const T *I = static_cast<const T *>(args.I);
     T *dst = reinterpret_cast<T *>(args.pyr + args.off[l]);
     const size_t n = static_cast<size_t>(w) * h;

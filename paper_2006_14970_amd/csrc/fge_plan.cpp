@@ -54,19 +54,30 @@ fge_status make_plan(int W, int H, const fge_params &p, Plan *out) {
         const bool small = w <= p.small_size && h <= p.small_size;
         pl.lv[i] = {w, h, small ? p.iters_small : p.iters_big};
     }
-    // Coarse block: the longest prefix of levels with w*h <= limit (sizes grow with l).
     // The coarse block and the fused fine kernels sweep in red-black order; the Jacobi order
     // runs every level on per-level kernels.
     const bool jacobi = p.order == FGE_JACOBI;
     if (jacobi && p.kernel == FGE_KERNEL_FUSED) return FGE_EUNSUPPORTED;
-    const int limit = jacobi ? -1 : (p.coarse_max_px == 0 ? kCoarseMaxPx : p.coarse_max_px);
+    // Coarse block: the longest prefix of levels with w*h <= limit (sizes grow with l).  The
+    // automatic limit keeps the block to the levels up to 1024 px -- larger ones run faster on
+    // the tile kernel, spread over several workgroups -- plus every level whose sweep count is
+    // not 2, which only the block or the per-level kernels can run (low-resolution levels when
+    // small_size exceeds 32).
+    const bool auto_limit = p.coarse_max_px == 0;
+    const int limit = jacobi ? -1 : (auto_limit ? kCoarseAutoPx : p.coarse_max_px);
     pl.nc = 0;
-    // A coarse level must also have at most kCoarseMaxPairs pairs of columns (thin levels of
-    // odd width can exceed that while still having <= 4096 pixels).
+    // A coarse level must also fit the block's LDS (kCoarseMaxPx pixels) and have at most
+    // kCoarseMaxPairs pairs of columns (thin levels of odd width can exceed that while still
+    // having <= 4096 pixels).
     if (limit > 0)
-        while (pl.nc < pl.n && static_cast<long>(pl.lv[pl.nc].w) * pl.lv[pl.nc].h <= limit &&
-               static_cast<long>((pl.lv[pl.nc].w + 1) / 2) * pl.lv[pl.nc].h <= kCoarseMaxPairs)
+        while (pl.nc < pl.n) {
+            const long px = static_cast<long>(pl.lv[pl.nc].w) * pl.lv[pl.nc].h;
+            const bool fits = px <= kCoarseMaxPx &&
+                              static_cast<long>((pl.lv[pl.nc].w + 1) / 2) * pl.lv[pl.nc].h <= kCoarseMaxPairs;
+            const bool wanted = px <= limit || (auto_limit && pl.lv[pl.nc].iters != 2);
+            if (!fits || !wanted) break;
             ++pl.nc;
+        }
     // Fine levels: the fused kernels (tile and streaming) implement exactly two sweeps per
     // level and need a previous level; mid-size levels take the tile kernel, large ones the
     // streaming kernel.

@@ -82,10 +82,15 @@ def test_bad_sizes(fge):
 
 def test_coarse_split(fge):
     info = fge.plan(4096, 3072)
-    assert info.n_coarse == 6            # up to 64x55 = 3520 px <= 4096
-    assert fge.plan(64, 64).n_coarse == 6
+    assert info.n_coarse == 5            # the automatic limit: up to 32x28 (<= 1024 px)
+    assert fge.plan(64, 64).n_coarse == 5
     assert fge.plan(4096, 3072, fge.default_params(coarse_max_px=-1)).n_coarse == 0
+    assert fge.plan(4096, 3072, fge.default_params(coarse_max_px=4096)).n_coarse == 6
     assert fge.plan(4096, 3072, fge.default_params(coarse_max_px=1024)).n_coarse == 5
+    assert fge.plan(64, 64, fge.default_params(coarse_max_px=4096)).n_coarse == 6
+    # with a larger low-resolution threshold the 10-sweep levels stay in the block (to 4096 px)
+    big = fge.plan(4096, 3072, fge.default_params(small_size=64))
+    assert big.n_coarse == 6 and big.levels[5][2] == 10
 
 
 def test_workspace_sizes(fge):
@@ -101,7 +106,7 @@ def test_workspace_sizes(fge):
             # two ping-pong state buffers plus the compact copies of the small levels' inputs
             small = sum(q for q in px if q <= 65536) if W * H > 65536 else 0
             assert need32 <= 6 * 4 * (px[-2] + px[-3]) + 16 * small + 256 * (len(px) + 2)
-    assert fge.workspace_bytes(64, 64) == 0          # whole pyramid in the coarse kernel
+    assert fge.workspace_bytes(64, 64, fge.default_params(coarse_max_px=4096)) == 0   # all coarse
 
 
 def _call(fge, W, H, p, I=0x1000, A=0x2000, F=0x3000, B=0x4000, ws=None, ws_len=0):
