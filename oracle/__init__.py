@@ -73,6 +73,12 @@ def _load():
     lib.fgo_ml_schedule.restype = i32
     lib.fgo_ml_converge.argtypes = [dp, dp, i32, i32, f64, f64, i32, f64, i32, ip, dp, dp]
     lib.fgo_ml_converge.restype = i32
+    lib.fgo_resize_area.argtypes = [dp, i32, i32, i32, dp, i32, i32]
+    lib.fgo_resize_area.restype = None
+    lib.fgo_resize_bilinear.argtypes = [dp, i32, i32, i32, dp, i32, i32]
+    lib.fgo_resize_bilinear.restype = None
+    lib.fgo_ml_resize.argtypes = [dp, dp, i32, i32, f64, f64, i32, i32, ip, dp, dp]
+    lib.fgo_ml_resize.restype = i32
     _lib = lib
     return lib
 
@@ -194,3 +200,47 @@ def ml_converge(I: np.ndarray, alpha: np.ndarray, tol: float, max_sweeps: int,
     _load().fgo_ml_converge(_ptr(I), _ptr(a), W, H, float(omega), float(eps), ORDERS[order],
                             float(tol), int(max_sweeps), sw, _ptr(F), _ptr(B))
     return F, B, list(sw)
+
+
+RESIZES = {"nearest": 0, "smooth": 1}
+
+
+def _resize_with(fn, src, wd, hd):
+    s = _f64c(src)
+    squeeze = s.ndim == 2
+    if squeeze:
+        s = s[None]
+    p, hs, ws = s.shape
+    d = np.empty((p, hd, wd), dtype=np.float64)
+    fn(_ptr(s), ws, hs, p, _ptr(d), wd, hd)
+    return d[0] if squeeze else d
+
+
+def resize_area(src: np.ndarray, wd: int, hd: int) -> np.ndarray:
+    """Area (overlap-weighted mean) resize of a (P, hs, ws) or (hs, ws) array."""
+    return _resize_with(_load().fgo_resize_area, src, wd, hd)
+
+
+def resize_bilinear(src: np.ndarray, wd: int, hd: int) -> np.ndarray:
+    """Bilinear resize with half-integer pixel centres, clamped at the borders."""
+    return _resize_with(_load().fgo_resize_bilinear, src, wd, hd)
+
+
+def ml_resize(I: np.ndarray, alpha: np.ndarray, resize: str = "smooth", sweeps=None,
+              omega: float = 0.1, eps: float = 5e-3, order: str = "redblack"):
+    """Algorithm 1 with the resize variant ("nearest" or "smooth": area for I and alpha, bilinear
+    for F and B) and per-level sweep counts (default: the fixed 10 / 2 rule)."""
+    I = _f64c(I)
+    a = _f64c(alpha)
+    _, H, W = I.shape
+    if sweeps is None:
+        sweeps = [it for _, _, it in level_plan(W, H)]
+    n = num_levels(W, H)
+    if len(sweeps) != n:
+        raise ValueError(f"{n} levels, {len(sweeps)} sweep counts")
+    sw = (ctypes.c_int * n)(*[int(k) for k in sweeps])
+    F = np.empty((3, H, W), dtype=np.float64)
+    B = np.empty((3, H, W), dtype=np.float64)
+    _load().fgo_ml_resize(_ptr(I), _ptr(a), W, H, float(omega), float(eps), ORDERS[order],
+                          RESIZES[resize], sw, _ptr(F), _ptr(B))
+    return F, B

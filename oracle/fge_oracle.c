@@ -361,3 +361,131 @@ int fgo_ml_converge(const double *I, const double *a, int W, int H, double omega
     free(Bp);
     return n;
 }
+
+/*
+ * The smooth resize variant (the paper leaves the resize kernel open).
+ *
+ * Area resize: destination pixel (x, y) is the mean of the source over its footprint
+ * [x ws/wd, (x+1) ws/wd) x [y hs/hd, (y+1) hs/hd), every source pixel weighted by its overlap
+ * with it.  The weights are separable: the 1-D overlap of source index i with destination
+ * interval [x0, x1) is max(0, min(i + 1, x1) - max(i, x0)), divided by the interval length.
+ */
+static void area_weights(int ns, int nd, int x, int *lo, int *hi, double *w)
+{
+    double x0 = (double)x * ns / nd, x1 = (double)(x + 1) * ns / nd;
+    int i0 = (int)floor(x0), i1 = (int)ceil(x1);
+    if (i1 > ns) i1 = ns;
+    *lo = i0;
+    *hi = i1;
+    for (int i = i0; i < i1; i++) {
+        double a = i > x0 ? i : x0, b = i + 1 < x1 ? i + 1 : x1;
+        w[i - i0] = (b - a) / (x1 - x0);
+    }
+}
+
+void fgo_resize_area(const double *src, int ws, int hs, int planes, double *dst, int wd, int hd)
+{
+    double *wx = (double *)malloc(((size_t)ws + 2) * sizeof(double));
+    double *wy = (double *)malloc(((size_t)hs + 2) * sizeof(double));
+    for (int c = 0; c < planes; c++) {
+        for (int y = 0; y < hd; y++) {
+            int ylo, yhi;
+            area_weights(hs, hd, y, &ylo, &yhi, wy);
+            for (int x = 0; x < wd; x++) {
+                int xlo, xhi;
+                area_weights(ws, wd, x, &xlo, &xhi, wx);
+                double acc = 0.0;
+                for (int j = ylo; j < yhi; j++)
+                    for (int i = xlo; i < xhi; i++)
+                        acc += wy[j - ylo] * wx[i - xlo] * src[(size_t)c * ws * hs + (size_t)j * ws + i];
+                dst[(size_t)c * wd * hd + (size_t)y * wd + x] = acc;
+            }
+        }
+    }
+    free(wx);
+    free(wy);
+}
+
+/*
+ * Bilinear resize with pixel centres at half-integers: the destination pixel x samples source
+ * coordinate u = (x + 1/2) ws/wd - 1/2, clamped to [0, ws - 1]; it mixes source pixels floor(u)
+ * and floor(u) + 1 (clamped) with weights 1 - (u - floor(u)) and u - floor(u); likewise in y.
+ */
+static void bilinear_tap(int ns, int nd, int x, int *i0, int *i1, double *f)
+{
+    double u = ((double)x + 0.5) * ns / nd - 0.5;
+    if (u < 0.0) u = 0.0;
+    if (u > ns - 1) u = ns - 1;
+    *i0 = (int)floor(u);
+    *i1 = *i0 + 1 < ns ? *i0 + 1 : ns - 1;
+    *f = u - *i0;
+}
+
+void fgo_resize_bilinear(const double *src, int ws, int hs, int planes, double *dst, int wd, int hd)
+{
+    for (int c = 0; c < planes; c++) {
+        const double *s = src + (size_t)c * ws * hs;
+        for (int y = 0; y < hd; y++) {
+            int y0, y1;
+            double fy;
+            bilinear_tap(hs, hd, y, &y0, &y1, &fy);
+            for (int x = 0; x < wd; x++) {
+                int x0, x1;
+                double fx;
+                bilinear_tap(ws, wd, x, &x0, &x1, &fx);
+                double top = (1.0 - fx) * s[(size_t)y0 * ws + x0] + fx * s[(size_t)y0 * ws + x1];
+                double bot = (1.0 - fx) * s[(size_t)y1 * ws + x0] + fx * s[(size_t)y1 * ws + x1];
+                dst[(size_t)c * wd * hd + (size_t)y * wd + x] = (1.0 - fy) * top + fy * bot;
+            }
+        }
+    }
+}
+
+/*
+ * Algorithm 1 with the resize variant `resize` (0: nearest, as fgo_ml; 1: smooth -- area for the
+ * full-resolution image and matte, bilinear for the previous level's F and B) and sweeps[l-1]
+ * sweeps at level l.
+ */
+int fgo_ml_resize(const double *I, const double *a, int W, int H, double omega, double eps,
+                  int order, int resize, const int *sweeps, double *F, double *B)
+{
+    const int n = fgo_num_levels(W, H);
+    int wp = 1, hp = 1;
+    double *Fp = (double *)calloc(3, sizeof(double));
+    double *Bp = (double *)calloc(3, sizeof(double));
+    for (int l = 1; l <= n; l++) {
+        int w = fgo_level_size(W, l, n);
+        int h = fgo_level_size(H, l, n);
+        size_t plane = (size_t)w * h;
+        double *Il = (double *)malloc(3 * plane * sizeof(double));
+        double *al = (double *)malloc(plane * sizeof(double));
+        double *Fl = (double *)malloc(3 * plane * sizeof(double));
+        double *Bl = (double *)malloc(3 * plane * sizeof(double));
+        if (resize == 1) {
+            fgo_resize_area(I, W, H, 3, Il, w, h);
+            fgo_resize_area(a, W, H, 1, al, w, h);
+            fgo_resize_bilinear(Fp, wp, hp, 3, Fl, w, h);
+            fgo_resize_bilinear(Bp, wp, hp, 3, Bl, w, h);
+        } else {
+            fgo_resize_nearest(I, W, H, 3, Il, w, h);
+            fgo_resize_nearest(a, W, H, 1, al, w, h);
+            fgo_resize_nearest(Fp, wp, hp, 3, Fl, w, h);
+            fgo_resize_nearest(Bp, wp, hp, 3, Bl, w, h);
+        }
+        for (int it = 0; it < sweeps[l - 1]; it++)
+            fgo_sweep(Fl, Bl, Il, al, w, h, omega, eps, order);
+        free(Il);
+        free(al);
+        free(Fp);
+        free(Bp);
+        Fp = Fl;
+        Bp = Bl;
+        wp = w;
+        hp = h;
+    }
+    memcpy(F, Fp, 3 * (size_t)W * H * sizeof(double));
+    memcpy(B, Bp, 3 * (size_t)W * H * sizeof(double));
+    free(Fp);
+    free(Bp);
+    return n;
+}

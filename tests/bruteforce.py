@@ -61,6 +61,39 @@ def resize_bf(src: np.ndarray, wd: int, hd: int) -> np.ndarray:
     return src[:, ys][:, :, xs]
 
 
+def area_matrix(n_src: int, n_dst: int) -> np.ndarray:
+    """Area resize along one axis: row x holds the overlap of every source pixel [i, i+1) with
+    the destination footprint [x n_src/n_dst, (x+1) n_src/n_dst), divided by the footprint
+    length, computed in exact rationals."""
+    M = np.zeros((n_dst, n_src))
+    for x in range(n_dst):
+        lo, hi = Fraction(x * n_src, n_dst), Fraction((x + 1) * n_src, n_dst)
+        for i in range(n_src):
+            ov = min(Fraction(i + 1), hi) - max(Fraction(i), lo)
+            if ov > 0:
+                M[x, i] = float(ov / (hi - lo))
+    return M
+
+
+def bilinear_matrix(n_src: int, n_dst: int) -> np.ndarray:
+    """Bilinear resize along one axis with half-integer pixel centres, clamped at the borders."""
+    M = np.zeros((n_dst, n_src))
+    for x in range(n_dst):
+        u = min(max(Fraction(2 * x + 1, 2) * n_src / n_dst - Fraction(1, 2), 0), n_src - 1)
+        i0 = int(u)
+        f = u - i0
+        i1 = min(i0 + 1, n_src - 1)
+        M[x, i0] += float(1 - f)
+        M[x, i1] += float(f)
+    return M
+
+
+def resize_separable_bf(src: np.ndarray, wd: int, hd: int, matrix) -> np.ndarray:
+    p, hs, ws = src.shape
+    My, Mx = matrix(hs, hd), matrix(ws, wd)
+    return np.stack([My @ src[c] @ Mx.T for c in range(p)])
+
+
 def neighbours(x: int, y: int, w: int, h: int):
     """The four neighbours of Algorithm 1, clamped into the image."""
     out = []
@@ -123,18 +156,25 @@ def sweep_bf(F, B, I, a, omega=0.1, eps=5e-3, order="redblack"):
     return F, B
 
 
-def ml_bf(I, a, omega=0.1, eps=5e-3, small=32, it_small=10, it_big=2, order="redblack"):
-    """Algorithm 1 assembled from the helpers above (tiny images only)."""
+def ml_bf(I, a, omega=0.1, eps=5e-3, small=32, it_small=10, it_big=2, order="redblack",
+          resize="nearest"):
+    """Algorithm 1 assembled from the helpers above (tiny images only).  resize "smooth": area
+    resize of I and alpha, bilinear resize of F and B."""
     _, H, W = I.shape
     n = num_levels_exact(W, H)
     F = np.zeros((3, 1, 1))
     B = np.zeros((3, 1, 1))
+    if resize == "smooth":
+        down = lambda x, w, h: resize_separable_bf(x, w, h, area_matrix)       # noqa: E731
+        up = lambda x, w, h: resize_separable_bf(x, w, h, bilinear_matrix)     # noqa: E731
+    else:
+        down = up = resize_bf
     for lv in range(1, n + 1):
         w, h = level_size_exact(W, lv, n), level_size_exact(H, lv, n)
-        Il = resize_bf(I, w, h)
-        al = resize_bf(a[None], w, h)[0]
-        F = resize_bf(F, w, h)
-        B = resize_bf(B, w, h)
+        Il = down(I, w, h)
+        al = down(a[None], w, h)[0]
+        F = up(F, w, h)
+        B = up(B, w, h)
         iters = it_small if (w <= small and h <= small) else it_big
         for _ in range(iters):
             F, B = sweep_bf(F, B, Il, al, omega, eps, order)
