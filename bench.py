@@ -139,40 +139,42 @@ def run_storage(torch, fge, sample, storage, steps, warmup, oracle_F=None, oracl
     }
 
 
-def run_converge(torch, fge, sample, oracle_F=None):
-    """The convergence form of the level loop (tol 1e-4, at most 200 sweeps per level, red-black
-    and Jacobi, float16 storage) on the 4096x3072 image: time, sweeps per level, and quality
-    against the ground truth next to the fixed counts."""
+def run_variants(torch, fge, sample):
+    """The per-level-kernel variants of the level loop on the 4096x3072 image, float16 storage:
+    the convergence form (tol 1e-4, at most 200 sweeps per level) in red-black and Jacobi order,
+    and the smooth resize variant (area / bilinear) with the fixed counts and converged.  Each:
+    time, sweeps per level, and quality against the ground truth; the fused path's quality (nearest
+    resize, fixed counts) is the reference point."""
     dev = torch.device("cuda:0")
+    I = torch.from_numpy(sample.I).half().to(dev).contiguous()
+    a = torch.from_numpy(sample.alpha).half().to(dev).contiguous()
+    G = torch.from_numpy(sample.F).half().to(dev).contiguous()
     out = {}
-    G = None
-    for order_name, order in (("redblack", fge.REDBLACK), ("jacobi", fge.JACOBI)):
+    Ff, Bf = fge.estimate_foreground(I, a, fge.default_params(storage=fge.F16))
+    qf = fge.quality(Ff, G, a).cpu().numpy()
+    out["fused_fixed_counts_quality"] = {"SAD": float(qf[0]), "MSE": float(qf[1]), "GRAD": float(qf[2])}
+    cases = (("converge_redblack", fge.REDBLACK, "nearest", 1e-4),
+             ("converge_jacobi", fge.JACOBI, "nearest", 1e-4),
+             ("smooth_fixed_counts", fge.REDBLACK, "smooth", -1.0),
+             ("smooth_converge", fge.REDBLACK, "smooth", 1e-4))
+    for name, order, resize, tol in cases:
         p = fge.default_params(storage=fge.F16, order=order)
-        I = torch.from_numpy(sample.I).half().to(dev).contiguous()
-        a = torch.from_numpy(sample.alpha).half().to(dev).contiguous()
-        G = torch.from_numpy(sample.F).half().to(dev).contiguous()
-        fge.estimate_foreground_converge(I, a, p, tol=1e-4, max_sweeps=200)
+        fge.estimate_foreground_levels(I, a, p, resize=resize, tol=tol, max_sweeps=200)
         torch.cuda.synchronize()
         reps = 3
         t0 = time.perf_counter()
         for _ in range(reps):
-            F, B, sw = fge.estimate_foreground_converge(I, a, p, tol=1e-4, max_sweeps=200)
+            F, B, sw = fge.estimate_foreground_levels(I, a, p, resize=resize, tol=tol, max_sweeps=200)
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) / reps * 1e3
         q = fge.quality(F, G, a).cpu().numpy()
-        Ff, Bf = fge.estimate_foreground(I, a, p)
-        qf = fge.quality(Ff, G, a).cpu().numpy()
-        torch.cuda.synchronize()
-        out[order_name] = {"ms": ms, "value": W_IMG * H_IMG / 1e6 / (ms * 1e-3),
-                           "sweeps_per_level": sw.cpu().tolist(),
-                           "quality": {"SAD": float(q[0]), "MSE": float(q[1]), "GRAD": float(q[2])},
-                           "fixed_counts_quality": {"SAD": float(qf[0]), "MSE": float(qf[1]),
-                                                    "GRAD": float(qf[2])}}
-        log(f"  converge {order_name}: {ms:.1f} ms, sweeps {sw.cpu().tolist()}, SAD {q[0]:.1f} "
-            f"(fixed counts {qf[0]:.1f})")
-    return {"workload": "4096x3072 strands image, float16 storage, level loop until the level "
-                        "energy changes by at most 1e-4 (relative), at most 200 sweeps per level",
-            "unit": "MP/s", **out}
+        out[name] = {"ms": ms, "value": W_IMG * H_IMG / 1e6 / (ms * 1e-3),
+                     "sweeps_per_level": sw.cpu().tolist() if tol >= 0 else None,
+                     "quality": {"SAD": float(q[0]), "MSE": float(q[1]), "GRAD": float(q[2])}}
+        log(f"  {name}: {ms:.1f} ms, SAD {q[0]:.1f} (fused fixed counts {qf[0]:.1f})")
+    return {"workload": "4096x3072 strands image, float16 storage, per-level kernels: convergence "
+                        "form (level energy change <= 1e-4 relative, <= 200 sweeps per level) and "
+                        "the smooth resize variant", "unit": "MP/s", **out}
 
 
 def time_batch(torch, fge, sizes, p, Is, As, steps, warmup, stream):
@@ -375,7 +377,7 @@ def main():
                     help="skip the serving-stream (continuous batching, float16 storage) leg")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--no-converge", action="store_true",
-                    help="skip the convergence-form (while not converged) leg")
+                    help="skip the level-loop variants leg (convergence form, smooth resize)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 512 MiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -447,10 +449,10 @@ def main():
     s16 = summary(res["f16"], 2)
     s32["quality_vs_ground_truth"] = res["f32"]["quality"]
     s16["quality_vs_ground_truth"] = res["f16"]["quality"]
-    converge = None
+    variants = None
     if not args.no_converge:
-        log("convergence form of the level loop (float16 storage)")
-        converge = run_converge(torch, fge, sample)
+        log("level-loop variants: convergence form, smooth resize (float16 storage)")
+        variants = run_variants(torch, fge, sample)
     batch = None if args.no_batch else run_batch(torch, fge, synth, args, s32["value"],
                                                    not args.no_cpu_baseline)
     serving = None if args.no_serving else run_serving(torch, fge, synth, args, s32["value"],
@@ -477,7 +479,7 @@ def main():
         "fp16_store": s16,
         "level_ms_finest_first": s32["level_ms_finest_first"],
         "quality_vs_ground_truth": s32["quality_vs_ground_truth"],
-        "converge_fp16": converge,
+        "variants_fp16": variants,
         "batch_fp16": batch,
         "serving_fp16": serving,
         "cpu_baseline": cpu,

@@ -148,6 +148,30 @@ fge_status fge_estimate_foreground_converge(const void *I, const void *alpha, in
                                             void *F, void *B, int32_t *sweeps_out, void *workspace,
                                             size_t workspace_bytes, void *stream);
 
+/* Resize variant of the pyramid (the paper does not name the kernel).  NEAREST is the reading
+ * used everywhere; SMOOTH area-averages the full-resolution image and matte to every level (each
+ * level pixel is the overlap-weighted mean of its footprint) and resizes the previous level's F
+ * and B bilinearly (pixel centres at half-integers, clamped at the borders). */
+typedef enum fge_resize { FGE_RESIZE_NEAREST = 0, FGE_RESIZE_SMOOTH = 1 } fge_resize;
+
+typedef struct fge_level_options {
+    uint32_t size;         /* sizeof(fge_level_options) */
+    int32_t resize;        /* fge_resize */
+    double tol;            /* < 0: the fixed sweep counts; >= 0: the convergence form above */
+    int32_t max_sweeps;    /* convergence form: 1..100000 sweeps per level */
+    int32_t reserved0;
+} fge_level_options;
+
+/* The level loop on per-level kernels with these options (order from p->order): the general
+ * form of fge_estimate_foreground_converge (which is resize NEAREST).  The smooth variant's level
+ * inputs are float32 copies (area sums in float64).  Workspace: fge_levels_workspace_bytes. */
+size_t fge_levels_workspace_bytes(int32_t W, int32_t H, const fge_params *p,
+                                  const fge_level_options *o);
+fge_status fge_estimate_foreground_levels(const void *I, const void *alpha, int32_t W, int32_t H,
+                                          const fge_params *p, const fge_level_options *o,
+                                          void *F, void *B, int32_t *sweeps_out, void *workspace,
+                                          size_t workspace_bytes, void *stream);
+
 /* ---- batches of images of different sizes ---------------------------------------------- */
 
 /* A batch plan: every image follows its own level plan (so its F and B are bit-identical to

@@ -10,6 +10,10 @@
 // enqueues max_sweeps guarded sweeps without waiting; the decision never leaves the device.
 // With tol < 0 every level runs the fixed counts of the iteration rule (10 / 2), unguarded.
 //
+// Resize variants: nearest (Algorithm 1 as read everywhere else) or smooth (the image and matte
+// area-averaged from full resolution into float32 level copies, the previous level's F and B
+// resized bilinearly).
+//
 // Orders: red-black (two half-sweeps in place, (x + y) even first) or Jacobi (every pixel from
 // the previous sweep's values: sweep into a temporary, copy back).  The per-pixel update is the
 // 2x2 solve of eq. 9 in the same Sherman-Morrison form as the other kernels.  A level sweeps on
@@ -17,6 +21,7 @@
 // written (so binary16 storage rounds once per level, as on the fused path).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
 #include "fge_internal.h"
@@ -54,6 +59,99 @@ __global__ __launch_bounds__(kCvThreads) void cv_upsample_kernel(const T *Fp, co
             stv(Fo, c * n + p, Fp ? ldv(Fp, c * np + q) : 0.0f);
             stv(Bo, c * n + p, Bp ? ldv(Bp, c * np + q) : 0.0f);
         }
+    }
+}
+
+// Bilinear resize of the previous level's F and B (smooth variant): pixel centres at half-integers,
+// source coordinate (x + 1/2) wp / w - 1/2 clamped to [0, wp - 1], likewise in y.
+template <typename T>
+__global__ __launch_bounds__(kCvThreads) void cv_bilinear_kernel(const T *Fp, const T *Bp, int wp,
+                                                                 int hp, float *Fo, float *Bo, int w,
+                                                                 int h) {
+    const size_t n = static_cast<size_t>(w) * h, np = static_cast<size_t>(wp) * hp;
+    for (size_t p = static_cast<size_t>(blockIdx.x) * kCvThreads + threadIdx.x; p < n;
+         p += static_cast<size_t>(gridDim.x) * kCvThreads) {
+        const int y = static_cast<int>(p / w), x = static_cast<int>(p - static_cast<size_t>(y) * w);
+        auto tap = [](int i, int ns, int nd, int *i0, int *i1, double *f) {
+            double u = (i + 0.5) * ns / nd - 0.5;
+            u = u < 0.0 ? 0.0 : (u > ns - 1 ? ns - 1 : u);
+            *i0 = static_cast<int>(u);
+            *i1 = *i0 + 1 < ns ? *i0 + 1 : ns - 1;
+            *f = u - *i0;
+        };
+        int x0, x1, y0, y1;
+        double fx, fy;
+        tap(x, wp, w, &x0, &x1, &fx);
+        tap(y, hp, h, &y0, &y1, &fy);
+        auto mix = [&](const T *P) {
+            const double top = (1.0 - fx) * static_cast<float>(P[static_cast<size_t>(y0) * wp + x0]) +
+                               fx * static_cast<float>(P[static_cast<size_t>(y0) * wp + x1]);
+            const double bot = (1.0 - fx) * static_cast<float>(P[static_cast<size_t>(y1) * wp + x0]) +
+                               fx * static_cast<float>(P[static_cast<size_t>(y1) * wp + x1]);
+            return static_cast<float>((1.0 - fy) * top + fy * bot);
+        };
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            Fo[c * n + p] = Fp ? mix(Fp + c * np) : 0.0f;
+            Bo[c * n + p] = Bp ? mix(Bp + c * np) : 0.0f;
+        }
+    }
+}
+
+// Area resize (smooth variant), separable: destination pixel x of an axis of nd pixels averages
+// the source over [x ns/nd, (x+1) ns/nd), every source pixel weighted by its overlap.  Pass 1
+// resizes the rows of the 4 input planes (I then alpha, W x H, type T) to w columns; pass 2 the
+// columns of that result to h rows.  Sums in float64, results in float32.
+__device__ __forceinline__ double area_sum_begin(int x, int ns, int nd, int *i0, int *i1, double *x0,
+                                                 double *x1) {
+    *x0 = static_cast<double>(x) * ns / nd;
+    *x1 = static_cast<double>(x + 1) * ns / nd;
+    *i0 = static_cast<int>(floor(*x0));
+    *i1 = static_cast<int>(ceil(*x1));
+    if (*i1 > ns) *i1 = ns;
+    return *x1 - *x0;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kCvThreads) void cv_area_rows_kernel(const T *I, const T *A, int W,
+                                                                  int H, int w, float *out) {
+    const size_t n = static_cast<size_t>(w) * H * 4;
+    for (size_t p = static_cast<size_t>(blockIdx.x) * kCvThreads + threadIdx.x; p < n;
+         p += static_cast<size_t>(gridDim.x) * kCvThreads) {
+        const int c = static_cast<int>(p / (static_cast<size_t>(w) * H));
+        const size_t r = p - static_cast<size_t>(c) * w * H;
+        const int y = static_cast<int>(r / w), x = static_cast<int>(r - static_cast<size_t>(y) * w);
+        const T *row = (c < 3 ? I + static_cast<size_t>(c) * W * H : A) + static_cast<size_t>(y) * W;
+        int i0, i1;
+        double x0, x1;
+        const double len = area_sum_begin(x, W, w, &i0, &i1, &x0, &x1);
+        double acc = 0.0;
+        for (int i = i0; i < i1; ++i) {
+            const double a = i > x0 ? i : x0, b = i + 1 < x1 ? i + 1 : x1;
+            acc += (b - a) * static_cast<float>(row[i]);
+        }
+        out[p] = static_cast<float>(acc / len);
+    }
+}
+
+__global__ __launch_bounds__(kCvThreads) void cv_area_cols_kernel(const float *in, int w, int H,
+                                                                  int h, float *out) {
+    const size_t n = static_cast<size_t>(w) * h * 4;
+    for (size_t p = static_cast<size_t>(blockIdx.x) * kCvThreads + threadIdx.x; p < n;
+         p += static_cast<size_t>(gridDim.x) * kCvThreads) {
+        const int c = static_cast<int>(p / (static_cast<size_t>(w) * h));
+        const size_t r = p - static_cast<size_t>(c) * w * h;
+        const int y = static_cast<int>(r / w), x = static_cast<int>(r - static_cast<size_t>(y) * w);
+        const float *col = in + static_cast<size_t>(c) * w * H + x;
+        int j0, j1;
+        double y0, y1;
+        const double len = area_sum_begin(y, H, h, &j0, &j1, &y0, &y1);
+        double acc = 0.0;
+        for (int j = j0; j < j1; ++j) {
+            const double a = j > y0 ? j : y0, b = j + 1 < y1 ? j + 1 : y1;
+            acc += (b - a) * col[static_cast<size_t>(j) * w];
+        }
+        out[p] = static_cast<float>(acc / len);
     }
 }
 
@@ -180,12 +278,12 @@ __global__ void cv_check_kernel(const double *enow, double *eprev, int *stop, in
 // and the float32 Jacobi temporary (6 planes at full size each), the energy partial sums, and a
 // small block of scalars.
 struct CvLayout {
-    size_t work = 0, temp = 0, part = 0, scal = 0, total = 0;
+    size_t work = 0, temp = 0, lvin = 0, rows = 0, part = 0, scal = 0, total = 0;
 };
 
 size_t a256(size_t v) { return (v + 255) & ~static_cast<size_t>(255); }
 
-CvLayout cv_layout(const Plan &pl, bool jacobi) {
+CvLayout cv_layout(const Plan &pl, bool jacobi, bool smooth) {
     CvLayout L;
     size_t off = a256(pl.ws_bytes);
     const size_t planes6 = a256(6 * static_cast<size_t>(pl.W) * pl.H * sizeof(float));
@@ -193,6 +291,18 @@ CvLayout cv_layout(const Plan &pl, bool jacobi) {
     off += planes6;
     L.temp = off;
     off += jacobi ? planes6 : 0;
+    // smooth variant: the area-resized I and alpha of a level below full size (4 float planes)
+    // and the row pass of that resize (4 planes of w x H), at the largest such level
+    size_t lv_px = 0, rows_px = 0;
+    for (int j = 0; smooth && j < pl.n; ++j) {
+        if (pl.lv[j].w == pl.W && pl.lv[j].h == pl.H) continue;
+        lv_px = std::max(lv_px, static_cast<size_t>(pl.lv[j].w) * pl.lv[j].h);
+        rows_px = std::max(rows_px, static_cast<size_t>(pl.lv[j].w) * pl.H);
+    }
+    L.lvin = off;
+    off += a256(4 * lv_px * sizeof(float));
+    L.rows = off;
+    off += a256(4 * rows_px * sizeof(float));
     L.part = off;
     off += a256(static_cast<size_t>(energy_blocks(pl.W, pl.H)) * 5 * sizeof(double));
     L.scal = off;
@@ -209,13 +319,59 @@ fge_status cv_plan(int W, int H, const fge_params &p, Plan *pl) {
     return make_plan(W, H, q, pl);
 }
 
+// The sweeps of one level (and, in the convergence form, its energies and stop decisions), with
+// I and alpha of type TI read from Wi x Hi through the level's nearest map (the identity for the
+// smooth variant's level copies and for a full-size level).
+template <typename TI>
+fge_status cv_sweep_level(const fge_params &p, const TI *I, const TI *A, int Wi, int Hi, int ti,
+                          float *Fo, float *Bo, float *Ft, float *Bt, int w, int h, bool conv,
+                          double tol, int kmax, int *stop, int *count, double *part, double *enow,
+                          double *eprev, hipStream_t s) {
+    const size_t n = static_cast<size_t>(w) * h;
+    const bool jac = p.order == FGE_JACOBI;
+    const int *guard = conv ? stop : nullptr;
+    if (conv) {
+        hipLaunchKernelGGL(cv_begin_kernel, dim3(1), dim3(64), 0, s, stop, count);
+        if (launch_energy(I, A, Wi, Hi, Fo, Bo, w, h, p.omega, p.eps_r, ti, FGE_F32, stop, part,
+                          enow, s))
+            return FGE_EHIP;
+        hipLaunchKernelGGL(cv_check_kernel, dim3(1), dim3(64), 0, s, enow, eprev, stop, count, tol,
+                           0, kmax);
+        if (hipGetLastError() != hipSuccess) return FGE_EHIP;
+    }
+    for (int k = 1; k <= kmax; ++k) {
+        if (jac) {
+            hipLaunchKernelGGL(cv_jacobi_kernel<TI>, dim3(blocks_for(n)), dim3(kCvThreads), 0, s, I,
+                               A, Wi, Hi, Fo, Bo, Ft, Bt, w, h, p.omega, p.eps_r, guard);
+            hipLaunchKernelGGL(cv_copy_kernel<float>, dim3(blocks_for(3 * n)), dim3(kCvThreads), 0,
+                               s, Ft, Bt, Fo, Bo, n, guard);
+        } else {
+            const size_t npairs = static_cast<size_t>((w + 1) >> 1) * h;
+            for (int colour = 0; colour < 2; ++colour)
+                hipLaunchKernelGGL(cv_halfsweep_kernel<TI>, dim3(blocks_for(npairs)),
+                                   dim3(kCvThreads), 0, s, I, A, Wi, Hi, Fo, Bo, w, h, colour,
+                                   p.omega, p.eps_r, guard);
+        }
+        if (hipGetLastError() != hipSuccess) return FGE_EHIP;
+        if (conv) {
+            if (launch_energy(I, A, Wi, Hi, Fo, Bo, w, h, p.omega, p.eps_r, ti, FGE_F32, stop, part,
+                              enow, s))
+                return FGE_EHIP;
+            hipLaunchKernelGGL(cv_check_kernel, dim3(1), dim3(64), 0, s, enow, eprev, stop, count,
+                               tol, k, kmax);
+            if (hipGetLastError() != hipSuccess) return FGE_EHIP;
+        }
+    }
+    return FGE_OK;
+}
+
 template <typename T>
 fge_status cv_run(const Plan &pl, const fge_params &p, const void *Iv, const void *Av, void *Fv,
-                  void *Bv, double tol, int max_sweeps, int32_t *sweeps_out, char *ws,
+                  void *Bv, int resize, double tol, int max_sweeps, int32_t *sweeps_out, char *ws,
                   hipStream_t s) {
     const bool conv = tol >= 0.0;
-    const bool jac = p.order == FGE_JACOBI;
-    const CvLayout L = cv_layout(pl, jac);
+    const bool smooth = resize == FGE_RESIZE_SMOOTH;
+    const CvLayout L = cv_layout(pl, p.order == FGE_JACOBI, smooth);
     double *part = reinterpret_cast<double *>(ws + L.part);
     double *enow = reinterpret_cast<double *>(ws + L.scal);          // 6 doubles
     double *eprev = enow + 6;
@@ -231,44 +387,32 @@ fge_status cv_run(const Plan &pl, const fge_params &p, const void *Iv, const voi
         float *Bo = Fo + 3 * n;
         float *Ft = reinterpret_cast<float *>(ws + L.temp);
         float *Bt = Ft + 3 * n;
-        hipLaunchKernelGGL(cv_upsample_kernel<T>, dim3(blocks_for(n)), dim3(kCvThreads), 0, s,
-                           static_cast<const T *>(io.Fp), static_cast<const T *>(io.Bp), io.wp,
-                           io.hp, Fo, Bo, w, h);
+        if (smooth)
+            hipLaunchKernelGGL(cv_bilinear_kernel<T>, dim3(blocks_for(n)), dim3(kCvThreads), 0, s,
+                               static_cast<const T *>(io.Fp), static_cast<const T *>(io.Bp), io.wp,
+                               io.hp, Fo, Bo, w, h);
+        else
+            hipLaunchKernelGGL(cv_upsample_kernel<T>, dim3(blocks_for(n)), dim3(kCvThreads), 0, s,
+                               static_cast<const T *>(io.Fp), static_cast<const T *>(io.Bp), io.wp,
+                               io.hp, Fo, Bo, w, h);
         if (hipGetLastError() != hipSuccess) return FGE_EHIP;
         const int kmax = conv ? max_sweeps : pl.lv[j].iters;
-        const int *guard = conv ? stop : nullptr;
-        if (conv) {
-            hipLaunchKernelGGL(cv_begin_kernel, dim3(1), dim3(64), 0, s, stop, counts + j);
-            if (launch_energy(Iv, Av, pl.W, pl.H, Fo, Bo, w, h, p.omega, p.eps_r, p.storage,
-                              FGE_F32, stop, part, enow, s))
-                return FGE_EHIP;
-            hipLaunchKernelGGL(cv_check_kernel, dim3(1), dim3(64), 0, s, enow, eprev, stop,
-                               counts + j, tol, 0, kmax);
+        fge_status st;
+        if (smooth && (w != pl.W || h != pl.H)) {
+            float *lv = reinterpret_cast<float *>(ws + L.lvin);   // I (3 planes), alpha: w x h
+            float *rows = reinterpret_cast<float *>(ws + L.rows);
+            hipLaunchKernelGGL(cv_area_rows_kernel<T>, dim3(blocks_for(4 * static_cast<size_t>(w) * pl.H)),
+                               dim3(kCvThreads), 0, s, I, A, pl.W, pl.H, w, rows);
+            hipLaunchKernelGGL(cv_area_cols_kernel, dim3(blocks_for(4 * n)), dim3(kCvThreads), 0, s,
+                               rows, w, pl.H, h, lv);
             if (hipGetLastError() != hipSuccess) return FGE_EHIP;
+            st = cv_sweep_level<float>(p, lv, lv + 3 * n, w, h, FGE_F32, Fo, Bo, Ft, Bt, w, h, conv,
+                                       tol, kmax, stop, counts + j, part, enow, eprev, s);
+        } else {
+            st = cv_sweep_level<T>(p, I, A, pl.W, pl.H, p.storage, Fo, Bo, Ft, Bt, w, h, conv, tol,
+                                   kmax, stop, counts + j, part, enow, eprev, s);
         }
-        for (int k = 1; k <= kmax; ++k) {
-            if (jac) {
-                hipLaunchKernelGGL(cv_jacobi_kernel<T>, dim3(blocks_for(n)), dim3(kCvThreads), 0, s,
-                                   I, A, pl.W, pl.H, Fo, Bo, Ft, Bt, w, h, p.omega, p.eps_r, guard);
-                hipLaunchKernelGGL(cv_copy_kernel<float>, dim3(blocks_for(3 * n)), dim3(kCvThreads),
-                                   0, s, Ft, Bt, Fo, Bo, n, guard);
-            } else {
-                const size_t npairs = static_cast<size_t>((w + 1) >> 1) * h;
-                for (int colour = 0; colour < 2; ++colour)
-                    hipLaunchKernelGGL(cv_halfsweep_kernel<T>, dim3(blocks_for(npairs)),
-                                       dim3(kCvThreads), 0, s, I, A, pl.W, pl.H, Fo, Bo, w, h,
-                                       colour, p.omega, p.eps_r, guard);
-            }
-            if (hipGetLastError() != hipSuccess) return FGE_EHIP;
-            if (conv) {
-                if (launch_energy(Iv, Av, pl.W, pl.H, Fo, Bo, w, h, p.omega, p.eps_r, p.storage,
-                                  FGE_F32, stop, part, enow, s))
-                    return FGE_EHIP;
-                hipLaunchKernelGGL(cv_check_kernel, dim3(1), dim3(64), 0, s, enow, eprev, stop,
-                                   counts + j, tol, k, kmax);
-                if (hipGetLastError() != hipSuccess) return FGE_EHIP;
-            }
-        }
+        if (st != FGE_OK) return st;
         // the level's state, in the storage type
         hipLaunchKernelGGL(cv_copy_kernel<T>, dim3(blocks_for(3 * n)), dim3(kCvThreads), 0, s, Fo,
                            Bo, static_cast<T *>(io.Fo), static_cast<T *>(io.Bo), n, nullptr);
@@ -279,29 +423,42 @@ fge_status cv_run(const Plan &pl, const fge_params &p, const void *Iv, const voi
 
 }  // namespace
 
-size_t converge_workspace_bytes(int W, int H, const fge_params &p) {
+size_t levels_workspace_bytes(int W, int H, const fge_params &p, int resize) {
     Plan pl;
     if (cv_plan(W, H, p, &pl) != FGE_OK) return 0;
-    return cv_layout(pl, p.order == FGE_JACOBI).total;
+    return cv_layout(pl, p.order == FGE_JACOBI, resize == FGE_RESIZE_SMOOTH).total;
 }
 
-fge_status estimate_converge(const void *I, const void *A, int W, int H, const fge_params &p,
-                             double tol, int max_sweeps, void *F, void *B, int32_t *sweeps_out,
-                             void *workspace, size_t workspace_bytes, void *stream) {
+size_t converge_workspace_bytes(int W, int H, const fge_params &p) {
+    return levels_workspace_bytes(W, H, p, FGE_RESIZE_NEAREST);
+}
+
+fge_status estimate_levels(const void *I, const void *A, int W, int H, const fge_params &p,
+                           int resize, double tol, int max_sweeps, void *F, void *B,
+                           int32_t *sweeps_out, void *workspace, size_t workspace_bytes,
+                           void *stream) {
     Plan pl;
     const fge_status st = cv_plan(W, H, p, &pl);
     if (st != FGE_OK) return st;
     if (!I || !A || !F || !B || F == B) return FGE_EINVAL;
+    if (resize != FGE_RESIZE_NEAREST && resize != FGE_RESIZE_SMOOTH) return FGE_EINVAL;
     if (tol >= 0.0 && (max_sweeps < 1 || max_sweeps > kCvMaxSweeps)) return FGE_EINVAL;
     if (!(tol == tol)) return FGE_EINVAL;   // NaN
-    const size_t need = cv_layout(pl, p.order == FGE_JACOBI).total;
+    const size_t need = cv_layout(pl, p.order == FGE_JACOBI, resize == FGE_RESIZE_SMOOTH).total;
     if (!workspace || workspace_bytes < need || (reinterpret_cast<uintptr_t>(workspace) & 255))
         return FGE_EWORKSPACE;
     char *ws = static_cast<char *>(workspace);
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (p.storage == FGE_F16)
-        return cv_run<_Float16>(pl, p, I, A, F, B, tol, max_sweeps, sweeps_out, ws, s);
-    return cv_run<float>(pl, p, I, A, F, B, tol, max_sweeps, sweeps_out, ws, s);
+        return cv_run<_Float16>(pl, p, I, A, F, B, resize, tol, max_sweeps, sweeps_out, ws, s);
+    return cv_run<float>(pl, p, I, A, F, B, resize, tol, max_sweeps, sweeps_out, ws, s);
+}
+
+fge_status estimate_converge(const void *I, const void *A, int W, int H, const fge_params &p,
+                             double tol, int max_sweeps, void *F, void *B, int32_t *sweeps_out,
+                             void *workspace, size_t workspace_bytes, void *stream) {
+    return estimate_levels(I, A, W, H, p, FGE_RESIZE_NEAREST, tol, max_sweeps, F, B, sweeps_out,
+                           workspace, workspace_bytes, stream);
 }
 
 }  // namespace fge
@@ -315,6 +472,31 @@ size_t fge_converge_workspace_bytes(int32_t W, int32_t H, const fge_params *p) {
         p = &tmp;
     }
     return fge::converge_workspace_bytes(W, H, *p);
+}
+
+size_t fge_levels_workspace_bytes(int32_t W, int32_t H, const fge_params *p,
+                                  const fge_level_options *o) {
+    fge_params tmp;
+    if (!p) {
+        fge_default_params(&tmp);
+        p = &tmp;
+    }
+    if (!o || o->size != sizeof(fge_level_options)) return 0;
+    return fge::levels_workspace_bytes(W, H, *p, o->resize);
+}
+
+fge_status fge_estimate_foreground_levels(const void *I, const void *alpha, int32_t W, int32_t H,
+                                          const fge_params *p, const fge_level_options *o,
+                                          void *F, void *B, int32_t *sweeps_out, void *workspace,
+                                          size_t workspace_bytes, void *stream) {
+    fge_params tmp;
+    if (!p) {
+        fge_default_params(&tmp);
+        p = &tmp;
+    }
+    if (!o || o->size != sizeof(fge_level_options)) return FGE_EINVAL;
+    return fge::estimate_levels(I, alpha, W, H, *p, o->resize, o->tol, o->max_sweeps, F, B,
+                                sweeps_out, workspace, workspace_bytes, stream);
 }
 
 fge_status fge_estimate_foreground_converge(const void *I, const void *alpha, int32_t W, int32_t H,

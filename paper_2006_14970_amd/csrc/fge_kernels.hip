@@ -1341,12 +1341,12 @@ int fine_units(const FineArgs &a) { return a.nx * a.ny; }
 int launch_strip_rows(const int *w, const int *h, int n) {
     // A batched launch has the parallelism of all its levels together, so its strips can be
     // taller than one level alone would get (less halo work per output row): the tallest even
-    // height up to 64 rows that still leaves at least 4 strips per resident wave.
+    // height up to 64 rows that still gives every resident wave a strip.
     for (int rows = 64; rows >= 8; rows -= 2) {
         long items = 0;
         for (int k = 0; k < n; ++k)
             items += static_cast<long>(fine_strips_x(w[k])) * ((h[k] + rows - 1) / rows);
-        if (items >= 4L * kPersistentWaves) return rows;
+        if (items >= kPersistentWaves) return rows;
     }
     return 0;
 }

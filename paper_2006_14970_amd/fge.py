@@ -48,6 +48,19 @@ class Params(ctypes.Structure):
     ]
 
 
+class LevelOptions(ctypes.Structure):
+    _fields_ = [
+        ("size", ctypes.c_uint32),
+        ("resize", ctypes.c_int32),
+        ("tol", ctypes.c_double),
+        ("max_sweeps", ctypes.c_int32),
+        ("reserved0", ctypes.c_int32),
+    ]
+
+
+RESIZE_NEAREST, RESIZE_SMOOTH = 0, 1
+
+
 class TuneEntry(ctypes.Structure):
     _fields_ = [
         ("strip_rows", ctypes.c_int32),
@@ -172,6 +185,11 @@ def _lib():
     lib.fge_estimate_foreground_converge.argtypes = [vp, vp, i32, i32, pp, ctypes.c_double, i32,
                                                      vp, vp, vp, vp, sz, vp]
     lib.fge_estimate_foreground_converge.restype = ctypes.c_int
+    op = ctypes.POINTER(LevelOptions)
+    lib.fge_levels_workspace_bytes.argtypes = [i32, i32, pp, op]
+    lib.fge_levels_workspace_bytes.restype = sz
+    lib.fge_estimate_foreground_levels.argtypes = [vp, vp, i32, i32, pp, op, vp, vp, vp, vp, sz, vp]
+    lib.fge_estimate_foreground_levels.restype = ctypes.c_int
     tp = ctypes.POINTER(TuneEntry)
     lib.fge_tune_candidates.argtypes = []
     lib.fge_tune_candidates.restype = i32
@@ -746,3 +764,43 @@ def composite(F, alpha, B, stream=None):
                                 _dtype_code(F.dtype), C.data_ptr(), _stream_ptr(stream)),
            "fge_composite")
     return C
+
+
+def level_options(resize: str = "smooth", tol: float = -1.0, max_sweeps: int = 100) -> LevelOptions:
+    o = LevelOptions()
+    o.size = ctypes.sizeof(LevelOptions)
+    o.resize = {"nearest": RESIZE_NEAREST, "smooth": RESIZE_SMOOTH}[resize]
+    o.tol = float(tol)
+    o.max_sweeps = int(max_sweeps)
+    return o
+
+
+def estimate_foreground_levels(I, alpha, params: Params | None = None, resize: str = "smooth",
+                               tol: float = -1.0, max_sweeps: int = 100, F=None, B=None,
+                               stream=None):
+    """The level loop on per-level kernels with a resize variant and, for tol >= 0, the
+    convergence stop (fge_estimate_foreground_levels).  Returns (F, B, sweeps per level; the
+    counts are written in the convergence form only).  Does not synchronise."""
+    import torch
+    p = params if params is not None else default_params()
+    o = level_options(resize, tol, max_sweeps)
+    dt = storage_dtype(p)
+    _, H, W = I.shape
+    for name, t in (("I", I), ("alpha", alpha)):
+        if not t.is_cuda or t.dtype != dt or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous CUDA tensor of dtype {dt}")
+    if tuple(alpha.shape) != (H, W):
+        raise ValueError("alpha must be (H, W) matching I")
+    if F is None:
+        F = torch.empty((3, H, W), dtype=dt, device=I.device)
+    if B is None:
+        B = torch.empty((3, H, W), dtype=dt, device=I.device)
+    n = num_levels(W, H)
+    sweeps = torch.zeros(max(1, n), dtype=torch.int32, device=I.device)
+    need = _lib().fge_levels_workspace_bytes(W, H, ctypes.byref(p), ctypes.byref(o))
+    ws = torch.empty(max(1, need), dtype=torch.uint8, device=I.device)
+    _check(_lib().fge_estimate_foreground_levels(
+        I.data_ptr(), alpha.data_ptr(), W, H, ctypes.byref(p), ctypes.byref(o), F.data_ptr(),
+        B.data_ptr(), sweeps.data_ptr(), ws.data_ptr(), ws.numel(), _stream_ptr(stream)),
+        "fge_estimate_foreground_levels")
+    return F, B, sweeps[:n]

@@ -303,3 +303,32 @@ def test_quality_argument_errors(fge):
     assert lib.fge_quality(None, a, a, 64, 64, fge.F32, 1.4, a, a, nw, None) == fge.FGE_EINVAL
     assert lib.fge_composite(a, a, a, 64, 64, fge.U8, a, None) == fge.FGE_EINVAL
     assert lib.fge_composite(a, a, a, 0, 64, fge.F32, a, None) == fge.FGE_EINVAL
+
+
+def test_level_options_host_side(fge):
+    lib = fge.load()
+    assert ctypes.sizeof(fge.LevelOptions) == 24
+    p = fge.default_params()
+    near = fge.level_options("nearest")
+    smooth = fge.level_options("smooth")
+    wn = lib.fge_levels_workspace_bytes(1024, 768, ctypes.byref(p), ctypes.byref(near))
+    wsm = lib.fge_levels_workspace_bytes(1024, 768, ctypes.byref(p), ctypes.byref(smooth))
+    assert wn == lib.fge_converge_workspace_bytes(1024, 768, ctypes.byref(p))
+    # level copies (4 float planes of 512x384) and the row pass (4 planes of 512x768) on top
+    assert wsm >= wn + 16 * 512 * 384 + 16 * 512 * 768
+    bad = fge.level_options("smooth")
+    bad.size = 16
+    assert lib.fge_levels_workspace_bytes(64, 64, ctypes.byref(p), ctypes.byref(bad)) == 0
+    a = 0x100000
+    nw = lib.fge_levels_workspace_bytes(64, 64, ctypes.byref(p), ctypes.byref(smooth))
+
+    def run(o, ws=a):
+        return lib.fge_estimate_foreground_levels(a, a + 0x1000, 64, 64, ctypes.byref(p),
+                                                  ctypes.byref(o), a + 0x2000, a + 0x3000, None,
+                                                  ws, nw, None)
+    assert run(bad) == fge.FGE_EINVAL
+    odd = fge.level_options("smooth")
+    odd.resize = 7
+    assert run(odd) == fge.FGE_EINVAL
+    assert run(fge.level_options("smooth", tol=1e-4, max_sweeps=0)) == fge.FGE_EINVAL
+    assert run(smooth, ws=None) == fge.FGE_EWORKSPACE

@@ -1,0 +1,75 @@
+"""GPU tests of the smooth resize variant (area averaging of the image and matte, bilinear
+resize of F and B) against the oracle's form of Algorithm 1 with the same variant."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2006_14970_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f32": 1e-4, "f16": 2e-3}
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    assert torch.cuda.is_available(), "the GPU tests need an MI355X"
+    from paper_2006_14970_amd import fge
+    fge.load()
+    return torch, fge
+
+
+def maxabs(x, y):
+    return float(np.abs(x - y).max())
+
+
+@pytest.mark.parametrize("order", ["redblack", "jacobi"])
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+@pytest.mark.parametrize("wh", [(1, 1), (5, 3), (64, 64), (300, 200), (257, 129), (1, 300), (1024, 768)])
+def test_smooth_fixed_counts_match_oracle(gpu, order, storage, wh):
+    torch, fge = gpu
+    W, H = wh
+    p = fge.default_params(storage=fge.F16 if storage == "f16" else fge.F32,
+                           order=fge.JACOBI if order == "jacobi" else fge.REDBLACK)
+    dt = fge.storage_dtype(p)
+    s = synth.strands(W, H, seed=5 * W + H, n_strands=max(1, W * H // 4000))
+    I = torch.from_numpy(s.I).to(dt).cuda()
+    a = torch.from_numpy(s.alpha).to(dt).cuda()
+    F, B, _ = fge.estimate_foreground_levels(I, a, p, resize="smooth")
+    torch.cuda.synchronize()
+    Fo, Bo = oracle.ml_resize(I.double().cpu().numpy(), a.double().cpu().numpy(), "smooth",
+                              order=order)
+    err = max(maxabs(F.double().cpu().numpy(), Fo), maxabs(B.double().cpu().numpy(), Bo))
+    print(f"smooth {order} {storage} {W}x{H}: {err:.2e}")
+    assert err <= TOL[storage]
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_smooth_converge_replays_in_oracle(gpu, storage):
+    torch, fge = gpu
+    p = fge.default_params(storage=fge.F16 if storage == "f16" else fge.F32)
+    dt = fge.storage_dtype(p)
+    s = synth.strands(320, 240, seed=77, n_strands=20)
+    I = torch.from_numpy(s.I).to(dt).cuda()
+    a = torch.from_numpy(s.alpha).to(dt).cuda()
+    F, B, sw = fge.estimate_foreground_levels(I, a, p, resize="smooth", tol=1e-4, max_sweeps=300)
+    torch.cuda.synchronize()
+    sw = sw.cpu().tolist()
+    assert all(1 <= k <= 300 for k in sw)
+    Fo, Bo = oracle.ml_resize(I.double().cpu().numpy(), a.double().cpu().numpy(), "smooth", sweeps=sw)
+    err = max(maxabs(F.double().cpu().numpy(), Fo), maxabs(B.double().cpu().numpy(), Bo))
+    print(f"smooth converge {storage}: sweeps {sw}, {err:.2e}")
+    assert err <= TOL[storage]
+
+
+def test_nearest_levels_equal_converge_path(gpu):
+    torch, fge = gpu
+    p = fge.default_params()
+    s = synth.smooth(200, 150, seed=9)
+    I = torch.from_numpy(s.I).float().cuda()
+    a = torch.from_numpy(s.alpha).float().cuda()
+    r1 = fge.estimate_foreground_levels(I, a, p, resize="nearest", tol=1e-4, max_sweeps=50)
+    r2 = fge.estimate_foreground_converge(I, a, p, tol=1e-4, max_sweeps=50)
+    torch.cuda.synchronize()
+    assert torch.equal(r1[0], r2[0]) and torch.equal(r1[1], r2[1]) and torch.equal(r1[2], r2[2])
