@@ -652,6 +652,7 @@ constexpr int kStripCols = 128;         // two columns per lane
 constexpr int kFirstCore = kStripCols - kHalo;          // strip 0 keeps columns [0, 124)
 constexpr int kMidCore = kStripCols - 2 * kHalo;        // interior strips keep 120 columns
 constexpr int kWavesPerBlock = 4;
+constexpr int kXcds = 8;                // accelerator dies, one L2 each
 constexpr int kRsrcWord3 = 0x00020000;  // raw buffer resource, gfx9 family
 
 
@@ -1168,10 +1169,21 @@ __device__ __forceinline__ void fine_body(const FineArgs &args, int wave, int la
         fine_strip<T, false, false>(args, sx, sy, lane);
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs (workgroup b on XCD b % 8), each with its
+// own L2.  The row-major sequence of blocks (kWavesPerBlock strips each) is cut into 8 equal
+// chunks and chunk c runs on XCD c: each XCD then streams a band of whole-width strip rows, and
+// vertically adjacent strips, which read each other's halo rows, share an L2.
+__host__ __device__ inline int fine_block_chunk(int units) {
+    const int blocks = (units + kWavesPerBlock - 1) / kWavesPerBlock;
+    return (blocks + kXcds - 1) / kXcds;
+}
+
 template <typename T>
 __global__ __launch_bounds__(64 * kWavesPerBlock, 2) void fine_kernel(FineArgs args) {
-    const int wave = uniform(blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6));
-    if (wave >= args.nx * args.ny) return;
+    const int units = args.nx * args.ny;
+    const int pos = (blockIdx.x % kXcds) * fine_block_chunk(units) + blockIdx.x / kXcds;
+    const int wave = uniform(pos * kWavesPerBlock + (threadIdx.x >> 6));
+    if (wave >= units) return;
     fine_body<T>(args, wave, threadIdx.x & 63);
 }
 
@@ -1441,7 +1453,7 @@ int launch_coarse(const Plan &plan, const LevelSrc &src, void *Fo, void *Bo, flo
 int launch_fine_fused(const LevelIO &io, int strip_rows, int storage, void *stream) {
     FineArgs a;
     make_fine_args(io, strip_rows, &a);
-    const int blocks = (fine_units(a) + kWavesPerBlock - 1) / kWavesPerBlock;
+    const int blocks = kXcds * fine_block_chunk(fine_units(a));
     FGE_DISPATCH(storage, fine_kernel, dim3(blocks), dim3(64 * kWavesPerBlock), 0,
                  static_cast<hipStream_t>(stream), a);
     return static_cast<int>(hipGetLastError());
