@@ -50,6 +50,16 @@ def profiled_traffic(kernel):
     return None
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -64,7 +74,8 @@ def level_bytes(levels, elem):
     return out
 
 
-def run_storage(torch, fge, sample, storage, steps, warmup, oracle_F=None, oracle_B=None):
+def run_storage(torch, fge, sample, storage, steps, warmup, oracle_F=None, oracle_B=None,
+                rounded_ref=None):
     dt = torch.float16 if storage == fge.F16 else torch.float32
     p = fge.default_params(storage=storage)
     dev = torch.device("cuda:0")
@@ -85,11 +96,14 @@ def run_storage(torch, fge, sample, storage, steps, warmup, oracle_F=None, oracl
     for k in range(warmup):
         step(k)
     torch.cuda.synchronize()
-    err = None
+    err = err_rounded = None
     if oracle_F is not None:
         F = sets[(warmup - 1) % 2][2].double().cpu().numpy()
         B = sets[(warmup - 1) % 2][3].double().cpu().numpy()
         err = float(max(np.abs(F - oracle_F).max(), np.abs(B - oracle_B).max()))
+        if rounded_ref is not None:   # the oracle on the storage-rounded inputs: kernel error alone
+            err_rounded = float(max(np.abs(F - rounded_ref[0]).max(),
+                                    np.abs(B - rounded_ref[1]).max()))
 
     # pass 1: throughput (K steps back to back, nothing else on the stream)
     torch.cuda.synchronize()
@@ -133,6 +147,7 @@ def run_storage(torch, fge, sample, storage, steps, warmup, oracle_F=None, oracl
         "lat_ms": lat,
         "level_ms": [lvl_ms[i] / lvl_n[i] if lvl_n[i] else None for i in range(len(lvl_ms))],
         "max_abs_vs_oracle": err,
+        "max_abs_vs_oracle_rounded_inputs": err_rounded,
         "params": p,
         "quality": {"SAD": float(q[0]), "MSE": float(q[1]), "GRAD": float(q[2]),
                     "translucent_px": int(q[3]), "device_ms": e0.elapsed_time(e1)},
@@ -240,7 +255,7 @@ def run_batch(torch, fge, synth, args, single_f32_mps, check_oracle):
         order = sorted(range(len(sizes)), key=lambda i: sizes[i][0] * sizes[i][1])
         err = 0.0
         for i in order[:2]:
-            Fo, Bo = oracle.ml(samples[i].I, samples[i].alpha)
+            Fo, Bo = oracle.ml(samples[i].I, samples[i].alpha, parallel=True)
             err = max(err, float(np.abs(tuned["Fs"][i].double().cpu().numpy() - Fo).max()),
                       float(np.abs(tuned["Bs"][i].double().cpu().numpy() - Bo).max()))
     log(f"  batch (tuned): {tuned['run_ms']:.3f} ms per run, {tuned['graph_ms']:.3f} ms per graph "
@@ -350,7 +365,7 @@ def run_serving(torch, fge, synth, args, single_f32_mps, check_oracle):
         err = 0.0
         for k in order[:2]:
             I, a, F, B = views[int(k)]
-            Fo, Bo = oracle.ml(I.double().cpu().numpy(), a.double().cpu().numpy())
+            Fo, Bo = oracle.ml(I.double().cpu().numpy(), a.double().cpu().numpy(), parallel=True)
             err = max(err, float(np.abs(F.double().cpu().numpy() - Fo).max()),
                       float(np.abs(B.double().cpu().numpy() - Bo).max()))
     del pool_in, pool_out, arena, views
@@ -399,11 +414,23 @@ def main():
     log(f"  done in {time.perf_counter() - t:.1f} s, fractional alpha {sample.fractional_fraction():.3f}")
 
     oracle_F = oracle_B = None
-    cpu = None
+    rounded_ref = None
+    cpu = cpu_all = None
     if not args.no_cpu_baseline:
         import oracle
-        log("FP64 oracle, red-black order (parity reference for the error figures)")
-        oracle_F, oracle_B = oracle.ml(sample.I, sample.alpha, order="redblack")
+        nthr = oracle.threads(parallel=True)
+        log(f"FP64 oracle, red-black order, OpenMP on {nthr} threads (parity reference; timed)")
+        t = time.perf_counter()
+        oracle_F, oracle_B = oracle.ml(sample.I, sample.alpha, order="redblack", parallel=True)
+        rb_s = time.perf_counter() - t
+        cpu_all = {"value": W_IMG * H_IMG / 1e6 / rb_s, "unit": "MP/s", "cores": nthr,
+                   "kind": "oracle", "order": "redblack", "nproc": os.cpu_count(),
+                   "cpu_model": cpu_model(),
+                   "sample": f"the full 4096x3072 image, FP64 red-black order, one run of {rb_s:.2f} s"}
+        log("FP64 oracle on float16-rounded inputs (separates input rounding from kernel error)")
+        I16 = sample.I.astype(np.float16).astype(np.float64)
+        a16 = sample.alpha.astype(np.float16).astype(np.float64)
+        rounded_ref = oracle.ml(I16, a16, order="redblack", parallel=True)
         log("FP64 oracle, raster order, 1 thread: timing (CPU baseline)")
         times = []
         for _ in range(3):
@@ -421,7 +448,8 @@ def main():
     for name, storage in (("f32", fge.F32), ("f16", fge.F16)):
         log(f"GPU {name} storage: {args.warmup} warm-up + {args.steps} timed steps (x3 passes)")
         res[name] = run_storage(torch, fge, sample, storage, args.steps, args.warmup,
-                                oracle_F, oracle_B)
+                                oracle_F, oracle_B,
+                                rounded_ref if storage == fge.F16 else None)
         log(f"  {res[name]['ms_per_step']:.4f} ms/step, max-abs vs oracle {res[name]['max_abs_vs_oracle']}")
 
     mp = W_IMG * H_IMG / 1e6
@@ -447,6 +475,7 @@ def main():
 
     s32 = summary(res["f32"], 4)
     s16 = summary(res["f16"], 2)
+    s16["max_abs_vs_oracle_rounded_inputs"] = res["f16"]["max_abs_vs_oracle_rounded_inputs"]
     s32["quality_vs_ground_truth"] = res["f32"]["quality"]
     s16["quality_vs_ground_truth"] = res["f16"]["quality"]
     variants = None
@@ -483,14 +512,28 @@ def main():
         "batch_fp16": batch,
         "serving_fp16": serving,
         "cpu_baseline": cpu,
+        "cpu_baseline_all_cores": cpu_all,
     }
+    # a plain device copy of 512 MiB (twice the memory-side cache): the practical HBM ceiling of a
+    # pure stream, beside the 8 TB/s peak the roofline is quoted against
+    n = 512 * 1024 * 1024 // 4
+    src = torch.rand(n, device="cuda:0")
+    dst = torch.empty_like(src)
+    reps = 10
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(reps)]
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    for e0, e1 in ev:
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+    torch.cuda.synchronize()
+    copy_ms = float(np.median([e0.elapsed_time(e1) for e0, e1 in ev]))
+    out["copy_ceiling"] = {"value": 2 * n * 4 / (copy_ms * 1e-3) / 1e9, "unit": "GB/s",
+                           "bytes_per_copy": 2 * n * 4, "ms": copy_ms,
+                           "kernel": "device-to-device copy of 512 MiB (read + write)"}
     if args.copy_calibration:
-        n = 512 * 1024 * 1024 // 4
-        src = torch.rand(n, device="cuda:0")
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
         out["copy_calibration_bytes"] = {"read": n * 4, "write": n * 4}
     print(json.dumps(out), flush=True)
 

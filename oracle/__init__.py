@@ -29,31 +29,42 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "fge_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+_LIB_OMP = os.path.join(_HERE, "liboracle_omp.so")
 
 ORDERS = {"raster": 0, "redblack": 1, "jacobi": 2}
 
-_lib = None
+_libs: dict[bool, ctypes.CDLL] = {}
 
 
 def build(force: bool = True) -> str:
-    """Compile ``fge_oracle.c`` into ``liboracle.so`` with gcc (strict IEEE double, no FMA)."""
-    if force or not os.path.exists(_LIB):
-        tmp = _LIB + ".tmp"
-        subprocess.run(
-            ["gcc", "-O2", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math",
-             "-o", tmp, _SRC, "-lm"],
-            check=True)
-        os.replace(tmp, _LIB)
+    """Compile ``fge_oracle.c`` with gcc (strict IEEE double, no FMA) twice: ``liboracle.so``
+    (one thread) and ``liboracle_omp.so`` (OpenMP; red-black and Jacobi sweeps split their rows
+    over threads, with bit-identical results)."""
+    for path, extra in ((_LIB, []), (_LIB_OMP, ["-fopenmp"])):
+        if force or not os.path.exists(path):
+            tmp = path + ".tmp"
+            subprocess.run(
+                ["gcc", "-O2", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math", *extra,
+                 "-o", tmp, _SRC, "-lm"],
+                check=True)
+            os.replace(tmp, path)
     return _LIB
 
 
-def _load():
-    global _lib
-    if _lib is not None:
-        return _lib
-    if not os.path.exists(_LIB):
+def threads(parallel: bool = True) -> int:
+    """Threads one sweep of the chosen build uses (OMP_NUM_THREADS, else all cores)."""
+    return _load(parallel).fgo_threads()
+
+
+def _load(parallel: bool = False):
+    if parallel in _libs:
+        return _libs[parallel]
+    path = _LIB_OMP if parallel else _LIB
+    if not os.path.exists(path):
         build(force=False)
-    lib = ctypes.CDLL(_LIB)
+    lib = ctypes.CDLL(path)
+    lib.fgo_threads.argtypes = []
+    lib.fgo_threads.restype = ctypes.c_int
     dp = ctypes.POINTER(ctypes.c_double)
     i32, f64 = ctypes.c_int, ctypes.c_double
     lib.fgo_num_levels.argtypes = [i32, i32]
@@ -79,7 +90,7 @@ def _load():
     lib.fgo_resize_bilinear.restype = None
     lib.fgo_ml_resize.argtypes = [dp, dp, i32, i32, f64, f64, i32, i32, ip, dp, dp]
     lib.fgo_ml_resize.restype = i32
-    _lib = lib
+    _libs[parallel] = lib
     return lib
 
 
@@ -142,9 +153,10 @@ def sweep(F: np.ndarray, B: np.ndarray, I: np.ndarray, alpha: np.ndarray, omega:
 
 def ml(I: np.ndarray, alpha: np.ndarray, omega: float = 0.1, eps: float = 5e-3,
        small_size: int = 32, iters_small: int = 10, iters_big: int = 2,
-       order: str = "redblack", init=None) -> tuple[np.ndarray, np.ndarray]:
+       order: str = "redblack", init=None, parallel: bool = False) -> tuple[np.ndarray, np.ndarray]:
     """Algorithm 1 (multi-level estimation) in FP64.  ``init`` = (f3, b3) overrides the zero
-    1x1 start (used only by the constant-image fixed-point test)."""
+    1x1 start (used only by the constant-image fixed-point test).  ``parallel`` runs the OpenMP
+    build (same bits; raster order stays sequential)."""
     I = _f64c(I)
     a = _f64c(alpha)
     _, H, W = I.shape
@@ -156,7 +168,7 @@ def ml(I: np.ndarray, alpha: np.ndarray, omega: float = 0.1, eps: float = 5e-3,
         pf, pb = _ptr(f0), _ptr(b0)
     else:
         pf = pb = None
-    _load().fgo_ml(_ptr(I), _ptr(a), W, H, float(omega), float(eps), int(small_size),
+    _load(parallel).fgo_ml(_ptr(I), _ptr(a), W, H, float(omega), float(eps), int(small_size),
                    int(iters_small), int(iters_big), ORDERS[order], pf, pb, _ptr(F), _ptr(B))
     return F, B
 

@@ -28,9 +28,16 @@
  *     (all pixels with (x + y) even, then all odd, each in place) or Jacobi (every pixel from the
  *     previous sweep's values).
  *
+ * Built twice: plain (every loop on one thread) and with OpenMP, where the rows of one colour of a
+ * red-black sweep, or the rows of a Jacobi sweep, are split over threads.  Every pixel's
+ * arithmetic is the same in both builds, so their results are bit-identical.
+ *
  * Layout: planar, row-major, x fastest.  A 3-channel image of size w x h is 3 planes of w*h
  * doubles (plane c starts at c*w*h); the matte is one plane.
  */
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
@@ -141,6 +148,16 @@ static void update_in_place(double *F, double *B, const double *I, const double 
     }
 }
 
+/* Threads a parallel region uses: 1 unless built with OpenMP. */
+int fgo_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
 /* One sweep over every pixel of a w x h level, in the given order, updating F and B. */
 void fgo_sweep(double *F, double *B, const double *I, const double *a, int w, int h,
                double omega, double eps, int order)
@@ -150,17 +167,23 @@ void fgo_sweep(double *F, double *B, const double *I, const double *a, int w, in
             for (int x = 0; x < w; x++)
                 update_in_place(F, B, I, a, w, h, x, y, omega, eps);
     } else if (order == FGO_REDBLACK) {
-        for (int colour = 0; colour < 2; colour++)
+        /* A pixel of one colour reads only pixels of the other colour (and, through the border
+         * clamp, itself), so the rows of one colour may be split over threads (OpenMP build):
+         * every pixel gets the same value in any split. */
+        for (int colour = 0; colour < 2; colour++) {
+#pragma omp parallel for schedule(static)
             for (int y = 0; y < h; y++)
                 for (int x = 0; x < w; x++)
                     if (((x + y) & 1) == colour)
                         update_in_place(F, B, I, a, w, h, x, y, omega, eps);
+        }
     } else {
         const size_t plane = (size_t)w * h;
         double *Fo = (double *)malloc(3 * plane * sizeof(double));
         double *Bo = (double *)malloc(3 * plane * sizeof(double));
         memcpy(Fo, F, 3 * plane * sizeof(double));
         memcpy(Bo, B, 3 * plane * sizeof(double));
+#pragma omp parallel for schedule(static)
         for (int y = 0; y < h; y++) {
             for (int x = 0; x < w; x++) {
                 double f[3], g[3];

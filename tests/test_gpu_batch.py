@@ -112,7 +112,8 @@ def test_batch_graph_replays(gpu):
 
 def test_uneven_batch_workload_f16(gpu):
     """The 64-image uneven batch (W, H uniform on [256, 2048], float16 storage): a sample of
-    images bit-identical to their single-image runs, two against the oracle."""
+    images bit-identical to their single-image runs, and every image against the oracle (the
+    OpenMP build, same bits as the one-thread oracle)."""
     torch, fge = gpu
     p = fge.default_params(storage=fge.F16)
     sizes = synth.batch_sizes()
@@ -126,11 +127,13 @@ def test_uneven_batch_workload_f16(gpu):
         F1, B1 = single(torch, fge, Is[i], As[i], p)
         torch.cuda.synchronize()
         assert torch.equal(Fs[i], F1) and torch.equal(Bs[i], B1), (i, sizes[i])
-    for i in order[:2]:
+    worst = 0.0
+    for i in range(len(sizes)):
         s = samples[i]
-        Fo, Bo = oracle.ml(s.I, s.alpha)
-        err = max(float((Fs[i].double().cpu() - torch.from_numpy(Fo)).abs().max()),
-                  float((Bs[i].double().cpu() - torch.from_numpy(Bo)).abs().max()))
-        print(f"batch image {i} {sizes[i]} f16 max-abs vs oracle {err:.2e}")
-        assert err <= TOL["f16"]
+        Fo, Bo = oracle.ml(s.I, s.alpha, parallel=True)
+        err = max(float(np.abs(Fs[i].cpu().numpy().astype(np.float64) - Fo).max()),
+                  float(np.abs(Bs[i].cpu().numpy().astype(np.float64) - Bo).max()))
+        worst = max(worst, err)
+        assert err <= TOL["f16"], (i, sizes[i], err)
+    print(f"64 batch images: worst f16 max-abs vs oracle {worst:.2e}")
     b.close()

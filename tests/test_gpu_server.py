@@ -109,6 +109,39 @@ def test_served_results_match_oracle(gpu):
         assert err <= TOL["f16"], (w, h, err)
 
 
+def test_serving_workload_sample_matches_oracle(gpu):
+    """A 5% sample of the 2000-request serving workload: 100 requests drawn at random from the
+    same stream (area log-uniform on 0.25-16 MP, aspect uniform on [0.5, 2], seed 5; inputs from
+    the smooth generator with seed 5000 + request id, float16), served together under the default
+    64 GB budget, each against the FP64 oracle on its float16 inputs."""
+    torch, fge = gpu
+    p = fge.default_params(storage=fge.F16)
+    reqs = synth.serving_requests(2000, seed=5)
+    pick = sorted(np.random.Generator(np.random.PCG64(55)).choice(len(reqs), size=100,
+                                                                  replace=False).tolist())
+    inputs = []
+    for i in pick:
+        r = reqs[i]
+        inputs.append(synth.smooth_device(r.W, r.H, 5000 + r.rid, "cuda", dtype=torch.float16))
+    torch.cuda.synchronize()
+    srv = new_server(torch, fge, p, arena_gb=8.0)
+    served = [srv.submit(k, I, a) for k, (I, a) in enumerate(inputs)]
+    srv.drain()
+    done = srv.poll()
+    srv.close()
+    assert len(done) == len(pick) and all(d.status == 0 for d in done)
+    worst, mp = 0.0, 0.0
+    for (I, a), (F, B) in zip(inputs, served):
+        Fo, Bo = oracle.ml(I.cpu().numpy().astype(np.float64), a.cpu().numpy().astype(np.float64),
+                           parallel=True)
+        err = max(float(np.abs(F.cpu().numpy().astype(np.float64) - Fo).max()),
+                  float(np.abs(B.cpu().numpy().astype(np.float64) - Bo).max()))
+        worst = max(worst, err)
+        mp += a.numel() / 1e6
+        assert err <= TOL["f16"], (tuple(a.shape), err)
+    print(f"{len(pick)} sampled requests ({mp:.0f} MP): worst f16 max-abs vs oracle {worst:.2e}")
+
+
 def test_budget_admission(gpu):
     """A budget that holds about two of the requests: admission waits for memory, the peak
     admitted footprint stays within the budget, and the results are unchanged."""

@@ -444,3 +444,18 @@ def test_nearest_variant_is_algorithm_1(oracle_mod):
     F, B = oracle_mod.ml(s.I, s.alpha)
     F2, B2 = oracle_mod.ml_resize(s.I, s.alpha, "nearest")
     assert np.array_equal(F, F2) and np.array_equal(B, B2)
+
+
+def test_openmp_build_bit_identical(oracle_mod):
+    """The OpenMP build of the oracle splits the rows of one colour (red-black) or of one sweep
+    (Jacobi) over threads; a pixel's arithmetic does not depend on the split, so both builds
+    give the same bits, including sizes smaller than the thread count."""
+    from paper_2006_14970_amd import synth
+    assert oracle_mod.threads(parallel=False) == 1
+    assert oracle_mod.threads(parallel=True) >= 1
+    for k, (w, h) in enumerate(((257, 130), (64, 64), (5, 3), (1, 1), (33, 70))):
+        s = synth.strands(w, h, seed=880 + k, n_strands=max(1, w * h // 3000))
+        for order in ("redblack", "jacobi"):
+            F1, B1 = oracle_mod.ml(s.I, s.alpha, order=order)
+            F2, B2 = oracle_mod.ml(s.I, s.alpha, order=order, parallel=True)
+            assert np.array_equal(F1, F2) and np.array_equal(B1, B2), (w, h, order)
