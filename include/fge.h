@@ -127,7 +127,9 @@ size_t fge_workspace_bytes(int32_t W, int32_t H, const fge_params *p);
 /* Algorithm 1 for one image: reads I (3 x H x W) and alpha (H x W), writes F and B
  * (3 x H x W each), all in p->storage element type, on `stream`.  `workspace` must hold
  * fge_workspace_bytes(W, H, p) bytes (it may be NULL when that is 0).  p == NULL means the
- * defaults. */
+ * defaults.  Before the finest level writes them, the call may use F's memory for compact
+ * copies of the lower levels' inputs, so F and B must not overlap I, alpha or the workspace
+ * (as for any output). */
 fge_status fge_estimate_foreground(const void *I, const void *alpha, int32_t W, int32_t H,
                                    const fge_params *p, void *F, void *B, void *workspace,
                                    size_t workspace_bytes, void *stream);

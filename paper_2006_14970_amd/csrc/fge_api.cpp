@@ -123,7 +123,7 @@ size_t fge_workspace_bytes(int32_t W, int32_t H, const fge_params *p) {
     fge_params tmp;
     fge::Plan plan;
     const fge_params &prm = resolve(p, tmp);
-    if (fge::make_plan(W, H, prm, &plan) != FGE_OK) return 0;
+    if (fge::make_plan(W, H, prm, &plan, true) != FGE_OK) return 0;
     if (prm.order == FGE_JACOBI) return fge::converge_workspace_bytes(W, H, prm);
     return plan.ws_bytes;
 }
@@ -134,7 +134,7 @@ fge_status fge_estimate_foreground(const void *I, const void *alpha, int32_t W, 
     fge_params tmp;
     const fge_params &prm = resolve(p, tmp);
     fge::Plan plan;
-    const fge_status st = fge::make_plan(W, H, prm, &plan);
+    const fge_status st = fge::make_plan(W, H, prm, &plan, true);
     if (st != FGE_OK) return st;
     if (!I || !alpha || !F || !B || F == B) return FGE_EINVAL;
     if (prm.order == FGE_JACOBI)   // fixed counts on the per-level Jacobi kernels
@@ -146,17 +146,23 @@ fge_status fge_estimate_foreground(const void *I, const void *alpha, int32_t W, 
     hipStream_t s = static_cast<hipStream_t>(stream);
     char *ws = static_cast<char *>(workspace);
     const int n = plan.n;
-    if (plan.ng > 0) {
+    if (plan.ng > 0 && !plan.gather_in_coarse) {
         LaunchTimer timer(n, s);   // recorded under index n_levels
-        if (fge::launch_gather(plan, I, alpha, ws + plan.pyr_off, prm.storage, s)) return FGE_EHIP;
+        if (fge::launch_gather(plan, I, alpha, fge::pyr_base(plan, ws, F), prm.storage, s))
+            return FGE_EHIP;
     }
     if (plan.nc > 0) {
         void *fo, *bo;
         fge::level_state(plan, ws, plan.nc - 1, F, B, &fo, &bo);
-        const fge::LevelSrc src = fge::coarse_src(plan, ws, I, alpha);
+        const fge::LevelSrc src = fge::coarse_src(plan, ws, F, I, alpha);
         LaunchTimer timer(n - plan.nc, s);
-        if (fge::launch_coarse(plan, src, fo, bo, prm.omega, prm.eps_r, prm.storage, s))
-            return FGE_EHIP;
+        const int err = plan.gather_in_coarse
+                            ? fge::launch_coarse_gather(plan, src, fo, bo, prm.omega, prm.eps_r, I,
+                                                        alpha, fge::pyr_base(plan, ws, F),
+                                                        prm.storage, s)
+                            : fge::launch_coarse(plan, src, fo, bo, prm.omega, prm.eps_r,
+                                                 prm.storage, s);
+        if (err) return FGE_EHIP;
     }
     for (int i = plan.nc; i < n; ++i) {
         const fge::LevelIO io = fge::level_io(plan, ws, i, I, alpha, F, B, prm.omega, prm.eps_r);

@@ -87,7 +87,7 @@ void fill_tables(const fge_batch &b, char *tab, char *ws, const void *const *I,
         const int i = b.coarse_imgs[k];
         const fge::Plan &pl = b.plans[i];
         char *iws = ws + b.img_off[i];
-        const fge::LevelSrc src = fge::coarse_src(pl, iws, I[i], A[i]);
+        const fge::LevelSrc src = fge::coarse_src(pl, iws, F[i], I[i], A[i]);
         void *fo, *bo;
         fge::level_state(pl, iws, pl.nc - 1, F[i], B[i], &fo, &bo);
         fge::make_coarse_args(pl, src, fo, bo, b.prm.omega, b.prm.eps_r, &cd[k]);
@@ -233,7 +233,8 @@ fge_status fge_batch_create(int32_t n, const int32_t *W, const int32_t *H, const
     t = align256(t + b->coarse_imgs.size() * sizeof(fge::CoarseArgs));
     for (const int i : b->gather_imgs) {
         const fge::Plan &pl = b->plans[i];
-        for (int j = 0; j < pl.ng; ++j) b->gather_total += static_cast<long long>(pl.lv[j].w) * pl.lv[j].h;
+        for (int j = 0; j < pl.n; ++j)
+            if (pl.copy[j]) b->gather_total += static_cast<long long>(pl.lv[j].w) * pl.lv[j].h;
     }
     int counter = 0;
     for (Launch &L : b->launches) {

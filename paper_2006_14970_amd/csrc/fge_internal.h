@@ -38,9 +38,16 @@ struct Plan {
     size_t buf_px[2] = {0, 0};
     size_t ws_bytes = 0;
     int kind[kMaxLevels] = {};     // per fine level: a LevelKind
-    // Gather pre-pass: levels [0, ng) get a compact copy of their resized I (3 planes) and alpha
-    // (1 plane) at pyr_off + pyr_lv[i] bytes of the workspace.
+    // Gather: the ng levels with copy[i] set get a compact copy of their resized I (3 planes)
+    // and alpha (1 plane) at pyr_lv[i] bytes from the copies' base.  Either a pre-pass launch
+    // for the small levels, copies in the workspace at pyr_off; or (gather_in_coarse) extra
+    // workgroups of the coarse launch for levels between the coarse block and the finest
+    // level, copies in the caller's F (written only by the finest level, which reads I and
+    // alpha at full resolution), while the coarse block reads its own levels from full
+    // resolution.
     int ng = 0;
+    bool copy[kMaxLevels] = {};
+    bool gather_in_coarse = false;
     size_t pyr_off = 0;
     size_t pyr_lv[kMaxLevels] = {};
 };
@@ -48,7 +55,9 @@ struct Plan {
 int num_levels(int W, int H);
 int level_size(int full, int level, int n);
 bool params_valid(const fge_params &p);
-fge_status make_plan(int W, int H, const fge_params &p, Plan *out);
+// single_image: the plan drives fge_estimate_foreground, whose coarse launch can carry the
+// gather (batched and served plans keep the separate pre-pass).
+fge_status make_plan(int W, int H, const fge_params &p, Plan *out, bool single_image = false);
 
 // Kernel launchers (fge_kernels.hip).  All enqueue on `stream` and return a HIP error code.
 struct LevelIO {
@@ -80,14 +89,20 @@ struct LevelSrc {
 //   level_io:     the record of fine level j > 0 (source, previous state, output state).
 //   coarse_src:   level_source of every coarse level.
 void level_state(const Plan &pl, char *ws, int j, void *F, void *B, void **f, void **b);
-void level_source(const Plan &pl, const char *ws, int j, const void *I, const void *A,
+// Base of the compact input copies: the caller's F (gather_in_coarse) or the workspace.
+char *pyr_base(const Plan &pl, char *ws, void *F);
+void level_source(const Plan &pl, const char *ws, const void *F, int j, const void *I, const void *A,
                   const void **Ij, const void **Aj, int *Wj, int *Hj);
 LevelIO level_io(const Plan &pl, char *ws, int j, const void *I, const void *A, void *F, void *B,
                  float omega, float eps);
-LevelSrc coarse_src(const Plan &pl, const char *ws, const void *I, const void *A);
+LevelSrc coarse_src(const Plan &pl, const char *ws, const void *F, const void *I, const void *A);
 
 int launch_gather(const Plan &plan, const void *I, const void *A, void *pyr, int storage,
                   void *stream);
+// The coarse block plus the gather of levels [g0, g0 + ng) in one launch (gather_in_coarse).
+int launch_coarse_gather(const Plan &plan, const LevelSrc &src, void *Fo, void *Bo, float omega,
+                         float eps, const void *I, const void *A, void *pyr, int storage,
+                         void *stream);
 int launch_coarse(const Plan &plan, const LevelSrc &src, void *Fo, void *Bo, float omega,
                   float eps, int storage, void *stream);
 int launch_fine_fused(const LevelIO &io, int strip_rows, int storage, void *stream);

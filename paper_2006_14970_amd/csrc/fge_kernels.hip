@@ -1244,8 +1244,17 @@ __global__ __launch_bounds__(kTileThreads) void tile_batch_kernel(
 // Gather pre-pass: unit p writes pixel p of the concatenated small levels of one image: I (3
 // planes) and alpha resized from full resolution by the nearest map, into each level's compact
 // planes.
+// One pixel of a gather: the four values read, and where they go.
 template <typename T>
-__device__ __forceinline__ void gather_body(const GatherArgs &args, long long p) {
+struct GatherPx {
+    T *dst;
+    size_t n;
+    int q;
+    T v[4];
+};
+
+template <typename T>
+__device__ __forceinline__ void gather_fetch(const GatherArgs &args, long long p, GatherPx<T> &g) {
     int l = 0;
     while (l + 1 < args.ng && p >= args.first[l + 1]) ++l;
     const int w = args.lw[l], h = args.lh[l];
@@ -1255,17 +1264,62 @@ __device__ __forceinline__ void gather_body(const GatherArgs &args, long long p)
     const size_t planeI = static_cast<size_t>(args.W) * args.H;
     const size_t src = static_cast<size_t>(fdiv(y * args.H, h, rh)) * args.W + fdiv(x * args.W, w, rw);
     const T *I = static_cast<const T *>(args.I);
-    T *dst = reinterpret_cast<T *>(args.pyr + args.off[l]);
-    const size_t n = static_cast<size_t>(w) * h;
+    g.dst = reinterpret_cast<T *>(args.pyr + args.off[l]);
+    g.n = static_cast<size_t>(w) * h;
+    g.q = q;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) dst[c * n + q] = I[c * planeI + src];
-    dst[3 * n + q] = static_cast<const T *>(args.A)[src];
+    for (int c = 0; c < 3; ++c) g.v[c] = I[c * planeI + src];
+    g.v[3] = static_cast<const T *>(args.A)[src];
+}
+
+template <typename T>
+__device__ __forceinline__ void gather_put(const GatherPx<T> &g) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) g.dst[c * g.n + g.q] = g.v[c];
+}
+
+template <typename T>
+__device__ __forceinline__ void gather_body(const GatherArgs &args, long long p) {
+    GatherPx<T> g;
+    gather_fetch<T>(args, p, g);
+    gather_put<T>(g);
 }
 
 template <typename T>
 __global__ __launch_bounds__(256) void gather_kernel(GatherArgs args) {
     const long long p = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (p < args.first[args.ng]) gather_body<T>(args, p);
+}
+
+// The coarse block and the gather of the levels after it in one launch.  Workgroup 0 runs the
+// coarse levels (their inputs come from full resolution); the others copy the compact inputs of
+// the later levels, grid-stride, kGatherUnroll pixels per thread in flight at once.  The levels
+// that read those copies run in later launches.
+constexpr int kGatherUnroll = 8;
+constexpr int kGatherBlocksMax = 255;   // every CU but the coarse block's
+
+template <typename T>
+__global__ __launch_bounds__(kCoarseThreads) void coarse_gather_kernel(CoarseArgs cargs,
+                                                                       GatherArgs gargs) {
+    __shared__ CoarseLds lds;
+    if (blockIdx.x == 0) {
+        coarse_body<T>(cargs, lds);
+        return;
+    }
+    const long long total = gargs.first[gargs.ng];
+    const long long stride = static_cast<long long>(gridDim.x - 1) * kCoarseThreads;
+    for (long long base = static_cast<long long>(blockIdx.x - 1) * kCoarseThreads + threadIdx.x;
+         base < total; base += stride * kGatherUnroll) {
+        GatherPx<T> g[kGatherUnroll];
+#pragma unroll
+        for (int u = 0; u < kGatherUnroll; ++u) {   // every load first ...
+            const long long p = base + u * stride;
+            if (p < total) gather_fetch<T>(gargs, p, g[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < kGatherUnroll; ++u)      // ... then the stores
+            if (base + u * stride < total) gather_put<T>(g[u]);
+    }
 }
 
 // Batch: `first` holds each image's first pixel in the concatenation of all images' gathers.
@@ -1409,12 +1463,14 @@ void make_gather_args(const Plan &plan, const void *I, const void *A, void *pyr,
     a->pyr = static_cast<char *>(pyr);
     a->ng = plan.ng;
     long long total = 0;
-    for (int i = 0; i < plan.ng; ++i) {
-        a->lw[i] = plan.lv[i].w;
-        a->lh[i] = plan.lv[i].h;
-        a->first[i] = total;
-        a->off[i] = static_cast<long long>(plan.pyr_lv[i]);
+    for (int i = 0, k = 0; i < plan.n; ++i) {
+        if (!plan.copy[i]) continue;
+        a->lw[k] = plan.lv[i].w;
+        a->lh[k] = plan.lv[i].h;
+        a->first[k] = total;
+        a->off[k] = static_cast<long long>(plan.pyr_lv[i]);
         total += static_cast<long long>(plan.lv[i].w) * plan.lv[i].h;
+        ++k;
     }
     a->first[plan.ng] = total;
 }
@@ -1438,6 +1494,21 @@ int launch_gather(const Plan &plan, const void *I, const void *A, void *pyr, int
     const int blocks = static_cast<int>((gather_units(a) + 255) / 256);
     FGE_DISPATCH(storage, gather_kernel, dim3(blocks), dim3(256), 0,
                  static_cast<hipStream_t>(stream), a);
+    return static_cast<int>(hipGetLastError());
+}
+
+int launch_coarse_gather(const Plan &plan, const LevelSrc &src, void *Fo, void *Bo, float omega,
+                         float eps, const void *I, const void *A, void *pyr, int storage,
+                         void *stream) {
+    CoarseArgs c;
+    make_coarse_args(plan, src, Fo, Bo, omega, eps, &c);
+    GatherArgs g;
+    make_gather_args(plan, I, A, pyr, &g);
+    const long long per_block = static_cast<long long>(kCoarseThreads) * kGatherUnroll;
+    const long long want = (gather_units(g) + per_block - 1) / per_block;
+    const int gblocks = static_cast<int>(want < kGatherBlocksMax ? want : kGatherBlocksMax);
+    FGE_DISPATCH(storage, coarse_gather_kernel, dim3(1 + gblocks), dim3(kCoarseThreads), 0,
+                 static_cast<hipStream_t>(stream), c, g);
     return static_cast<int>(hipGetLastError());
 }
 

@@ -40,7 +40,7 @@ bool params_valid(const fge_params &p) {
 
 static size_t align256(size_t v) { return (v + 255) & ~static_cast<size_t>(255); }
 
-fge_status make_plan(int W, int H, const fge_params &p, Plan *out) {
+fge_status make_plan(int W, int H, const fge_params &p, Plan *out, bool single_image) {
     if (W < 1 || H < 1 || W > kMaxSide || H > kMaxSide) return FGE_EINVAL;
     if (!params_valid(p)) return FGE_EINVAL;
     Plan pl;
@@ -106,22 +106,44 @@ fge_status make_plan(int W, int H, const fge_params &p, Plan *out) {
     pl.buf_off[1] = align256(6 * pl.buf_px[0] * pl.elem);
     pl.ws_bytes = pl.buf_px[1] ? pl.buf_off[1] + align256(6 * pl.buf_px[1] * pl.elem)
                                : (pl.buf_px[0] ? pl.buf_off[1] : 0);
-    // Gather pre-pass for the small coarse and tile levels, whose nearest-neighbour reads from
-    // full resolution touch one cache line per pixel: one GPU-wide kernel copies them into
-    // compact per-level planes first.  Not when the full image is itself that small.
+    // Compact inputs.  A level below full resolution reads I and alpha through the nearest map,
+    // which touches far more cache lines than it uses (all of every mapped row at 2:1, one line
+    // per pixel further down).  Not when the full image is itself small.
+    //  - Single image with a coarse block: the coarse block runs on one CU for tens of
+    //    microseconds while the rest of the GPU idles, so the same launch copies the inputs of
+    //    every level after the block except the finest into compact planes, and the coarse
+    //    block reads its own (tiny) levels from full resolution.  The staged levels then read
+    //    their inputs with the identity map (the streaming kernel's paired loads apply to 2:1
+    //    levels).
+    //  - Otherwise a pre-pass launch copies the small coarse and tile levels.
     pl.ng = 0;
-    if (static_cast<long>(W) * H > kGatherMaxPx)
-        while (pl.ng < pl.n &&
-               (pl.kind[pl.ng] == kKindCoarse || pl.kind[pl.ng] == kKindTile) &&
-               static_cast<long>(pl.lv[pl.ng].w) * pl.lv[pl.ng].h <= kGatherMaxPx)
-            ++pl.ng;
+    pl.gather_in_coarse = false;
+    for (int i = 0; i < pl.n; ++i) pl.copy[i] = false;
+    if (static_cast<long>(W) * H > kGatherMaxPx) {
+        size_t staged = 0;   // bytes of the staged copies, which must fit in F (3 W H elements)
+        for (int i = pl.nc; i < pl.n - 1; ++i)
+            staged += align256(4 * static_cast<size_t>(pl.lv[i].w) * pl.lv[i].h * pl.elem);
+        if (single_image && pl.nc > 0 && pl.n - 1 > pl.nc && p.kernel != FGE_KERNEL_NAIVE &&
+            staged <= 3 * static_cast<size_t>(W) * H * pl.elem) {
+            pl.gather_in_coarse = true;
+            for (int i = pl.nc; i < pl.n - 1; ++i) pl.copy[i] = true;
+        } else {
+            for (int i = 0; i < pl.n && (pl.kind[i] == kKindCoarse || pl.kind[i] == kKindTile) &&
+                            static_cast<long>(pl.lv[i].w) * pl.lv[i].h <= kGatherMaxPx;
+                 ++i)
+                pl.copy[i] = true;
+        }
+        for (int i = 0; i < pl.n; ++i) pl.ng += pl.copy[i];
+        if (pl.ng == 0) pl.gather_in_coarse = false;
+    }
     pl.pyr_off = pl.ws_bytes;
     size_t pyr = 0;
-    for (int i = 0; i < pl.ng; ++i) {
+    for (int i = 0; i < pl.n; ++i) {
+        if (!pl.copy[i]) continue;
         pl.pyr_lv[i] = pyr;
         pyr += align256(4 * static_cast<size_t>(pl.lv[i].w) * pl.lv[i].h * pl.elem);
     }
-    pl.ws_bytes += pyr;
+    if (!pl.gather_in_coarse) pl.ws_bytes += pyr;
     *out = pl;
     return FGE_OK;
 }
@@ -137,10 +159,14 @@ void level_state(const Plan &pl, char *ws, int j, void *F, void *B, void **f, vo
     *b = base + 3 * static_cast<size_t>(pl.lv[j].w) * pl.lv[j].h * pl.elem;
 }
 
-void level_source(const Plan &pl, const char *ws, int j, const void *I, const void *A,
+char *pyr_base(const Plan &pl, char *ws, void *F) {
+    return pl.gather_in_coarse ? static_cast<char *>(F) : ws + pl.pyr_off;
+}
+
+void level_source(const Plan &pl, const char *ws, const void *F, int j, const void *I, const void *A,
                   const void **Ij, const void **Aj, int *Wj, int *Hj) {
-    if (j < pl.ng) {
-        const char *base = ws + pl.pyr_off + pl.pyr_lv[j];
+    if (pl.copy[j]) {
+        const char *base = pyr_base(pl, const_cast<char *>(ws), const_cast<void *>(F)) + pl.pyr_lv[j];
         *Ij = base;
         *Aj = base + 3 * static_cast<size_t>(pl.lv[j].w) * pl.lv[j].h * pl.elem;
         *Wj = pl.lv[j].w;
@@ -156,7 +182,7 @@ void level_source(const Plan &pl, const char *ws, int j, const void *I, const vo
 LevelIO level_io(const Plan &pl, char *ws, int j, const void *I, const void *A, void *F, void *B,
                  float omega, float eps) {
     LevelIO io{};
-    level_source(pl, ws, j, I, A, &io.I, &io.A, &io.W, &io.H);
+    level_source(pl, ws, F, j, I, A, &io.I, &io.A, &io.W, &io.H);
     if (j > 0) {
         void *fp, *bp;
         level_state(pl, ws, j - 1, F, B, &fp, &bp);
@@ -176,10 +202,10 @@ LevelIO level_io(const Plan &pl, char *ws, int j, const void *I, const void *A, 
     return io;
 }
 
-LevelSrc coarse_src(const Plan &pl, const char *ws, const void *I, const void *A) {
+LevelSrc coarse_src(const Plan &pl, const char *ws, const void *F, const void *I, const void *A) {
     LevelSrc src{};
     for (int j = 0; j < pl.nc; ++j)
-        level_source(pl, ws, j, I, A, &src.I[j], &src.A[j], &src.W[j], &src.H[j]);
+        level_source(pl, ws, F, j, I, A, &src.I[j], &src.A[j], &src.W[j], &src.H[j]);
     return src;
 }
 

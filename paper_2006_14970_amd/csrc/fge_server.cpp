@@ -358,7 +358,7 @@ fge_status enqueue_tick(fge_server *s) {
     for (size_t k = 0; k < fresh.size(); ++k) {
         Request *r = fresh[k];
         char *ws = s->arena + r->ws_off;
-        const fge::LevelSrc src = fge::coarse_src(r->plan, ws, r->I, r->A);
+        const fge::LevelSrc src = fge::coarse_src(r->plan, ws, r->F, r->I, r->A);
         void *fo, *bo;
         fge::level_state(r->plan, ws, r->plan.nc - 1, r->F, r->B, &fo, &bo);
         fge::make_coarse_args(r->plan, src, fo, bo, om, ep,

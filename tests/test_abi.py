@@ -183,11 +183,20 @@ def test_server_host_functions(fge):
     assert fge.server_reserved_bytes(c) == 2 * (16 << 20)
     assert fge.server_reserved_bytes(fge.server_config(pipeline_depth=3)) == 3 * (16 << 20)
     p16 = fge.default_params(storage=fge.F16)
-    for (W, H) in ((4096, 3072), (300, 7), (1, 1), (1920, 1080)):
-        ws = fge.workspace_bytes(W, H, p16)
-        assert fge.server_request_bytes(W, H, p16) == 20 * W * H + (ws + 255) // 256 * 256
-        assert fge.server_request_bytes(W, H) == 40 * W * H + \
-            (fge.workspace_bytes(W, H) + 255) // 256 * 256
+    # The footprint is I, alpha, F, B plus the served plan's workspace.  For images above
+    # 64K px the single-image plan keeps its compact input copies in F instead of the workspace,
+    # so the served workspace exceeds fge_workspace_bytes by the small levels' copies (levels of
+    # at most 64K px: 4 planes of fewer than 2^17 px in all).
+    for (W, H), staged in (((4096, 3072), True), ((300, 7), False), ((1, 1), False),
+                           ((1920, 1080), True)):
+        for p, elem in ((p16, 2), (None, 4)):
+            ws = fge.workspace_bytes(W, H, p) if p else fge.workspace_bytes(W, H)
+            got = fge.server_request_bytes(W, H, p) if p else fge.server_request_bytes(W, H)
+            extra = got - (10 * elem * W * H + (ws + 255) // 256 * 256)
+            if staged:
+                assert 0 < extra <= 4 * elem * (1 << 17) + 16 * 256, (W, H, elem, extra)
+            else:
+                assert extra == 0, (W, H, elem, extra)
     assert fge.server_request_bytes(0, 5) == 0
     lib = fge.load()
     h = ctypes.c_void_p()
@@ -332,3 +341,15 @@ def test_level_options_host_side(fge):
     assert run(odd) == fge.FGE_EINVAL
     assert run(fge.level_options("smooth", tol=1e-4, max_sweeps=0)) == fge.FGE_EINVAL
     assert run(smooth, ws=None) == fge.FGE_EWORKSPACE
+
+
+def test_staged_inputs_do_not_grow_workspace(fge):
+    """A large single image stages the compact inputs of its intermediate levels in F's memory
+    (F is written only by the finest level), so its workspace is the two ping-pong state
+    buffers alone: level 11 (2048x1573) in one, level 10 (1024x806) in the other."""
+    def a256(x):
+        return (x + 255) // 256 * 256
+    for elem, p in ((4, None), (2, fge.default_params(storage=fge.F16))):
+        want = a256(6 * 2048 * 1573 * elem) + a256(6 * 1024 * 806 * elem)
+        got = fge.workspace_bytes(4096, 3072, p) if p else fge.workspace_bytes(4096, 3072)
+        assert got == want, (elem, got, want)
