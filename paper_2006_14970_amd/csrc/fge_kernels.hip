@@ -1338,15 +1338,16 @@ __global__ __launch_bounds__(256) void gather_batch_kernel(const GatherArgs *des
 }
 
 int auto_strip_rows(int w, int h) {
-    // Large levels: about two waves per SIMD (256 CUs x 4 SIMDs x 2), so one wave's memory
-    // waits overlap the other's arithmetic.  Smaller levels: up to one wave per SIMD with strips
-    // of at most 28 rows, which keeps the halo overhead (8 extra rows per strip) bounded.
+    // The height that gives one round of two waves per SIMD (256 CUs x 4 SIMDs x 2), so one
+    // wave's memory waits overlap the other's arithmetic, clamped to [8, 16] rows.  Measured at
+    // 4096x3072 over 6..64 rows: levels whose round would need taller strips run faster as
+    // several rounds of 16-row strips (the XCD-chunked block order then keeps each XCD's
+    // resident strips within a band of ~120 rows, whose shared halo rows hit in its L2) in spite
+    // of the larger halo share; below 8 rows the halo (9 extra rows per strip) dominates.
     const long nx = fine_strips_x(w);
     const long two = (static_cast<long>(h) * nx + 2047) / 2048;
-    const long one = (static_cast<long>(h) * nx + 1023) / 1024;
-    long rows = two > 28 ? two : (one < 28 ? one : 28);
+    long rows = two < 8 ? 8 : (two > 16 ? 16 : two);
     rows = (rows + 1) & ~1L;
-    if (rows < 8) rows = 8;
     if (rows > h) rows = h;
     return static_cast<int>(rows);
 }
