@@ -165,6 +165,13 @@ fge_status fge_estimate_foreground(const void *I, const void *alpha, int32_t W, 
         if (err) return FGE_EHIP;
     }
     for (int i = plan.nc; i < n; ++i) {
+        if (i == plan.pyr_first) {   // the run of tile levels in one launch
+            LaunchTimer timer(n - 1 - plan.pyr_last, s);   // recorded under the run's last level
+            if (fge::launch_pyramid(plan, ws, I, alpha, F, B, prm.omega, prm.eps_r, prm.storage, s))
+                return FGE_EHIP;
+            i = plan.pyr_last;
+            continue;
+        }
         const fge::LevelIO io = fge::level_io(plan, ws, i, I, alpha, F, B, prm.omega, prm.eps_r);
         LaunchTimer timer(n - 1 - i, s);
         int err = 0;

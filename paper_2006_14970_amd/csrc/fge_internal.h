@@ -32,10 +32,12 @@ struct Plan {
     Level lv[kMaxLevels];
     int elem = 4;   // bytes per stored element
     // Two ping-pong state buffers in the workspace.  Each holds F (3 planes) then B (3 planes)
-    // of one level at that level's size.  Level i < n-1 lives in buffer (n - 2 - i) % 2; the
-    // last level is written straight into the caller's F and B.
+    // of one level at that level's size.  A stored level i < n-1 lives in buffer buf_of[i]
+    // (the stored levels alternate from the last one down; -1: not stored); the last level is
+    // written straight into the caller's F and B.
     size_t buf_off[2] = {0, 0};
     size_t buf_px[2] = {0, 0};
+    int buf_of[kMaxLevels] = {};
     size_t ws_bytes = 0;
     int kind[kMaxLevels] = {};     // per fine level: a LevelKind
     // Gather: the ng levels with copy[i] set get a compact copy of their resized I (3 planes)
@@ -48,6 +50,8 @@ struct Plan {
     int ng = 0;
     bool copy[kMaxLevels] = {};
     bool gather_in_coarse = false;
+    // Single image: tile levels [pyr_first, pyr_last] run as one pyramid launch (-1: none).
+    int pyr_first = -1, pyr_last = -1;
     size_t pyr_off = 0;
     size_t pyr_lv[kMaxLevels] = {};
 };
@@ -99,7 +103,12 @@ LevelSrc coarse_src(const Plan &pl, const char *ws, const void *F, const void *I
 
 int launch_gather(const Plan &plan, const void *I, const void *A, void *pyr, int storage,
                   void *stream);
-// The coarse block plus the gather of levels [g0, g0 + ng) in one launch (gather_in_coarse).
+// Whether every region of a pyramid run over levels [first, last] fits the tile kernel's LDS
+// buffer (checked for every output tile), and the run's launch.
+bool pyramid_fits(const Plan &plan, int first, int last);
+int launch_pyramid(const Plan &plan, char *ws, const void *I, const void *A, void *F, void *B,
+                   float omega, float eps, int storage, void *stream);
+// The coarse block plus the gather of the staged levels in one launch (gather_in_coarse).
 int launch_coarse_gather(const Plan &plan, const LevelSrc &src, void *Fo, void *Bo, float omega,
                          float eps, const void *I, const void *A, void *pyr, int storage,
                          void *stream);
@@ -134,6 +143,27 @@ struct TileArgs {
     void *Bo;
     int w, h;
     int tiles_x;
+    float omega, eps;
+};
+
+// A run of consecutive tile levels in one launch (pyramid kernel): per level its I and alpha
+// source and its size; the stored level before the run; the run's last level's outputs.
+constexpr int kPyrMaxLevels = 8;
+struct PyramidLevel {
+    const void *I;
+    const void *A;
+    int W, H;
+    int w, h;
+};
+struct PyramidArgs {
+    int nl;
+    PyramidLevel lv[kPyrMaxLevels];
+    const void *Fp;
+    const void *Bp;
+    int wp, hp;
+    void *Fo;
+    void *Bo;
+    int tiles_x, tiles;
     float omega, eps;
 };
 

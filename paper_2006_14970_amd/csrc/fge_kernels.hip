@@ -45,6 +45,12 @@ __device__ __forceinline__ void stf(T *p, float v) {
 
 __device__ __forceinline__ float clamp01(float v) { return fminf(fmaxf(v, 0.0f), 1.0f); }
 
+// v rounded to the storage type T and back (the value a store and a reload would give).
+template <typename T>
+__device__ __forceinline__ float round_to(float v) {
+    return static_cast<float>(static_cast<T>(v));
+}
+
 // Reciprocal with v_rcp_f32 (1 ulp); its arguments here are in [0.02, 4].
 __device__ __forceinline__ float rcp(float v) { return __builtin_amdgcn_rcpf(v); }
 
@@ -392,31 +398,58 @@ struct TileLds {
     float4 B[kTilePx];    // (B0, B1, B2, unused)
 };
 
-template <typename T>
-__device__ __forceinline__ void tile_body(const TileArgs &args, int tile, TileLds &lds) {
-    float4 *sFA = lds.FA;
-    float4 *sB = lds.B;
+// The part of a level one tile pass computes: region [rx0, rx0 + rw) x [ry0, ry0 + rh) of the
+// level (the core plus a ring of up to kTileHalo pixels, clamped to the image), and the core
+// [cx0, cx1) x [cy0, cy1) whose values come out exact.
+struct TileRegion {
+    int rx0, ry0, rw, rh;
+    int cx0, cx1, cy0, cy1;
+};
 
-    const T *I = static_cast<const T *>(args.I);
-    const T *A = static_cast<const T *>(args.A);
-    const T *Fp = static_cast<const T *>(args.Fp);
-    const T *Bp = static_cast<const T *>(args.Bp);
-    const int w = args.w, h = args.h;
-    const size_t planeI = static_cast<size_t>(args.W) * args.H;
-    const size_t planeP = static_cast<size_t>(args.wp) * args.hp;
-    const float omega = args.omega, eps = args.eps;
+__device__ __forceinline__ TileRegion tile_region(int cx0, int cx1, int cy0, int cy1, int w, int h) {
+    TileRegion R;
+    R.cx0 = cx0;
+    R.cx1 = cx1;
+    R.cy0 = cy0;
+    R.cy1 = cy1;
+    R.rx0 = max(0, cx0 - kTileHalo);
+    R.ry0 = max(0, cy0 - kTileHalo);
+    R.rw = min(w, cx1 + kTileHalo) - R.rx0;
+    R.rh = min(h, cy1 + kTileHalo) - R.ry0;
+    return R;
+}
+
+// Where a tile pass takes the previous level's F and B: global memory (the stored level), or
+// the region of the previous level another pass of the same workgroup left in LDS.
+struct TilePrev {
+    const void *Fp, *Bp;            // global: 3 planes of wp x hp each
+    const float4 *sFA, *sB;         // LDS: the previous level's region records
+    int rx0, ry0, rw;               // LDS: that region's origin and width
+    int wp, hp;
+};
+
+// One level of a tile pass over region R: load the region (alpha, F and B into LDS, I into
+// registers), run the level's red-black half-sweeps with neighbours clamped to the region, and
+// store the core to Fo, Bo when they are given.  Where the region edge is the image border the
+// clamp is exactly Algorithm 1's; elsewhere the ring absorbs the stale neighbours (one ring per
+// half-sweep).  Previous-level values taken from LDS are rounded to the storage type first, as
+// they would have been on their way through memory, so the result does not depend on the path.
+template <typename T, bool PREV_LDS>
+__device__ __forceinline__ void tile_level(const T *I, const T *A, int W, int H, int w, int h,
+                                           const TilePrev &pv, const TileRegion &R, float4 *sFA,
+                                           float4 *sB, float omega, float eps, T *Fo, T *Bo) {
+    const T *Fp = static_cast<const T *>(pv.Fp);
+    const T *Bp = static_cast<const T *>(pv.Bp);
+    const size_t planeI = static_cast<size_t>(W) * H;
+    const size_t planeP = static_cast<size_t>(pv.wp) * pv.hp;
     const int tid = threadIdx.x;
 
-    const int tx = tile % args.tiles_x, ty = tile / args.tiles_x;
-    const int cx0 = tx * kTileCore, cy0 = ty * kTileCore;
-    const int cx1 = min(w, cx0 + kTileCore), cy1 = min(h, cy0 + kTileCore);
-    const int rx0 = max(0, cx0 - kTileHalo), ry0 = max(0, cy0 - kTileHalo);
-    const int rw = min(w, cx1 + kTileHalo) - rx0, rh = min(h, cy1 + kTileHalo) - ry0;
+    const int rx0 = R.rx0, ry0 = R.ry0, rw = R.rw, rh = R.rh;
     const int pw = (rw + 1) >> 1;
     const int npairs = pw * rh;
     const float rpw = rcp(static_cast<float>(pw));
     const float rcw = rcp(static_cast<float>(w)), rch = rcp(static_cast<float>(h));
-    const bool same = args.W == w && args.H == h;   // compact copy or the full-size level
+    const bool same = W == w && H == h;   // compact copy or the full-size level
 
     // Owned pairs: q = tid + k * threads covers region columns (2j, 2j+1) of region row y.
     // All global gathers are issued before any LDS store, so they are in flight together.
@@ -437,17 +470,25 @@ __device__ __forceinline__ void tile_body(const TileArgs &args, int tile, TileLd
             const bool ok = s ? qv1[k] : qv0[k];
             const int gx = rx0 + (ok ? qx[k] + s : 0), gy = ry0 + (ok ? y : 0);
             const size_t src = same ? static_cast<size_t>(gy) * w + gx
-                                    : static_cast<size_t>(fdiv(gy * args.H, h, rch)) * args.W +
-                                          fdiv(gx * args.W, w, rcw);
-            const size_t prv = static_cast<size_t>(fdiv(gy * args.hp, h, rch)) * args.wp +
-                               fdiv(gx * args.wp, w, rcw);
+                                    : static_cast<size_t>(fdiv(gy * H, h, rch)) * W +
+                                          fdiv(gx * W, w, rcw);
+            const int px = fdiv(gx * pv.wp, w, rcw), py = fdiv(gy * pv.hp, h, rch);
             const float a = ldf(A + src);
 #pragma unroll
             for (int c = 0; c < 3; ++c) iv[k][s][c] = ldf(I + c * planeI + src);
-            lf[k][s] = make_float4(ldf(Fp + prv), ldf(Fp + planeP + prv), ldf(Fp + 2 * planeP + prv), a);
-            lb[k][s] = make_float4(ldf(Bp + prv), ldf(Bp + planeP + prv), ldf(Bp + 2 * planeP + prv), 0.0f);
+            if constexpr (PREV_LDS) {
+                const int li = (py - pv.ry0) * pv.rw + (px - pv.rx0);
+                const float4 f = pv.sFA[ok ? li : 0], g = pv.sB[ok ? li : 0];
+                lf[k][s] = make_float4(round_to<T>(f.x), round_to<T>(f.y), round_to<T>(f.z), a);
+                lb[k][s] = make_float4(round_to<T>(g.x), round_to<T>(g.y), round_to<T>(g.z), 0.0f);
+            } else {
+                const size_t prv = static_cast<size_t>(py) * pv.wp + px;
+                lf[k][s] = make_float4(ldf(Fp + prv), ldf(Fp + planeP + prv), ldf(Fp + 2 * planeP + prv), a);
+                lb[k][s] = make_float4(ldf(Bp + prv), ldf(Bp + planeP + prv), ldf(Bp + 2 * planeP + prv), 0.0f);
+            }
         }
     }
+    // (From LDS the previous region and this one are different buffers: no barrier between.)
 #pragma unroll
     for (int k = 0; k < kTilePairsPerThread; ++k)
 #pragma unroll
@@ -551,15 +592,14 @@ __device__ __forceinline__ void tile_body(const TileArgs &args, int tile, TileLd
         }
     }
 
+    if (!Fo) return;
     // Store the core.
-    T *Fo = static_cast<T *>(args.Fo);
-    T *Bo = static_cast<T *>(args.Bo);
     const size_t planeO = static_cast<size_t>(w) * h;
-    const int cw_ = cx1 - cx0, ch_ = cy1 - cy0;
+    const int cw_ = R.cx1 - R.cx0, ch_ = R.cy1 - R.cy0;
     const float rcw_ = rcp(static_cast<float>(cw_));
     for (int p = tid; p < cw_ * ch_; p += kTileThreads) {
         const int yy = fdiv(p, cw_, rcw_), xx = p - yy * cw_;
-        const int gx = cx0 + xx, gy = cy0 + yy;
+        const int gx = R.cx0 + xx, gy = R.cy0 + yy;
         const int li = (gy - ry0) * rw + (gx - rx0);
         const float4 f = sFA[li], g = sB[li];
         const size_t o = static_cast<size_t>(gy) * w + gx;
@@ -572,10 +612,106 @@ __device__ __forceinline__ void tile_body(const TileArgs &args, int tile, TileLd
     }
 }
 
+// One fine level, output tile `tile`: the level's F and B come from the stored previous level.
+template <typename T>
+__device__ __forceinline__ void tile_body(const TileArgs &args, int tile, TileLds &lds) {
+    const int w = args.w, h = args.h;
+    const int tx = tile % args.tiles_x, ty = tile / args.tiles_x;
+    const int cx0 = tx * kTileCore, cy0 = ty * kTileCore;
+    const TileRegion R = tile_region(cx0, min(w, cx0 + kTileCore), cy0, min(h, cy0 + kTileCore), w, h);
+    TilePrev pv{};
+    pv.Fp = args.Fp;
+    pv.Bp = args.Bp;
+    pv.wp = args.wp;
+    pv.hp = args.hp;
+    tile_level<T, false>(static_cast<const T *>(args.I), static_cast<const T *>(args.A), args.W,
+                         args.H, w, h, pv, R, lds.FA, lds.B, args.omega, args.eps,
+                         static_cast<T *>(args.Fo), static_cast<T *>(args.Bo));
+}
+
 template <typename T>
 __global__ __launch_bounds__(kTileThreads) void tile_kernel(TileArgs args) {
     __shared__ TileLds lds;
     tile_body<T>(args, blockIdx.x, lds);
+}
+
+// ------------------------------------------------------------------------------------------
+// Pyramid kernel: a run of consecutive tile levels in one launch.
+// ------------------------------------------------------------------------------------------
+//
+// Workgroup t owns output tile t of the run's last level and computes, from the run's first
+// level up, exactly the region of each level its tile depends on: the last level's region is
+// the tile plus its ring; a lower level's core is the set of rows and columns the nearest map of
+// the level above reads over that region (an interval: the map is monotone), and its region
+// that core plus its own ring.  Each level's region stays in LDS for the next one; only the
+// first level reads a stored previous level and only the last stores its core.  Neighbouring
+// workgroups recompute overlapping lower-level regions; in exchange the run is one launch, not
+// one per level, and its intermediate levels never go through memory.  Every level uses the
+// tile kernel's arithmetic, so the stored values are bit-identical to a per-level run.
+
+// Regions of the run for output tile `tile` (levels 0..nl-1 of the run, last = output level).
+// The host (pyramid_fits) evaluates the same function to check that every region fits LDS.
+__host__ __device__ inline void pyramid_regions(const PyramidArgs &a, int tile, TileRegion *R) {
+    const int L = a.nl;
+    const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
+    int cx0 = tx * kTileCore, cy0 = ty * kTileCore;
+    int cx1 = cx0 + kTileCore < a.lv[L - 1].w ? cx0 + kTileCore : a.lv[L - 1].w;
+    int cy1 = cy0 + kTileCore < a.lv[L - 1].h ? cy0 + kTileCore : a.lv[L - 1].h;
+    for (int l = L - 1; l >= 0; --l) {
+        const int w = a.lv[l].w, h = a.lv[l].h;
+        TileRegion r;
+        r.cx0 = cx0;
+        r.cx1 = cx1;
+        r.cy0 = cy0;
+        r.cy1 = cy1;
+        r.rx0 = cx0 - kTileHalo > 0 ? cx0 - kTileHalo : 0;
+        r.ry0 = cy0 - kTileHalo > 0 ? cy0 - kTileHalo : 0;
+        r.rw = (cx1 + kTileHalo < w ? cx1 + kTileHalo : w) - r.rx0;
+        r.rh = (cy1 + kTileHalo < h ? cy1 + kTileHalo : h) - r.ry0;
+        R[l] = r;
+        if (l == 0) break;
+        const int wp = a.lv[l - 1].w, hp = a.lv[l - 1].h;
+        cx0 = r.rx0 * wp / w;
+        cx1 = (r.rx0 + r.rw - 1) * wp / w + 1;
+        cy0 = r.ry0 * hp / h;
+        cy1 = (r.ry0 + r.rh - 1) * hp / h + 1;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kTileThreads) void pyramid_kernel(PyramidArgs args) {
+    __shared__ TileLds buf[2];
+    __shared__ TileRegion sR[kPyrMaxLevels];
+    if (threadIdx.x == 0) pyramid_regions(args, blockIdx.x, sR);
+    lds_sync();
+    const int L = args.nl;
+    for (int l = 0; l < L; ++l) {
+        const PyramidLevel &d = args.lv[l];
+        const TileRegion R = sR[l];
+        T *Fo = l == L - 1 ? static_cast<T *>(args.Fo) : nullptr;
+        T *Bo = l == L - 1 ? static_cast<T *>(args.Bo) : nullptr;
+        TilePrev pv{};
+        if (l == 0) {
+            pv.Fp = args.Fp;
+            pv.Bp = args.Bp;
+            pv.wp = args.wp;
+            pv.hp = args.hp;
+            tile_level<T, false>(static_cast<const T *>(d.I), static_cast<const T *>(d.A), d.W, d.H,
+                                 d.w, d.h, pv, R, buf[0].FA, buf[0].B, args.omega, args.eps, Fo, Bo);
+        } else {
+            const TileRegion P = sR[l - 1];
+            pv.sFA = buf[(l - 1) & 1].FA;
+            pv.sB = buf[(l - 1) & 1].B;
+            pv.rx0 = P.rx0;
+            pv.ry0 = P.ry0;
+            pv.rw = P.rw;
+            pv.wp = args.lv[l - 1].w;
+            pv.hp = args.lv[l - 1].h;
+            tile_level<T, true>(static_cast<const T *>(d.I), static_cast<const T *>(d.A), d.W, d.H,
+                                d.w, d.h, pv, R, buf[l & 1].FA, buf[l & 1].B, args.omega, args.eps,
+                                Fo, Bo);
+        }
+    }
 }
 
 
@@ -1527,6 +1663,64 @@ int launch_fine_fused(const LevelIO &io, int strip_rows, int storage, void *stre
     make_fine_args(io, strip_rows, &a);
     const int blocks = kXcds * fine_block_chunk(fine_units(a));
     FGE_DISPATCH(storage, fine_kernel, dim3(blocks), dim3(64 * kWavesPerBlock), 0,
+                 static_cast<hipStream_t>(stream), a);
+    return static_cast<int>(hipGetLastError());
+}
+
+void make_pyramid_args(const Plan &plan, char *ws, const void *I, const void *A, void *F,
+                       void *B, float omega, float eps, int first, int last, PyramidArgs *a) {
+    *a = PyramidArgs{};
+    a->nl = last - first + 1;
+    for (int j = first; j <= last; ++j) {
+        const LevelIO io = level_io(plan, ws, j, I, A, F, B, omega, eps);
+        PyramidLevel &d = a->lv[j - first];
+        d.I = io.I;
+        d.A = io.A;
+        d.W = io.W;
+        d.H = io.H;
+        d.w = io.w;
+        d.h = io.h;
+        if (j == first) {
+            a->Fp = io.Fp;
+            a->Bp = io.Bp;
+            a->wp = io.wp;
+            a->hp = io.hp;
+        }
+        if (j == last) {
+            a->Fo = io.Fo;
+            a->Bo = io.Bo;
+            a->tiles_x = (io.w + kTileCore - 1) / kTileCore;
+            a->tiles = a->tiles_x * ((io.h + kTileCore - 1) / kTileCore);
+        }
+    }
+    a->omega = omega;
+    a->eps = eps;
+}
+
+bool pyramid_fits(const Plan &plan, int first, int last) {
+    if (first < 1 || last <= first || last - first + 1 > kPyrMaxLevels) return false;
+    PyramidArgs a{};
+    a.nl = last - first + 1;
+    for (int j = first; j <= last; ++j) {
+        a.lv[j - first].w = plan.lv[j].w;
+        a.lv[j - first].h = plan.lv[j].h;
+    }
+    a.tiles_x = (plan.lv[last].w + kTileCore - 1) / kTileCore;
+    const int tiles = a.tiles_x * ((plan.lv[last].h + kTileCore - 1) / kTileCore);
+    TileRegion R[kPyrMaxLevels];
+    for (int t = 0; t < tiles; ++t) {
+        pyramid_regions(a, t, R);
+        for (int l = 0; l < a.nl; ++l)
+            if (R[l].rw > kTileSide || R[l].rh > kTileSide || R[l].rw < 1 || R[l].rh < 1) return false;
+    }
+    return true;
+}
+
+int launch_pyramid(const Plan &plan, char *ws, const void *I, const void *A, void *F, void *B,
+                   float omega, float eps, int storage, void *stream) {
+    PyramidArgs a;
+    make_pyramid_args(plan, ws, I, A, F, B, omega, eps, plan.pyr_first, plan.pyr_last, &a);
+    FGE_DISPATCH(storage, pyramid_kernel, dim3(a.tiles), dim3(kTileThreads), 0,
                  static_cast<hipStream_t>(stream), a);
     return static_cast<int>(hipGetLastError());
 }

@@ -94,18 +94,6 @@ fge_status make_plan(int W, int H, const fge_params &p, Plan *out, bool single_i
         else
             pl.kind[i] = kKindStream;
     }
-    // Workspace: the state of every level except the last goes through a ping-pong buffer.
-    // Only levels from nc-1 on are materialised (coarser ones live in LDS).
-    const int first_mat = pl.nc > 0 ? pl.nc - 1 : 0;
-    for (int i = first_mat; i < pl.n - 1; ++i) {
-        const int b = (pl.n - 2 - i) % 2;
-        const size_t px = static_cast<size_t>(pl.lv[i].w) * pl.lv[i].h;
-        if (px > pl.buf_px[b]) pl.buf_px[b] = px;
-    }
-    pl.buf_off[0] = 0;
-    pl.buf_off[1] = align256(6 * pl.buf_px[0] * pl.elem);
-    pl.ws_bytes = pl.buf_px[1] ? pl.buf_off[1] + align256(6 * pl.buf_px[1] * pl.elem)
-                               : (pl.buf_px[0] ? pl.buf_off[1] : 0);
     // Compact inputs.  A level below full resolution reads I and alpha through the nearest map,
     // which touches far more cache lines than it uses (all of every mapped row at 2:1, one line
     // per pixel further down).  Not when the full image is itself small.
@@ -114,7 +102,7 @@ fge_status make_plan(int W, int H, const fge_params &p, Plan *out, bool single_i
     //    every level after the block except the finest into compact planes, and the coarse
     //    block reads its own (tiny) levels from full resolution.  The staged levels then read
     //    their inputs with the identity map (the streaming kernel's paired loads apply to 2:1
-    //    levels).
+    //    levels).  The copies live in F, which only the finest level writes.
     //  - Otherwise a pre-pass launch copies the small coarse and tile levels.
     pl.ng = 0;
     pl.gather_in_coarse = false;
@@ -136,6 +124,39 @@ fge_status make_plan(int W, int H, const fge_params &p, Plan *out, bool single_i
         for (int i = 0; i < pl.n; ++i) pl.ng += pl.copy[i];
         if (pl.ng == 0) pl.gather_in_coarse = false;
     }
+    // Single image: a run of at least two tile levels becomes one pyramid launch, when every
+    // region it needs fits the tile buffer.  The run stops before the finest level when the
+    // staged copies live in F: the finest level's stores would overwrite copies that other
+    // workgroups of the same launch still read.
+    pl.pyr_first = pl.pyr_last = -1;
+    if (single_image && p.kernel != FGE_KERNEL_NAIVE) {
+        int a = pl.nc;
+        while (a < pl.n && pl.kind[a] != kKindTile) ++a;
+        int b = a;
+        while (b + 1 < pl.n && pl.kind[b + 1] == kKindTile && b + 1 - a + 1 <= kPyrMaxLevels) ++b;
+        if (pl.gather_in_coarse && b == pl.n - 1) --b;
+        if (a < pl.n && b > a && pyramid_fits(pl, a, b)) {
+            pl.pyr_first = a;
+            pl.pyr_last = b;
+        }
+    }
+    // Workspace: the state of every stored level except the last goes through one of two
+    // buffers, alternating from the last level down, so a level never writes the buffer its
+    // input is in.  Stored are the levels from nc-1 on (coarser ones live in LDS) except those
+    // inside a pyramid run, which stay in LDS too.
+    const int first_mat = pl.nc > 0 ? pl.nc - 1 : 0;
+    for (int i = 0; i < pl.n; ++i) pl.buf_of[i] = -1;
+    for (int i = pl.n - 2, k = 0; i >= first_mat; --i) {
+        if (i >= pl.pyr_first && i < pl.pyr_last) continue;
+        const int b = k++ & 1;
+        pl.buf_of[i] = b;
+        const size_t px = static_cast<size_t>(pl.lv[i].w) * pl.lv[i].h;
+        if (px > pl.buf_px[b]) pl.buf_px[b] = px;
+    }
+    pl.buf_off[0] = 0;
+    pl.buf_off[1] = align256(6 * pl.buf_px[0] * pl.elem);
+    pl.ws_bytes = pl.buf_px[1] ? pl.buf_off[1] + align256(6 * pl.buf_px[1] * pl.elem)
+                               : (pl.buf_px[0] ? pl.buf_off[1] : 0);
     pl.pyr_off = pl.ws_bytes;
     size_t pyr = 0;
     for (int i = 0; i < pl.n; ++i) {
@@ -154,7 +175,11 @@ void level_state(const Plan &pl, char *ws, int j, void *F, void *B, void **f, vo
         *b = B;
         return;
     }
-    char *base = ws + pl.buf_off[(pl.n - 2 - j) % 2];
+    if (pl.buf_of[j] < 0) {   // not stored (inside the coarse block or a pyramid run)
+        *f = *b = nullptr;
+        return;
+    }
+    char *base = ws + pl.buf_off[pl.buf_of[j]];
     *f = base;
     *b = base + 3 * static_cast<size_t>(pl.lv[j].w) * pl.lv[j].h * pl.elem;
 }
