@@ -398,6 +398,15 @@ struct TileLds {
     float4 B[kTilePx];    // (B0, B1, B2, unused)
 };
 
+// Records of a region in LDS, split by red-black colour: pixel (x, y) of the region (relative
+// coordinates, global colour g) at g * kTileHalf + y * pw + x / 2, pw = ceil(width / 2).  The
+// pixels one half-sweep updates then sit at consecutive records for consecutive pairs, and so do
+// the neighbours they read (all of the other colour): 16-byte accesses without bank conflicts.
+constexpr int kTileHalf = kTilePx / 2;   // >= pw * height for every region (width, height <= 40)
+__device__ __forceinline__ int tile_slot(int x, int y, int colour, int pw) {
+    return colour * kTileHalf + y * pw + (x >> 1);
+}
+
 // The part of a level one tile pass computes: region [rx0, rx0 + rw) x [ry0, ry0 + rh) of the
 // level (the core plus a ring of up to kTileHalo pixels, clamped to the image), and the core
 // [cx0, cx1) x [cy0, cy1) whose values come out exact.
@@ -423,24 +432,61 @@ __device__ __forceinline__ TileRegion tile_region(int cx0, int cx1, int cy0, int
 // the region of the previous level another pass of the same workgroup left in LDS.
 struct TilePrev {
     const void *Fp, *Bp;            // global: 3 planes of wp x hp each
-    const float4 *sFA, *sB;         // LDS: the previous level's region records
-    int rx0, ry0, rw;               // LDS: that region's origin and width
+    const float4 *sFA, *sB;         // LDS: the previous level's region records (tile_slot)
+    int rx0, ry0, pw;               // LDS: that region's origin and half width, rounded up
     int wp, hp;
 };
 
-// One level of a tile pass over region R: load the region (alpha, F and B into LDS, I into
-// registers), run the level's red-black half-sweeps with neighbours clamped to the region, and
-// store the core to Fo, Bo when they are given.  Where the region edge is the image border the
-// clamp is exactly Algorithm 1's; elsewhere the ring absorbs the stale neighbours (one ring per
-// half-sweep).  Previous-level values taken from LDS are rounded to the storage type first, as
-// they would have been on their way through memory, so the result does not depend on the path.
+// The level inputs of the pixels one thread owns in a tile pass over region R: pair
+// q = tid + k * threads covers region columns (2j, 2j+1) of region row y.
+struct TileInput {
+    float a[kTilePairsPerThread][2];
+    float iv[kTilePairsPerThread][2][3];
+};
+
+// Issue the gathers of alpha and I of region R (they complete in the background: nothing here
+// waits for them).
+template <typename T>
+__device__ __forceinline__ void tile_fetch(const T *I, const T *A, int W, int H, int w, int h,
+                                           const TileRegion &R, TileInput &in) {
+    const size_t planeI = static_cast<size_t>(W) * H;
+    const int pw = (R.rw + 1) >> 1;
+    const int npairs = pw * R.rh;
+    const float rpw = rcp(static_cast<float>(pw));
+    const float rcw = rcp(static_cast<float>(w)), rch = rcp(static_cast<float>(h));
+    const bool same = W == w && H == h;   // compact copy or the full-size level
+#pragma unroll
+    for (int k = 0; k < kTilePairsPerThread; ++k) {
+        const int q = threadIdx.x + k * kTileThreads;
+        const int y = fdiv(q, pw, rpw);
+        const int x = 2 * (q - y * pw);
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            const bool ok = q < npairs && x + s < R.rw;
+            const int gx = R.rx0 + (ok ? x + s : 0), gy = R.ry0 + (ok ? y : 0);
+            const size_t src = same ? static_cast<size_t>(gy) * w + gx
+                                    : static_cast<size_t>(fdiv(gy * H, h, rch)) * W +
+                                          fdiv(gx * W, w, rcw);
+            in.a[k][s] = ldf(A + src);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) in.iv[k][s][c] = ldf(I + c * planeI + src);
+        }
+    }
+}
+
+// One level of a tile pass over region R, with its inputs fetched (tile_fetch): load F and B
+// of the region (alpha, F and B into LDS), run the level's red-black half-sweeps with
+// neighbours clamped to the region, and store the core to Fo, Bo when they are given.  Where
+// the region edge is the image border the clamp is exactly Algorithm 1's; elsewhere the ring
+// absorbs the stale neighbours (one ring per half-sweep).  Previous-level values taken from LDS
+// are rounded to the storage type first, as they would have been on their way through memory,
+// so the result does not depend on the path.
 template <typename T, bool PREV_LDS>
-__device__ __forceinline__ void tile_level(const T *I, const T *A, int W, int H, int w, int h,
-                                           const TilePrev &pv, const TileRegion &R, float4 *sFA,
-                                           float4 *sB, float omega, float eps, T *Fo, T *Bo) {
+__device__ __forceinline__ void tile_level(const TileInput &in, int w, int h, const TilePrev &pv,
+                                           const TileRegion &R, float4 *sFA, float4 *sB,
+                                           float omega, float eps, T *Fo, T *Bo) {
     const T *Fp = static_cast<const T *>(pv.Fp);
     const T *Bp = static_cast<const T *>(pv.Bp);
-    const size_t planeI = static_cast<size_t>(W) * H;
     const size_t planeP = static_cast<size_t>(pv.wp) * pv.hp;
     const int tid = threadIdx.x;
 
@@ -449,13 +495,11 @@ __device__ __forceinline__ void tile_level(const T *I, const T *A, int W, int H,
     const int npairs = pw * rh;
     const float rpw = rcp(static_cast<float>(pw));
     const float rcw = rcp(static_cast<float>(w)), rch = rcp(static_cast<float>(h));
-    const bool same = W == w && H == h;   // compact copy or the full-size level
 
-    // Owned pairs: q = tid + k * threads covers region columns (2j, 2j+1) of region row y.
-    // All global gathers are issued before any LDS store, so they are in flight together.
+    // Owned pairs as in tile_fetch.  All global gathers are issued before any LDS store, so
+    // they are in flight together.
     int qy[kTilePairsPerThread], qx[kTilePairsPerThread];
     bool qv0[kTilePairsPerThread], qv1[kTilePairsPerThread];
-    float iv[kTilePairsPerThread][2][3];
     float4 lf[kTilePairsPerThread][2], lb[kTilePairsPerThread][2];
 #pragma unroll
     for (int k = 0; k < kTilePairsPerThread; ++k) {
@@ -469,15 +513,10 @@ __device__ __forceinline__ void tile_level(const T *I, const T *A, int W, int H,
         for (int s = 0; s < 2; ++s) {
             const bool ok = s ? qv1[k] : qv0[k];
             const int gx = rx0 + (ok ? qx[k] + s : 0), gy = ry0 + (ok ? y : 0);
-            const size_t src = same ? static_cast<size_t>(gy) * w + gx
-                                    : static_cast<size_t>(fdiv(gy * H, h, rch)) * W +
-                                          fdiv(gx * W, w, rcw);
             const int px = fdiv(gx * pv.wp, w, rcw), py = fdiv(gy * pv.hp, h, rch);
-            const float a = ldf(A + src);
-#pragma unroll
-            for (int c = 0; c < 3; ++c) iv[k][s][c] = ldf(I + c * planeI + src);
+            const float a = in.a[k][s];
             if constexpr (PREV_LDS) {
-                const int li = (py - pv.ry0) * pv.rw + (px - pv.rx0);
+                const int li = tile_slot(px - pv.rx0, py - pv.ry0, (px + py) & 1, pv.pw);
                 const float4 f = pv.sFA[ok ? li : 0], g = pv.sB[ok ? li : 0];
                 lf[k][s] = make_float4(round_to<T>(f.x), round_to<T>(f.y), round_to<T>(f.z), a);
                 lb[k][s] = make_float4(round_to<T>(g.x), round_to<T>(g.y), round_to<T>(g.z), 0.0f);
@@ -494,7 +533,7 @@ __device__ __forceinline__ void tile_level(const T *I, const T *A, int W, int H,
 #pragma unroll
         for (int s = 0; s < 2; ++s)
             if (s ? qv1[k] : qv0[k]) {
-                const int li = qy[k] * rw + qx[k] + s;
+                const int li = tile_slot(qx[k] + s, qy[k], (rx0 + ry0 + qx[k] + s + qy[k]) & 1, pw);
                 sFA[li] = lf[k][s];
                 sB[li] = lb[k][s];
             }
@@ -513,11 +552,12 @@ __device__ __forceinline__ void tile_level(const T *I, const T *A, int W, int H,
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
             const int x = min(qx[k] + s, rw - 1), y = min(qy[k], rh - 1);
-            const int i = y * rw + x;
-            tnb[s][0] = x > 0 ? i - 1 : i;
-            tnb[s][1] = x < rw - 1 ? i + 1 : i;
-            tnb[s][2] = y > 0 ? i - rw : i;
-            tnb[s][3] = y < rh - 1 ? i + rw : i;
+            const int g = (rx0 + ry0 + x + y) & 1;   // this pixel's colour; neighbours have 1 - g
+            const int i = tile_slot(x, y, g, pw);
+            tnb[s][0] = x > 0 ? tile_slot(x - 1, y, g ^ 1, pw) : i;
+            tnb[s][1] = x < rw - 1 ? tile_slot(x + 1, y, g ^ 1, pw) : i;
+            tnb[s][2] = y > 0 ? tile_slot(x, y - 1, g ^ 1, pw) : i;
+            tnb[s][3] = y < rh - 1 ? tile_slot(x, y + 1, g ^ 1, pw) : i;
             const float a = sFA[i].w;
             float sj[4], S = 0.0f;
 #pragma unroll
@@ -537,7 +577,7 @@ __device__ __forceinline__ void tile_level(const T *I, const T *A, int W, int H,
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
             const bool hi = flip ? (c == 0) : (c == 1);
-            cpix[k][c] = qy[k] * rw + qx[k] + (hi ? 1 : 0);
+            cpix[k][c] = tile_slot(qx[k] + (hi ? 1 : 0), qy[k], c, pw);
             cok[k][c] = hi ? qv1[k] : qv0[k];
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
@@ -548,7 +588,7 @@ __device__ __forceinline__ void tile_level(const T *I, const T *A, int W, int H,
             ckb[k][c] = hi ? tkb[1] : tkb[0];
             ca[k][c] = hi ? ta[1] : ta[0];
 #pragma unroll
-            for (int ch = 0; ch < 3; ++ch) ci[k][c][ch] = hi ? iv[k][1][ch] : iv[k][0][ch];
+            for (int ch = 0; ch < 3; ++ch) ci[k][c][ch] = hi ? in.iv[k][1][ch] : in.iv[k][0][ch];
         }
     }
 
@@ -600,7 +640,7 @@ __device__ __forceinline__ void tile_level(const T *I, const T *A, int W, int H,
     for (int p = tid; p < cw_ * ch_; p += kTileThreads) {
         const int yy = fdiv(p, cw_, rcw_), xx = p - yy * cw_;
         const int gx = R.cx0 + xx, gy = R.cy0 + yy;
-        const int li = (gy - ry0) * rw + (gx - rx0);
+        const int li = tile_slot(gx - rx0, gy - ry0, (gx + gy) & 1, pw);
         const float4 f = sFA[li], g = sB[li];
         const size_t o = static_cast<size_t>(gy) * w + gx;
         stf(Fo + o, f.x);
@@ -624,8 +664,10 @@ __device__ __forceinline__ void tile_body(const TileArgs &args, int tile, TileLd
     pv.Bp = args.Bp;
     pv.wp = args.wp;
     pv.hp = args.hp;
-    tile_level<T, false>(static_cast<const T *>(args.I), static_cast<const T *>(args.A), args.W,
-                         args.H, w, h, pv, R, lds.FA, lds.B, args.omega, args.eps,
+    TileInput in;
+    tile_fetch<T>(static_cast<const T *>(args.I), static_cast<const T *>(args.A), args.W, args.H,
+                  w, h, R, in);
+    tile_level<T, false>(in, w, h, pv, R, lds.FA, lds.B, args.omega, args.eps,
                          static_cast<T *>(args.Fo), static_cast<T *>(args.Bo));
 }
 
@@ -652,13 +694,26 @@ __global__ __launch_bounds__(kTileThreads) void tile_kernel(TileArgs args) {
 // Regions of the run for output tile `tile` (levels 0..nl-1 of the run, last = output level).
 // The host (pyramid_fits) evaluates the same function to check that every region fits LDS.
 __host__ __device__ inline void pyramid_regions(const PyramidArgs &a, int tile, TileRegion *R) {
+    // Level sizes first, at fixed indices (on the device: every argument load in flight at once).
     const int L = a.nl;
-    const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
-    int cx0 = tx * kTileCore, cy0 = ty * kTileCore;
-    int cx1 = cx0 + kTileCore < a.lv[L - 1].w ? cx0 + kTileCore : a.lv[L - 1].w;
-    int cy1 = cy0 + kTileCore < a.lv[L - 1].h ? cy0 + kTileCore : a.lv[L - 1].h;
-    for (int l = L - 1; l >= 0; --l) {
-        const int w = a.lv[l].w, h = a.lv[l].h;
+    int lw[kPyrMaxLevels], lh[kPyrMaxLevels];
+#pragma unroll
+    for (int l = 0; l < kPyrMaxLevels; ++l) {
+        lw[l] = a.lv[l].w;
+        lh[l] = a.lv[l].h;
+    }
+    int cx0 = 0, cx1 = 0, cy0 = 0, cy1 = 0;
+#pragma unroll
+    for (int l = kPyrMaxLevels - 1; l >= 0; --l) {
+        if (l >= L) continue;
+        const int w = lw[l], h = lh[l];
+        if (l == L - 1) {   // the output tile
+            const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
+            cx0 = tx * kTileCore;
+            cy0 = ty * kTileCore;
+            cx1 = cx0 + kTileCore < w ? cx0 + kTileCore : w;
+            cy1 = cy0 + kTileCore < h ? cy0 + kTileCore : h;
+        }
         TileRegion r;
         r.cx0 = cx0;
         r.cx1 = cx1;
@@ -669,12 +724,13 @@ __host__ __device__ inline void pyramid_regions(const PyramidArgs &a, int tile, 
         r.rw = (cx1 + kTileHalo < w ? cx1 + kTileHalo : w) - r.rx0;
         r.rh = (cy1 + kTileHalo < h ? cy1 + kTileHalo : h) - r.ry0;
         R[l] = r;
-        if (l == 0) break;
-        const int wp = a.lv[l - 1].w, hp = a.lv[l - 1].h;
-        cx0 = r.rx0 * wp / w;
-        cx1 = (r.rx0 + r.rw - 1) * wp / w + 1;
-        cy0 = r.ry0 * hp / h;
-        cy1 = (r.ry0 + r.rh - 1) * hp / h + 1;
+        if (l > 0) {   // the part of the level below that the nearest map reads over r
+            const int wp = lw[l - 1], hp = lh[l - 1];
+            cx0 = r.rx0 * wp / w;
+            cx1 = (r.rx0 + r.rw - 1) * wp / w + 1;
+            cy0 = r.ry0 * hp / h;
+            cy1 = (r.ry0 + r.rh - 1) * hp / h + 1;
+        }
     }
 }
 
@@ -685,9 +741,19 @@ __global__ __launch_bounds__(kTileThreads) void pyramid_kernel(PyramidArgs args)
     if (threadIdx.x == 0) pyramid_regions(args, blockIdx.x, sR);
     lds_sync();
     const int L = args.nl;
+    // Each level's inputs are fetched one level ahead: their gathers run during the sweeps of
+    // the level before (the workgroup barriers wait for LDS only).
+    TileInput cur, nxt;
+    tile_fetch<T>(static_cast<const T *>(args.lv[0].I), static_cast<const T *>(args.lv[0].A),
+                  args.lv[0].W, args.lv[0].H, args.lv[0].w, args.lv[0].h, sR[0], cur);
     for (int l = 0; l < L; ++l) {
         const PyramidLevel &d = args.lv[l];
         const TileRegion R = sR[l];
+        if (l + 1 < L) {
+            const PyramidLevel &e = args.lv[l + 1];
+            tile_fetch<T>(static_cast<const T *>(e.I), static_cast<const T *>(e.A), e.W, e.H, e.w,
+                          e.h, sR[l + 1], nxt);
+        }
         T *Fo = l == L - 1 ? static_cast<T *>(args.Fo) : nullptr;
         T *Bo = l == L - 1 ? static_cast<T *>(args.Bo) : nullptr;
         TilePrev pv{};
@@ -696,21 +762,21 @@ __global__ __launch_bounds__(kTileThreads) void pyramid_kernel(PyramidArgs args)
             pv.Bp = args.Bp;
             pv.wp = args.wp;
             pv.hp = args.hp;
-            tile_level<T, false>(static_cast<const T *>(d.I), static_cast<const T *>(d.A), d.W, d.H,
-                                 d.w, d.h, pv, R, buf[0].FA, buf[0].B, args.omega, args.eps, Fo, Bo);
+            tile_level<T, false>(cur, d.w, d.h, pv, R, buf[0].FA, buf[0].B, args.omega, args.eps,
+                                 Fo, Bo);
         } else {
             const TileRegion P = sR[l - 1];
             pv.sFA = buf[(l - 1) & 1].FA;
             pv.sB = buf[(l - 1) & 1].B;
             pv.rx0 = P.rx0;
             pv.ry0 = P.ry0;
-            pv.rw = P.rw;
+            pv.pw = (P.rw + 1) >> 1;
             pv.wp = args.lv[l - 1].w;
             pv.hp = args.lv[l - 1].h;
-            tile_level<T, true>(static_cast<const T *>(d.I), static_cast<const T *>(d.A), d.W, d.H,
-                                d.w, d.h, pv, R, buf[l & 1].FA, buf[l & 1].B, args.omega, args.eps,
-                                Fo, Bo);
+            tile_level<T, true>(cur, d.w, d.h, pv, R, buf[l & 1].FA, buf[l & 1].B, args.omega,
+                                args.eps, Fo, Bo);
         }
+        cur = nxt;
     }
 }
 

@@ -39,6 +39,36 @@ SIZES = [(1, 1), (3, 2), (37, 64), (64, 37), (129, 300), (300, 129), (257, 255),
          (1000, 77), (16, 900), (520, 520), (128, 128)]
 
 
+# Single images whose run of tile levels is one pyramid launch: runs of 2 to 5 levels, regions
+# near the 40x40 limit (level ratios well below 2 on one axis), and a run that ends at the
+# finest level (images too small to stage their inputs in F).
+PYRAMID_SIZES = [(65, 65), (300, 7000), (7000, 300), (517, 1029), (1001, 257), (640, 480),
+                 (1920, 1080), (3001, 2999)]
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_pyramid_bit_identical_to_per_level_tiles(gpu, storage):
+    """The single-image path runs its tile levels as one pyramid launch (lower levels recomputed
+    in LDS per output tile); a batch of one image runs the same levels one launch each.  The
+    stored results must be the same bits, and match the oracle."""
+    torch, fge = gpu
+    p = fge.default_params(storage=fge.F16 if storage == "f16" else fge.F32)
+    for k, (w, h) in enumerate(PYRAMID_SIZES):
+        s = synth.smooth(w, h, seed=950 + k)
+        Is, As = inputs(torch, fge, [s], p)
+        F1, B1 = single(torch, fge, Is[0], As[0], p)
+        b = fge.Batch([(w, h)], p)
+        Fs, Bs = b.run(Is, As)
+        torch.cuda.synchronize()
+        assert torch.equal(Fs[0], F1) and torch.equal(Bs[0], B1), (w, h)
+        b.close()
+        if w * h <= 1 << 20:
+            Fo, Bo = oracle.ml(s.I, s.alpha, parallel=True)
+            err = max(float(np.abs(F1.cpu().numpy().astype(np.float64) - Fo).max()),
+                      float(np.abs(B1.cpu().numpy().astype(np.float64) - Bo).max()))
+            assert err <= TOL[storage], (w, h, err)
+
+
 @pytest.mark.parametrize("storage", ["f32", "f16"])
 def test_batch_bit_identical_to_single(gpu, storage):
     torch, fge = gpu
