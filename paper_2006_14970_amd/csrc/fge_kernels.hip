@@ -979,19 +979,24 @@ struct RowMap {
     }
 };
 
-// Gather one row into slot R: I and alpha from input row qi (nearest), F and B from
-// previous-level row qp.
+// Access paths of a streaming strip (template parameter PAIR):
+//   kPairNone  every pixel loads and stores on its own (strips at an image border, odd widths);
+//   kPairIn    the input map is the identity in x and the width even: a lane's two columns are
+//              adjacent in I and alpha (one load per plane) and in F and B (one store per
+//              plane); the previous level is read per pixel;
+//   kPairFull  as kPairIn, and the previous level is exactly half as wide: both columns read
+//              the same previous-level column (one load per plane).
+constexpr int kPairNone = 0, kPairIn = 1, kPairFull = 2;
+
 // Gather one row into slot R: I and alpha from input row qi (nearest), F and B from
 // previous-level row qp.  float32 lands in the float window directly; binary16 lands as raw
 // bits and is converted when the row is consumed.
-template <int R, bool PAIR, typename T>
+template <int R, int PAIR, typename T>
 __device__ __forceinline__ void fine_load_row(FineWin &v, const FineGeo &g, int qi, int qp) {
     const uint32_t si = static_cast<uint32_t>(qi) * static_cast<uint32_t>(g.W) * sizeof(T);
     const uint32_t sp = static_cast<uint32_t>(qp) * static_cast<uint32_t>(g.wp) * sizeof(T);
     if constexpr (sizeof(T) == 4) {
-        if constexpr (PAIR) {
-            // The lane's two columns are adjacent in the input (identity map) and share one
-            // source column of the previous level (exact 2:1): one load per plane.
+        if constexpr (PAIR >= kPairIn) {
             const f32x2 av = loadf2(g.A, g.sia, si);
             v.al[R][0] = av.x;
             v.al[R][1] = av.y;
@@ -1000,18 +1005,28 @@ __device__ __forceinline__ void fine_load_row(FineWin &v, const FineGeo &g, int 
                 const f32x2 iv = loadf2(g.I, g.sia, si + c * g.pI);
                 v.iv[R][0][c] = iv.x;
                 v.iv[R][1][c] = iv.y;
-                const uint32_t cp = sp + c * g.pP;
-                v.fv[R][0][c] = v.fv[R][1][c] = loadf(g.P, g.spa, cp);
-                v.bv[R][0][c] = v.bv[R][1][c] = loadf(g.P, g.spa, cp + 3 * g.pP);
             }
         } else {
             v.al[R][0] = loadf(g.A, g.sia, si);
             v.al[R][1] = loadf(g.A, g.sib, si);
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                const uint32_t ci = si + c * g.pI, cp = sp + c * g.pP;
+                const uint32_t ci = si + c * g.pI;
                 v.iv[R][0][c] = loadf(g.I, g.sia, ci);
                 v.iv[R][1][c] = loadf(g.I, g.sib, ci);
+            }
+        }
+        if constexpr (PAIR == kPairFull) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const uint32_t cp = sp + c * g.pP;
+                v.fv[R][0][c] = v.fv[R][1][c] = loadf(g.P, g.spa, cp);
+                v.bv[R][0][c] = v.bv[R][1][c] = loadf(g.P, g.spa, cp + 3 * g.pP);
+            }
+        } else {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const uint32_t cp = sp + c * g.pP;
                 v.fv[R][0][c] = loadf(g.P, g.spa, cp);
                 v.fv[R][1][c] = loadf(g.P, g.spb, cp);
                 v.bv[R][0][c] = loadf(g.P, g.spa, cp + 3 * g.pP);
@@ -1019,7 +1034,7 @@ __device__ __forceinline__ void fine_load_row(FineWin &v, const FineGeo &g, int 
             }
         }
     } else {
-        if constexpr (PAIR) {
+        if constexpr (PAIR >= kPairIn) {
             const uint32_t av = bload<float>(g.A, g.sia, si);
             v.ra[R][0] = av;
             v.ra[R][1] = av >> 16;
@@ -1028,18 +1043,28 @@ __device__ __forceinline__ void fine_load_row(FineWin &v, const FineGeo &g, int 
                 const uint32_t iv = bload<float>(g.I, g.sia, si + c * g.pI);
                 v.ri[R][0][c] = iv;
                 v.ri[R][1][c] = iv >> 16;
-                const uint32_t cp = sp + c * g.pP;
-                v.rf[R][0][c] = v.rf[R][1][c] = bload<T>(g.P, g.spa, cp);
-                v.rb[R][0][c] = v.rb[R][1][c] = bload<T>(g.P, g.spa, cp + 3 * g.pP);
             }
         } else {
             v.ra[R][0] = bload<T>(g.A, g.sia, si);
             v.ra[R][1] = bload<T>(g.A, g.sib, si);
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                const uint32_t ci = si + c * g.pI, cp = sp + c * g.pP;
+                const uint32_t ci = si + c * g.pI;
                 v.ri[R][0][c] = bload<T>(g.I, g.sia, ci);
                 v.ri[R][1][c] = bload<T>(g.I, g.sib, ci);
+            }
+        }
+        if constexpr (PAIR == kPairFull) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const uint32_t cp = sp + c * g.pP;
+                v.rf[R][0][c] = v.rf[R][1][c] = bload<T>(g.P, g.spa, cp);
+                v.rb[R][0][c] = v.rb[R][1][c] = bload<T>(g.P, g.spa, cp + 3 * g.pP);
+            }
+        } else {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const uint32_t cp = sp + c * g.pP;
                 v.rf[R][0][c] = bload<T>(g.P, g.spa, cp);
                 v.rf[R][1][c] = bload<T>(g.P, g.spb, cp);
                 v.rb[R][0][c] = bload<T>(g.P, g.spa, cp + 3 * g.pP);
@@ -1179,10 +1204,10 @@ __device__ __forceinline__ void bstore_pair(__amdgpu_buffer_rsrc_t r, uint32_t v
     }
 }
 
-template <int R, bool PAIR, typename T>
+template <int R, int PAIR, typename T>
 __device__ __forceinline__ void fine_store_row(const FineWin &v, const FineGeo &g, int r) {
     const uint32_t so = static_cast<uint32_t>(r) * static_cast<uint32_t>(g.w) * sizeof(T);
-    if constexpr (PAIR) {
+    if constexpr (PAIR >= kPairIn) {
         if (g.store_a) {   // == store_b: core boundaries are even in a paired strip
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
@@ -1211,7 +1236,7 @@ __device__ __forceinline__ void fine_store_row(const FineWin &v, const FineGeo &
 // One pipeline step at row t (TT = (t - t0) mod kWin): load row t + kPD (clamped into the image)
 // into its slot, take row t, compute the weights of row t-1, run half-sweep k on row t-1-k for
 // k = 0..3, and store row t-4, which has now seen both sweeps.
-template <int TT, bool EDGE, bool BORDER, bool PAIR, typename T>
+template <int TT, bool EDGE, bool BORDER, int PAIR, typename T>
 __device__ __forceinline__ void fine_step(FineWin &v, const FineGeo &g, RowMap &mi, RowMap &mp,
                                           int t) {
     constexpr int S = (TT + 1) & 1;       // column of the pair updated in this step
@@ -1234,7 +1259,7 @@ __device__ __forceinline__ void fine_step(FineWin &v, const FineGeo &g, RowMap &
     __builtin_amdgcn_sched_barrier(0);
 }
 
-template <bool EDGE, bool BORDER, bool PAIR, typename T>
+template <bool EDGE, bool BORDER, int PAIR, typename T>
 __device__ __forceinline__ void fine_block(FineWin &v, const FineGeo &g, RowMap &mi, RowMap &mp,
                                            int t) {
     fine_step<0, EDGE, BORDER, PAIR, T>(v, g, mi, mp, t);
@@ -1247,7 +1272,7 @@ __device__ __forceinline__ void fine_block(FineWin &v, const FineGeo &g, RowMap 
     fine_step<7, EDGE, BORDER, PAIR, T>(v, g, mi, mp, t + 7);
 }
 
-template <typename T, bool EDGE, bool PAIR>
+template <typename T, bool EDGE, int PAIR>
 __device__ __forceinline__ void fine_strip(const FineArgs &args, int sx, int sy, int lane) {
     FineGeo g;
     const size_t planeI = static_cast<size_t>(args.W) * args.H * sizeof(T);
@@ -1359,16 +1384,19 @@ __device__ __forceinline__ void fine_strip(const FineArgs &args, int sx, int sy,
 template <typename T>
 __device__ __forceinline__ void fine_body(const FineArgs &args, int wave, int lane) {
     const int sx = wave % args.nx, sy = wave / args.nx;
-    // Paired access: identity input map and an exact 2:1 previous level, even width (interior
-    // strips then start on even columns and their core boundaries are even).
-    const bool pair = args.w == args.W && args.h == args.H && 2 * args.wp == args.w &&
-                      (args.w & 1) == 0;
+    // Paired access needs an even width (interior strips then start on even columns and their
+    // core boundaries are even) and the identity input map in x; sharing the previous level's
+    // column needs it exactly half as wide.
+    const bool pair_in = args.w == args.W && (args.w & 1) == 0;
+    const bool pair_full = pair_in && 2 * args.wp == args.w;
     if (args.w <= kStripCols || sx == 0 || sx == args.nx - 1)
-        fine_strip<T, true, false>(args, sx, sy, lane);
-    else if (pair)
-        fine_strip<T, false, true>(args, sx, sy, lane);
+        fine_strip<T, true, kPairNone>(args, sx, sy, lane);
+    else if (pair_full)
+        fine_strip<T, false, kPairFull>(args, sx, sy, lane);
+    else if (pair_in)
+        fine_strip<T, false, kPairIn>(args, sx, sy, lane);
     else
-        fine_strip<T, false, false>(args, sx, sy, lane);
+        fine_strip<T, false, kPairNone>(args, sx, sy, lane);
 }
 
 // Workgroups are dispatched round-robin over the 8 XCDs (workgroup b on XCD b % 8), each with its

@@ -228,3 +228,17 @@ def test_runtime_errors(gpu):
     assert e.value.status == fge.FGE_EWORKSPACE
     with pytest.raises(ValueError):
         fge.estimate_foreground(I.half(), a.half(), p)
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_paired_input_path(gpu, storage):
+    """Streaming levels with an even width and the identity input map whose previous level is not
+    exactly half as wide (1000 -> 501, 1920 -> 966, 1366 -> 709, 2000 -> 1002): paired loads of
+    I and alpha and paired stores, per-pixel reads of the previous level."""
+    torch, fge = gpu
+    for k, (W, H) in enumerate(((1000, 600), (1920, 1080), (1366, 768), (2000, 300))):
+        s = synth.strands(W, H, seed=1200 + k, n_strands=W * H // 4000)
+        Fo, Bo = oracle.ml(s.I, s.alpha, parallel=True)
+        F, B = run(gpu, s.I, s.alpha, storage=fge.F16 if storage == "f16" else fge.F32)
+        err = max(maxabs(F, Fo), maxabs(B, Bo))
+        assert err <= TOL[storage], (W, H, err)
