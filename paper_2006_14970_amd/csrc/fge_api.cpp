@@ -123,7 +123,7 @@ size_t fge_workspace_bytes(int32_t W, int32_t H, const fge_params *p) {
     fge_params tmp;
     fge::Plan plan;
     const fge_params &prm = resolve(p, tmp);
-    if (fge::make_plan(W, H, prm, &plan, true) != FGE_OK) return 0;
+    if (fge::make_plan(W, H, prm, &plan, fge::kPlanSingle) != FGE_OK) return 0;
     if (prm.order == FGE_JACOBI) return fge::converge_workspace_bytes(W, H, prm);
     return plan.ws_bytes;
 }
@@ -134,7 +134,7 @@ fge_status fge_estimate_foreground(const void *I, const void *alpha, int32_t W, 
     fge_params tmp;
     const fge_params &prm = resolve(p, tmp);
     fge::Plan plan;
-    const fge_status st = fge::make_plan(W, H, prm, &plan, true);
+    const fge_status st = fge::make_plan(W, H, prm, &plan, fge::kPlanSingle);
     if (st != FGE_OK) return st;
     if (!I || !alpha || !F || !B || F == B) return FGE_EINVAL;
     if (prm.order == FGE_JACOBI)   // fixed counts on the per-level Jacobi kernels

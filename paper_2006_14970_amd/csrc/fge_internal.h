@@ -59,9 +59,12 @@ struct Plan {
 int num_levels(int W, int H);
 int level_size(int full, int level, int n);
 bool params_valid(const fge_params &p);
-// single_image: the plan drives fge_estimate_foreground, whose coarse launch can carry the
-// gather (batched and served plans keep the separate pre-pass).
-fge_status make_plan(int W, int H, const fge_params &p, Plan *out, bool single_image = false);
+// How the plan will be run.  kPlanSingle (fge_estimate_foreground): the coarse launch carries the
+// gather of every intermediate level, with the copies in F, and a run of tile levels may be one
+// pyramid launch.  kPlanBatched (batched and served images, whose coarse blocks run one
+// workgroup per image): a gather pre-pass copies the small levels into the workspace.
+enum PlanUse { kPlanBatched = 0, kPlanSingle = 1 };
+fge_status make_plan(int W, int H, const fge_params &p, Plan *out, PlanUse use = kPlanBatched);
 
 // Kernel launchers (fge_kernels.hip).  All enqueue on `stream` and return a HIP error code.
 struct LevelIO {

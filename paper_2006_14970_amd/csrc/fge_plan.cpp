@@ -40,7 +40,7 @@ bool params_valid(const fge_params &p) {
 
 static size_t align256(size_t v) { return (v + 255) & ~static_cast<size_t>(255); }
 
-fge_status make_plan(int W, int H, const fge_params &p, Plan *out, bool single_image) {
+fge_status make_plan(int W, int H, const fge_params &p, Plan *out, PlanUse use) {
     if (W < 1 || H < 1 || W > kMaxSide || H > kMaxSide) return FGE_EINVAL;
     if (!params_valid(p)) return FGE_EINVAL;
     Plan pl;
@@ -111,7 +111,7 @@ fge_status make_plan(int W, int H, const fge_params &p, Plan *out, bool single_i
         size_t staged = 0;   // bytes of the staged copies, which must fit in F (3 W H elements)
         for (int i = pl.nc; i < pl.n - 1; ++i)
             staged += align256(4 * static_cast<size_t>(pl.lv[i].w) * pl.lv[i].h * pl.elem);
-        if (single_image && pl.nc > 0 && pl.n - 1 > pl.nc && p.kernel != FGE_KERNEL_NAIVE &&
+        if (use == kPlanSingle && pl.nc > 0 && pl.n - 1 > pl.nc && p.kernel != FGE_KERNEL_NAIVE &&
             staged <= 3 * static_cast<size_t>(W) * H * pl.elem) {
             pl.gather_in_coarse = true;
             for (int i = pl.nc; i < pl.n - 1; ++i) pl.copy[i] = true;
@@ -129,7 +129,7 @@ fge_status make_plan(int W, int H, const fge_params &p, Plan *out, bool single_i
     // staged copies live in F: the finest level's stores would overwrite copies that other
     // workgroups of the same launch still read.
     pl.pyr_first = pl.pyr_last = -1;
-    if (single_image && p.kernel != FGE_KERNEL_NAIVE) {
+    if (use == kPlanSingle && p.kernel != FGE_KERNEL_NAIVE) {
         int a = pl.nc;
         while (a < pl.n && pl.kind[a] != kKindTile) ++a;
         int b = a;

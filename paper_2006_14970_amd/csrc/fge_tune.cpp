@@ -107,7 +107,7 @@ size_t fge_tune_workspace_bytes(int32_t W, int32_t H, const fge_params *p) {
     size_t need = 0;
     for (const Candidate &c : candidates(base)) {
         fge::Plan pl;
-        if (fge::make_plan(W, H, c.p, &pl, true) != FGE_OK) return 0;
+        if (fge::make_plan(W, H, c.p, &pl, fge::kPlanSingle) != FGE_OK) return 0;
         if (pl.ws_bytes > need) need = pl.ws_bytes;
     }
     return need;
