@@ -1381,22 +1381,35 @@ __device__ __forceinline__ void fine_strip(const FineArgs &args, int sx, int sy,
     for (; t <= g.tlast; t += kWin) fine_block<EDGE, true, PAIR, T>(v, g, mi, mp, t);
 }
 
-template <typename T>
+// EDGE_PAIR: whether border strips may take the paired paths too (the single-image kernel; the
+// persistent batch kernel, which holds more state, spills with the extra variants).
+template <typename T, bool EDGE_PAIR>
 __device__ __forceinline__ void fine_body(const FineArgs &args, int wave, int lane) {
     const int sx = wave % args.nx, sy = wave / args.nx;
     // Paired access needs an even width (interior strips then start on even columns and their
     // core boundaries are even) and the identity input map in x; sharing the previous level's
     // column needs it exactly half as wide.
-    const bool pair_in = args.w == args.W && (args.w & 1) == 0;
+    // The two border strips of a level wider than one strip qualify as well: the first starts at
+    // column 0 and the last ends at column w - 1, so with an even width their lanes' pairs lie
+    // inside the row and their core boundaries are even; the border clamp is a per-lane select
+    // either way.  A level of one strip (w <= 128) has lanes past the last column and stays
+    // unpaired.
+    const bool pair_in = args.w == args.W && (args.w & 1) == 0 && args.w > kStripCols;
     const bool pair_full = pair_in && 2 * args.wp == args.w;
-    if (args.w <= kStripCols || sx == 0 || sx == args.nx - 1)
-        fine_strip<T, true, kPairNone>(args, sx, sy, lane);
-    else if (pair_full)
+    if (args.w <= kStripCols || sx == 0 || sx == args.nx - 1) {
+        if (EDGE_PAIR && pair_full)
+            fine_strip<T, true, EDGE_PAIR ? kPairFull : kPairNone>(args, sx, sy, lane);
+        else if (EDGE_PAIR && pair_in)
+            fine_strip<T, true, EDGE_PAIR ? kPairIn : kPairNone>(args, sx, sy, lane);
+        else
+            fine_strip<T, true, kPairNone>(args, sx, sy, lane);
+    } else if (pair_full) {
         fine_strip<T, false, kPairFull>(args, sx, sy, lane);
-    else if (pair_in)
+    } else if (pair_in) {
         fine_strip<T, false, kPairIn>(args, sx, sy, lane);
-    else
+    } else {
         fine_strip<T, false, kPairNone>(args, sx, sy, lane);
+    }
 }
 
 // Workgroups are dispatched round-robin over the 8 XCDs (workgroup b on XCD b % 8), each with its
@@ -1414,7 +1427,7 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, 2) void fine_kernel(FineArgs a
     const int pos = (blockIdx.x % kXcds) * fine_block_chunk(units) + blockIdx.x / kXcds;
     const int wave = uniform(pos * kWavesPerBlock + (threadIdx.x >> 6));
     if (wave >= units) return;
-    fine_body<T>(args, wave, threadIdx.x & 63);
+    fine_body<T, true>(args, wave, threadIdx.x & 63);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -1450,7 +1463,7 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, 2) void fine_batch_kernel(
         const int it = next_item_wave(counter, lane);
         if (it >= nitems) return;
         const WorkItem w = items[it];
-        fine_body<T>(descs[uniform(w.desc)], uniform(w.unit), lane);
+        fine_body<T, false>(descs[uniform(w.desc)], uniform(w.unit), lane);
     }
 }
 
