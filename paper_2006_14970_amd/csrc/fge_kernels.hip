@@ -1,20 +1,30 @@
 // HIP kernels (gfx950) for multi-level foreground estimation, arXiv 2006.14970, Algorithm 1.
 //
-// Three kernel families, all computing in float32 and storing in T (float or _Float16):
+// Kernel families, all computing in float32 and storing in T (float or _Float16):
 //
-//  coarse_kernel   One workgroup runs every level whose w*h <= 4096 entirely in LDS (alpha, F
-//                  and B planes, 112 KB), including the 10-sweep low-resolution levels, then
-//                  writes the last of those levels to memory.  Removes ~100 dependent launches.
+//  coarse_kernel   One workgroup runs the low-resolution levels (by default those of at most
+//                  1024 px, plus every level whose sweep count is not 2) entirely in LDS,
+//                  including their 10 sweeps, then writes the last of them to memory.
+//                  coarse_gather_kernel runs it in workgroup 0 while the rest of the launch copies
+//                  the compact inputs of the later levels (single image).
 //
-//  fine_kernel     One launch per fine level.  Each wave owns a strip of 128 columns (a pair of
-//                  adjacent pixels per lane, so every lane has exactly one pixel of each colour)
-//                  and streams down its rows: for every new row it gathers I and alpha from the
-//                  full-resolution input (nearest), upsamples F and B from the previous level,
-//                  and runs all four red-black half-sweeps of the level's two sweeps on a
-//                  six-row register window (temporal blocking).  Horizontal neighbours cross
-//                  lanes with DPP; nothing goes through LDS.  A half-sweep invalidates one ring
-//                  at the strip edge, so strips overlap by 4 rows/columns of halo that are
-//                  computed but not stored.  One HBM round trip per level.
+//  tile_kernel     One level, one workgroup per 32x32 output tile plus a 4-pixel ring in LDS.
+//                  pyramid_kernel runs a run of consecutive tile levels in one launch, each
+//                  workgroup computing exactly the lower-level regions its output tile needs.
+//
+//  fine_kernel     One launch per large fine level.  Each wave owns a strip of 128 columns (a
+//                  pair of adjacent pixels per lane, so every lane has exactly one pixel of each
+//                  colour) and streams down its rows: for every new row it gathers I and alpha
+//                  (nearest), upsamples F and B from the previous level, and runs all four
+//                  red-black half-sweeps of the level's two sweeps on an eight-row register
+//                  window (temporal blocking).  Horizontal neighbours cross lanes with DPP;
+//                  nothing goes through LDS.  A half-sweep invalidates one ring at the strip
+//                  edge, so strips overlap by 4 rows/columns of halo that are computed but not
+//                  stored.  One HBM round trip per level.
+//
+//  batch kernels   Persistent versions of the tile and streaming kernels pulling (level, tile or
+//                  strip) items from a work counter, one coarse workgroup per image, a batched
+//                  gather.
 //
 //  naive kernels   Debug path: one launch per upsample and per half-sweep, in place.
 //
