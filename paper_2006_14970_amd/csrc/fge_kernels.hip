@@ -1548,7 +1548,7 @@ __global__ __launch_bounds__(256) void gather_kernel(GatherArgs args) {
 // coarse levels (their inputs come from full resolution); the others copy the compact inputs of
 // the later levels, grid-stride, kGatherUnroll pixels per thread in flight at once.  The levels
 // that read those copies run in later launches.
-constexpr int kGatherUnroll = 8;
+constexpr int kGatherUnroll = 16;
 constexpr int kGatherBlocksMax = 255;   // every CU but the coarse block's
 
 template <typename T>
