@@ -991,9 +991,9 @@ struct RowMap {
 
 // Access paths of a streaming strip (template parameter PAIR):
 //   kPairNone  every pixel loads and stores on its own (strips at an image border, odd widths);
-//   kPairIn    the input map is the identity in x and the width even: a lane's two columns are
-//              adjacent in I and alpha (one load per plane) and in F and B (one store per
-//              plane); the previous level is read per pixel;
+//   kPairIn    the input map is the identity in x and the strip starts on an even column: a
+//              lane's two columns are adjacent in I and alpha (one load per plane) and in F and
+//              B (one store per plane); the previous level is read per pixel;
 //   kPairFull  as kPairIn, and the previous level is exactly half as wide: both columns read
 //              the same previous-level column (one load per plane).
 constexpr int kPairNone = 0, kPairIn = 1, kPairFull = 2;
@@ -1207,10 +1207,14 @@ __device__ __forceinline__ void bstore_pair(__amdgpu_buffer_rsrc_t r, uint32_t v
         const u32x2 d = {__float_as_uint(v0), __float_as_uint(v1)};
         __builtin_amdgcn_raw_buffer_store_b64(d, r, static_cast<int>(voff), static_cast<int>(soff), 2);
     } else {
-        const _Float16 h0 = static_cast<_Float16>(v0), h1 = static_cast<_Float16>(v1);
-        const uint32_t d = static_cast<uint32_t>(__builtin_bit_cast(unsigned short, h0)) |
-                           (static_cast<uint32_t>(__builtin_bit_cast(unsigned short, h1)) << 16);
-        __builtin_amdgcn_raw_buffer_store_b32(d, r, static_cast<int>(voff), static_cast<int>(soff), 2);
+        // One vector conversion: gfx950 converts and packs the pair in a single instruction,
+        // rounding each value to nearest even as a scalar conversion does.
+        typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+        asm volatile("" : "+v"(v0), "+v"(v1));   // as above: keeps the window in registers
+        const f32x2 fv = {v0, v1};
+        const f16x2 hv = __builtin_convertvector(fv, f16x2);
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, hv), r,
+                                              static_cast<int>(voff), static_cast<int>(soff), 2);
     }
 }
 
@@ -1396,20 +1400,22 @@ __device__ __forceinline__ void fine_strip(const FineArgs &args, int sx, int sy,
 template <typename T, bool EDGE_PAIR>
 __device__ __forceinline__ void fine_body(const FineArgs &args, int wave, int lane) {
     const int sx = wave % args.nx, sy = wave / args.nx;
-    // Paired access needs an even width (interior strips then start on even columns and their
-    // core boundaries are even) and the identity input map in x; sharing the previous level's
-    // column needs it exactly half as wide.
-    // The two border strips of a level wider than one strip qualify as well: the first starts at
-    // column 0 and the last ends at column w - 1, so with an even width their lanes' pairs lie
-    // inside the row and their core boundaries are even; the border clamp is a per-lane select
-    // either way.  A level of one strip (w <= 128) has lanes past the last column and stays
-    // unpaired.
-    const bool pair_in = args.w == args.W && (args.w & 1) == 0 && args.w > kStripCols;
+    // Paired access needs the identity input map in x; sharing the previous level's column needs
+    // the previous level exactly half as wide.  Interior strips start on even columns and keep
+    // even core boundaries at any width, so a lane's two columns are both stored or both not;
+    // in an odd-width level the pair of an odd row starts at an odd element, an access aligned
+    // to its element size only, which the vector-memory path performs as an unaligned access.
+    // Of the two border strips of a level wider than one strip, the first starts at column 0
+    // and qualifies at any width; the last ends at column w - 1, so it starts on an even column
+    // only when w is even.  The border clamp is a per-lane select either way.  A level of one
+    // strip (w <= 128) has lanes past the last column and stays unpaired.
+    const bool pair_in = args.w == args.W && args.w > kStripCols;
     const bool pair_full = pair_in && 2 * args.wp == args.w;
     if (args.w <= kStripCols || sx == 0 || sx == args.nx - 1) {
-        if (EDGE_PAIR && pair_full)
+        const bool edge_ok = EDGE_PAIR && (sx == 0 || (args.w & 1) == 0);
+        if (edge_ok && pair_full)
             fine_strip<T, true, EDGE_PAIR ? kPairFull : kPairNone>(args, sx, sy, lane);
-        else if (EDGE_PAIR && pair_in)
+        else if (edge_ok && pair_in)
             fine_strip<T, true, EDGE_PAIR ? kPairIn : kPairNone>(args, sx, sy, lane);
         else
             fine_strip<T, true, kPairNone>(args, sx, sy, lane);

@@ -242,3 +242,19 @@ def test_paired_input_path(gpu, storage):
         F, B = run(gpu, s.I, s.alpha, storage=fge.F16 if storage == "f16" else fge.F32)
         err = max(maxabs(F, Fo), maxabs(B, Bo))
         assert err <= TOL[storage], (W, H, err)
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_paired_input_path_odd_width(gpu, storage):
+    """Odd widths on the paired paths: interior strips and the first strip pair their columns
+    (the pair of an odd row then starts on an odd element), the last strip, which starts on an
+    odd column, stays unpaired.  Widths with several interior strips, one interior strip and
+    none (247 = two border strips only), heights odd and even; every finest level is above the
+    tile kernel's 256K-pixel limit, so it streams."""
+    torch, fge = gpu
+    for k, (W, H) in enumerate(((1001, 600), (1921, 1081), (4001, 150), (247, 1201), (301, 1001))):
+        s = synth.strands(W, H, seed=1300 + k, n_strands=max(1, W * H // 4000))
+        Fo, Bo = oracle.ml(s.I, s.alpha, parallel=True)
+        F, B = run(gpu, s.I, s.alpha, storage=fge.F16 if storage == "f16" else fge.F32)
+        err = max(maxabs(F, Fo), maxabs(B, Bo))
+        assert err <= TOL[storage], (W, H, err)
