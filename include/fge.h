@@ -279,7 +279,7 @@ fge_status fge_planar_to_hwc(const void *planes, int32_t src_dtype, int32_t W, i
  * settings that change how the work is cut, never what is computed: strip_rows (the streaming
  * kernel's strip height, i.e. how many output rows share the halo of the two fused sweeps; 0 is
  * the automatic choice) over {0, 16, 24, 32, 48, 64, 96}, and tile_max_px (the largest level on
- * the LDS tile kernel) over {0 (2^18), 2^16, 2^20}: fge_tune_candidates() settings.  Each runs
+ * the LDS tile kernel) over {2^16, 2^18, 2^20}: fge_tune_candidates() settings.  Each runs
  * once untimed, then `reps` times (0 = 3) between two events on `stream`; the call blocks until
  * the search is done.  F and B hold the last candidate's result (all candidates agree to the
  * parity tolerance).  entries[k] (k < max_entries) receives each candidate's strip_rows,

@@ -1395,9 +1395,7 @@ __device__ __forceinline__ void fine_strip(const FineArgs &args, int sx, int sy,
     for (; t <= g.tlast; t += kWin) fine_block<EDGE, true, PAIR, T>(v, g, mi, mp, t);
 }
 
-// EDGE_PAIR: whether border strips may take the paired paths too (the single-image kernel; the
-// persistent batch kernel, which holds more state, spills with the extra variants).
-template <typename T, bool EDGE_PAIR>
+template <typename T>
 __device__ __forceinline__ void fine_body(const FineArgs &args, int wave, int lane) {
     const int sx = wave % args.nx, sy = wave / args.nx;
     // Paired access needs the identity input map in x; sharing the previous level's column needs
@@ -1412,11 +1410,11 @@ __device__ __forceinline__ void fine_body(const FineArgs &args, int wave, int la
     const bool pair_in = args.w == args.W && args.w > kStripCols;
     const bool pair_full = pair_in && 2 * args.wp == args.w;
     if (args.w <= kStripCols || sx == 0 || sx == args.nx - 1) {
-        const bool edge_ok = EDGE_PAIR && (sx == 0 || (args.w & 1) == 0);
+        const bool edge_ok = sx == 0 || (args.w & 1) == 0;
         if (edge_ok && pair_full)
-            fine_strip<T, true, EDGE_PAIR ? kPairFull : kPairNone>(args, sx, sy, lane);
+            fine_strip<T, true, kPairFull>(args, sx, sy, lane);
         else if (edge_ok && pair_in)
-            fine_strip<T, true, EDGE_PAIR ? kPairIn : kPairNone>(args, sx, sy, lane);
+            fine_strip<T, true, kPairIn>(args, sx, sy, lane);
         else
             fine_strip<T, true, kPairNone>(args, sx, sy, lane);
     } else if (pair_full) {
@@ -1443,7 +1441,7 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, 2) void fine_kernel(FineArgs a
     const int pos = (blockIdx.x % kXcds) * fine_block_chunk(units) + blockIdx.x / kXcds;
     const int wave = uniform(pos * kWavesPerBlock + (threadIdx.x >> 6));
     if (wave >= units) return;
-    fine_body<T, true>(args, wave, threadIdx.x & 63);
+    fine_body<T>(args, wave, threadIdx.x & 63);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -1464,6 +1462,23 @@ __global__ void zero_kernel(int *p, int n) {
     if (i < n) p[i] = 0;
 }
 
+// A descriptor that every lane of a wave loaded from the same address, with each 32-bit word
+// taken from the first active lane.  The compiler then knows every field is wave-uniform, so the
+// buffer resources built from the pointers live in scalar registers; a resource it must assume
+// may differ across lanes turns every buffer access into a loop over the lanes' distinct values.
+template <typename S>
+__device__ __forceinline__ S uniform_copy(const S &s) {
+    static_assert(sizeof(S) % 4 == 0, "descriptor of whole 32-bit words");
+    int words[sizeof(S) / 4];
+    __builtin_memcpy(words, &s, sizeof(S));
+#pragma unroll
+    for (int i = 0; i < static_cast<int>(sizeof(S) / 4); ++i)
+        words[i] = __builtin_amdgcn_readfirstlane(words[i]);
+    S r;
+    __builtin_memcpy(&r, words, sizeof(S));
+    return r;
+}
+
 // One item per wave.  The counter is bumped by lane 0 with a vector atomic and broadcast.
 __device__ __forceinline__ int next_item_wave(int *counter, int lane) {
     int v = 0;
@@ -1479,7 +1494,8 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, 2) void fine_batch_kernel(
         const int it = next_item_wave(counter, lane);
         if (it >= nitems) return;
         const WorkItem w = items[it];
-        fine_body<T, false>(descs[uniform(w.desc)], uniform(w.unit), lane);
+        const FineArgs a = uniform_copy(descs[uniform(w.desc)]);
+        fine_body<T>(a, uniform(w.unit), lane);
     }
 }
 
@@ -1667,8 +1683,10 @@ int fine_units(const FineArgs &a) { return a.nx * a.ny; }
 int launch_strip_rows(const int *w, const int *h, int n) {
     // A batched launch has the parallelism of all its levels together, so its strips can be
     // taller than one level alone would get (less halo work per output row): the tallest even
-    // height up to 64 rows that still gives every resident wave a strip.
-    for (int rows = 64; rows >= 8; rows -= 2) {
+    // height up to 32 rows that still gives every resident wave a strip.  Taller strips lose
+    // again (64 uneven images, float16, per batch: 1.58 ms at 24-32 rows, 1.62 ms at 48 and 64,
+    // 1.60 ms at 16).
+    for (int rows = 32; rows >= 8; rows -= 2) {
         long items = 0;
         for (int k = 0; k < n; ++k)
             items += static_cast<long>(fine_strips_x(w[k])) * ((h[k] + rows - 1) / rows);

@@ -18,7 +18,7 @@
 namespace {
 
 constexpr int kRows[] = {0, 16, 24, 32, 48, 64, 96};
-constexpr int kTileMax[] = {0, 1 << 16, 1 << 20};
+constexpr int kTileMax[] = {1 << 16, 1 << 18, 1 << 20};
 
 struct Candidate {
     fge_params p;

@@ -232,7 +232,7 @@ def test_autotuner_host_side(fge):
     for (W, H) in ((4096, 3072), (1024, 768), (300, 7)):
         need = lib.fge_tune_workspace_bytes(W, H, None)
         assert need >= fge.workspace_bytes(W, H)
-        for t in (0, 1 << 16, 1 << 20):
+        for t in (0, 1 << 16, 1 << 18, 1 << 20):
             assert need >= fge.workspace_bytes(W, H, fge.default_params(tile_max_px=t))
     sizes = [(300, 200), (1024, 768), (77, 900)]
     W = (ctypes.c_int32 * 3)(*[w for w, _ in sizes])
