@@ -283,7 +283,7 @@ def run_serving(torch, fge, synth, args, single_f32_mps, check_oracle):
     Inputs are generated into HBM before either pass; F and B land in preallocated HBM."""
     n = args.serve_requests
     reqs = synth.serving_requests(n=n, rate_per_s=1.0)   # unit-rate gaps, rescaled in pass 2
-    p = fge.default_params(storage=fge.F16)
+    p = fge.default_params(storage=fge.F16, tile_max_px=args.serve_tile_max)
     px = np.array([r.W * r.H for r in reqs], dtype=np.int64)
     mp = float(px.sum()) / 1e6
     in_off = np.concatenate([[0], np.cumsum(4 * px)])
@@ -372,7 +372,8 @@ def run_serving(torch, fge, synth, args, single_f32_mps, check_oracle):
     torch.cuda.empty_cache()
     return {"workload": f"{n} requests, area log-uniform on 0.25-16 MP, aspect uniform on "
                         "[0.5, 2] (seed 5), smooth generator on the device (seed 5000 + id), "
-                        "float16 storage, float32 arithmetic, 64 GB admission budget",
+                        "float16 storage, float32 arithmetic, 64 GB admission budget, "
+                        f"tile_max_px {args.serve_tile_max}",
             "requests": n, "megapixels": mp, "budget_bytes": budget, "unit": "MP/s",
             "saturated": sat, "poisson_rate_per_s": rate, "poisson": poi,
             "vs_single_image_f32": sat["value"] / single_f32_mps,
@@ -391,6 +392,9 @@ def main():
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the serving-stream (continuous batching, float16 storage) leg")
     ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-tile-max", type=int, default=1 << 16,
+                    help="tile_max_px of the serving leg's parameters (0 = automatic, 2^18); "
+                         "default 2^16, the limit the batch autotuner picks for batched launches")
     ap.add_argument("--no-converge", action="store_true",
                     help="skip the level-loop variants leg (convergence form, smooth resize)")
     ap.add_argument("--copy-calibration", action="store_true",
