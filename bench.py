@@ -85,7 +85,7 @@ def run_storage(torch, fge, sample, storage, steps, warmup, oracle_F=None, oracl
         a = torch.from_numpy(sample.alpha).to(dt).to(dev).contiguous()
         F = torch.empty((3, H_IMG, W_IMG), dtype=dt, device=dev)
         B = torch.empty_like(F)
-        ws = torch.empty(max(1, fge.workspace_bytes(W_IMG, H_IMG, p)), dtype=torch.uint8, device=dev)
+        ws = torch.empty(max(1, fge.workspace_bytes(H_IMG, W_IMG, p)), dtype=torch.uint8, device=dev)
         sets.append((I, a, F, B, ws))
     stream = torch.cuda.current_stream()
 
@@ -194,7 +194,7 @@ def run_variants(torch, fge, sample):
 
 def time_batch(torch, fge, sizes, p, Is, As, steps, warmup, stream):
     """One batch plan timed as plain runs (wall clock) and as hipGraph replays (events)."""
-    b = fge.Batch(sizes, p)
+    b = fge.Batch([(h, w) for w, h in sizes], p)
     ws = torch.empty(b.workspace_bytes, dtype=torch.uint8, device="cuda")
     Fs = [torch.empty((3, h, w), dtype=torch.float16, device="cuda") for w, h in sizes]
     Bs = [torch.empty((3, h, w), dtype=torch.float16, device="cuda") for w, h in sizes]
@@ -242,7 +242,7 @@ def run_batch(torch, fge, synth, args, single_f32_mps, check_oracle):
     stream = torch.cuda.Stream()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    best, entries = fge.autotune_batch(sizes, Is, As, p, reps=3, stream=stream)
+    best, entries = fge.autotune_batch([(h, w) for w, h in sizes], Is, As, p, reps=3, stream=stream)
     tune_s = time.perf_counter() - t0
     log(f"  autotuner: strip_rows {best.strip_rows}, tile_max_px {best.tile_max_px} "
         f"({len(entries)} candidates, {tune_s:.2f} s)")
@@ -319,7 +319,7 @@ def run_serving(torch, fge, synth, args, single_f32_mps, check_oracle):
             now = time.perf_counter() - start
             while k < n and arrivals[k] <= now:
                 I, a, F, B = ptrs[k]
-                srv.submit_ptrs(k, I, a, reqs[k].W, reqs[k].H, F, B)
+                srv.submit_ptrs(k, I, a, reqs[k].H, reqs[k].W, F, B)
                 late.append(time.perf_counter() - start - arrivals[k])
                 k += 1
         srv.drain()
@@ -447,7 +447,7 @@ def main():
                          "sweep), one thread, median of 3 runs of "
                          f"{med:.2f} s"}
 
-    plan = fge.plan(W_IMG, H_IMG)
+    plan = fge.plan(H_IMG, W_IMG)
     res = {}
     for name, storage in (("f32", fge.F32), ("f16", fge.F16)):
         log(f"GPU {name} storage: {args.warmup} warm-up + {args.steps} timed steps (x3 passes)")

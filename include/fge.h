@@ -17,12 +17,17 @@
  * input runs one level.
  *
  * Conventions for every entry point:
- *   - Images are planar, row-major, x fastest: I, F and B are 3 planes of W*H elements (plane c
- *     starts at element c*W*H); alpha is one plane of W*H elements.  Element type is float32 or
- *     IEEE binary16 according to fge_params.storage; values are expected in [0, 1] and are not
- *     checked.
+ *   - Sizes are passed height first, (H, W), the order of the array shapes below: an image of
+ *     H rows of W pixels.  Arrays of sizes (batches) are likewise an array of heights followed by
+ *     an array of widths.  The paper writes an input as w x h x 3 (Section III-D); the order of
+ *     the arguments here follows the row-major layout, not that notation.
+ *   - Images are planar, row-major, x fastest: I, F and B are 3 planes of H*W elements (3 x H x W;
+ *     plane c starts at element c*H*W); alpha is one plane of H*W elements (H x W).  Element type
+ *     is float32 or IEEE binary16 according to fge_params.storage; values are expected in [0, 1]
+ *     and are not checked.
  *   - All data pointers are DEVICE pointers owned by the caller; the library never frees or
- *     keeps them past the call.  F and B must not overlap I, alpha, each other or the workspace.
+ *     keeps them past the call.  F and B must not overlap I, alpha, each other or the workspace:
+ *     the estimation entry points compare the byte ranges and return FGE_EINVAL on any overlap.
  *   - `stream` is a hipStream_t (NULL = the default stream).  Work is enqueued asynchronously;
  *     the call returns once it is enqueued.  The caller synchronises before reading F, B.
  *   - Argument errors are reported synchronously (FGE_EINVAL / FGE_EWORKSPACE /
@@ -97,40 +102,41 @@ void fge_default_params(fge_params *p);
 /* Human-readable name of a status code (static string). */
 const char *fge_status_string(int status);
 
-/* Library ABI version (increments when fge_params or a signature changes); this header is 3. */
+/* Library ABI version (increments when fge_params or a signature changes); this header is 4
+ * (4 moved every size argument to height-first order). */
 int32_t fge_version(void);
 
 /* ---- host-only planning (no GPU needed) ---------------------------------------------- */
 
-/* Level count of Algorithm 1 for a W x H input: ceil(log2(max(W, H))), at least 1.
+/* Level count of Algorithm 1 for an H x W input: ceil(log2(max(W, H))), at least 1.
  * Returns 0 if W or H is outside [1, 32767]. */
-int32_t fge_num_levels(int32_t W, int32_t H);
+int32_t fge_num_levels(int32_t H, int32_t W);
 
 /* Size of level `level` (1-based) of `n_levels` along an axis of `full` pixels:
  * round(full^(level / n_levels)) (Algorithm 1).  Returns 0 on bad arguments. */
 int32_t fge_level_size(int32_t full, int32_t level, int32_t n_levels);
 
-/* The level schedule for a W x H input under *p: for l = 1..n, w_out[l-1], h_out[l-1] and
+/* The level schedule for an H x W input under *p: for l = 1..n, w_out[l-1], h_out[l-1] and
  * iters_out[l-1] (10 or 2 by the low-resolution rule), and *n_coarse_out, the number of leading
  * levels the LDS-resident coarse kernel runs.  Arrays hold at least max_levels entries (16 is
  * always enough).  FGE_EINVAL on bad sizes or parameters. */
-fge_status fge_plan(int32_t W, int32_t H, const fge_params *p, int32_t max_levels,
+fge_status fge_plan(int32_t H, int32_t W, const fge_params *p, int32_t max_levels,
                     int32_t *w_out, int32_t *h_out, int32_t *iters_out, int32_t *n_levels_out,
                     int32_t *n_coarse_out);
 
-/* Workspace bytes fge_estimate_foreground needs for a W x H input under *p (0 on bad
+/* Workspace bytes fge_estimate_foreground needs for an H x W input under *p (0 on bad
  * arguments; may be 0 for inputs whose pyramid fits the coarse kernel). */
-size_t fge_workspace_bytes(int32_t W, int32_t H, const fge_params *p);
+size_t fge_workspace_bytes(int32_t H, int32_t W, const fge_params *p);
 
 /* ---- estimation ------------------------------------------------------------------------ */
 
 /* Algorithm 1 for one image: reads I (3 x H x W) and alpha (H x W), writes F and B
  * (3 x H x W each), all in p->storage element type, on `stream`.  `workspace` must hold
- * fge_workspace_bytes(W, H, p) bytes (it may be NULL when that is 0).  p == NULL means the
+ * fge_workspace_bytes(H, W, p) bytes (it may be NULL when that is 0).  p == NULL means the
  * defaults.  Before the finest level writes them, the call may use F's memory for compact
  * copies of the lower levels' inputs, so F and B must not overlap I, alpha or the workspace
  * (as for any output). */
-fge_status fge_estimate_foreground(const void *I, const void *alpha, int32_t W, int32_t H,
+fge_status fge_estimate_foreground(const void *I, const void *alpha, int32_t H, int32_t W,
                                    const fge_params *p, void *F, void *B, void *workspace,
                                    size_t workspace_bytes, void *stream);
 
@@ -144,8 +150,8 @@ fge_status fge_estimate_foreground(const void *I, const void *alpha, int32_t W, 
  * (DEVICE int array of >= n_levels entries, or NULL) receives the sweeps each level ran (in the
  * tol >= 0 form).  Every level runs on per-level kernels (no coarse block, no fused levels), so
  * this is a quality mode, not the fast path.  Workspace: fge_converge_workspace_bytes. */
-size_t fge_converge_workspace_bytes(int32_t W, int32_t H, const fge_params *p);
-fge_status fge_estimate_foreground_converge(const void *I, const void *alpha, int32_t W, int32_t H,
+size_t fge_converge_workspace_bytes(int32_t H, int32_t W, const fge_params *p);
+fge_status fge_estimate_foreground_converge(const void *I, const void *alpha, int32_t H, int32_t W,
                                             const fge_params *p, double tol, int32_t max_sweeps,
                                             void *F, void *B, int32_t *sweeps_out, void *workspace,
                                             size_t workspace_bytes, void *stream);
@@ -167,17 +173,19 @@ typedef struct fge_level_options {
 /* The level loop on per-level kernels with these options (order from p->order): the general
  * form of fge_estimate_foreground_converge (which is resize NEAREST).  The smooth variant's level
  * inputs are float32 copies (area sums in float64).  Workspace: fge_levels_workspace_bytes. */
-size_t fge_levels_workspace_bytes(int32_t W, int32_t H, const fge_params *p,
+size_t fge_levels_workspace_bytes(int32_t H, int32_t W, const fge_params *p,
                                   const fge_level_options *o);
-fge_status fge_estimate_foreground_levels(const void *I, const void *alpha, int32_t W, int32_t H,
+fge_status fge_estimate_foreground_levels(const void *I, const void *alpha, int32_t H, int32_t W,
                                           const fge_params *p, const fge_level_options *o,
                                           void *F, void *B, int32_t *sweeps_out, void *workspace,
                                           size_t workspace_bytes, void *stream);
 
 /* ---- batches of images of different sizes ---------------------------------------------- */
 
-/* A batch plan: every image follows its own level plan (so its F and B are bit-identical to
- * fge_estimate_foreground's), and the levels of all images are aligned from the finest.  A run
+/* A batch plan: every image runs Algorithm 1 (Section III-D) on its own level plan -- the level
+ * sizes round(W^(l/n_l)) x round(H^(l/n_l)), 10 sweeps on low-resolution levels and 2 on the
+ * others, the per-pixel solve of eq. 9 -- so its F and B are bit-identical to
+ * fge_estimate_foreground's, and the levels of all images are aligned from the finest.  A run
  * is: one upload of descriptor tables into the workspace, a counter fill kernel, one batched
  * gather pre-pass, one batched coarse block (a workgroup per image), then per fine step one
  * persistent tile-kernel launch and one persistent streaming-kernel launch whose waves pull
@@ -185,12 +193,12 @@ fge_status fge_estimate_foreground_levels(const void *I, const void *alpha, int3
  * != -1) and fused fine levels (iters_big == 2, kernel != FGE_KERNEL_NAIVE). */
 typedef struct fge_batch fge_batch;
 
-/* Plan a batch of n images, image i of size W[i] x H[i], all under *p (NULL = defaults).
- * Host-only; *out receives the plan.  FGE_EINVAL / FGE_EUNSUPPORTED on bad input. */
-fge_status fge_batch_create(int32_t n, const int32_t *W, const int32_t *H, const fge_params *p,
+/* Plan a batch of n images, image i of H[i] rows of W[i] pixels, all under *p (NULL =
+ * defaults).  Host-only; *out receives the plan.  FGE_EINVAL / FGE_EUNSUPPORTED on bad input. */
+fge_status fge_batch_create(int32_t n, const int32_t *H, const int32_t *W, const fge_params *p,
                             fge_batch **out);
 
-/* Release the plan (waits for its last descriptor upload; a captured graph must not be running). */
+/* Release the plan (waits for its last descriptor upload and for the last replay of its graph). */
 void fge_batch_destroy(fge_batch *b);
 
 /* Workspace bytes a run of this plan needs (state buffers, compact copies, tables, counters). */
@@ -201,7 +209,7 @@ int32_t fge_batch_steps(const fge_batch *b);
 int32_t fge_batch_launch_count(const fge_batch *b);
 
 /* Run the batch: I[i], alpha[i], F[i], B[i] are image i's device buffers (layout and type as in
- * fge_estimate_foreground).  Asynchronous on `stream`; the descriptor tables are uploaded from a
+ * fge_estimate_foreground; F[i] and B[i] must not overlap any image's inputs or the workspace).  Asynchronous on `stream`; the descriptor tables are uploaded from a
  * pinned staging buffer owned by the plan, and a second run first waits for the previous run's
  * upload (not its kernels).  The plan must not be used by two threads at once. */
 fge_status fge_batch_run(fge_batch *b, const void *const *I, const void *const *alpha,
@@ -209,17 +217,21 @@ fge_status fge_batch_run(fge_batch *b, const void *const *I, const void *const *
                          void *stream);
 
 /* Capture one run with these pointers into a hipGraph owned by the plan (stream must not be
- * NULL); fge_batch_replay launches it again on any stream.  Nothing is executed by the capture. */
+ * NULL); fge_batch_replay launches it again on any stream.  Nothing is executed by the capture.
+ * Replays of one plan run one after the other (a replay on another stream first waits for the
+ * previous one: they share the workspace).  A new capture first waits for every replay of the
+ * previous graph to finish (it rewrites the pinned table buffer the graph's upload node reads),
+ * then replaces that graph. */
 fge_status fge_batch_capture(fge_batch *b, const void *const *I, const void *const *alpha,
                              void *const *F, void *const *B, void *workspace,
                              size_t workspace_bytes, void *stream);
 fge_status fge_batch_replay(fge_batch *b, void *stream);
 
 /* One-shot forms: workspace size for, and a run of, a batch planned on the fly. */
-size_t fge_batch_workspace_bytes_for(int32_t n, const int32_t *W, const int32_t *H,
+size_t fge_batch_workspace_bytes_for(int32_t n, const int32_t *H, const int32_t *W,
                                      const fge_params *p);
 fge_status fge_estimate_foreground_batch(int32_t n, const void *const *I, const void *const *alpha,
-                                         const int32_t *W, const int32_t *H, const fge_params *p,
+                                         const int32_t *H, const int32_t *W, const fge_params *p,
                                          void *const *F, void *const *B, void *workspace,
                                          size_t workspace_bytes, void *stream);
 
@@ -231,45 +243,46 @@ fge_status fge_estimate_foreground_batch(int32_t n, const void *const *I, const 
  *       (eps_r + omega |a_i - a_j|) sum_c [(F_i^c - F_j^c)^2 + (B_i^c - B_j^c)^2],
  * the quadratic whose per-pixel stationarity conditions are the systems of eq. 9 (eq. 3's local
  * costs with each edge counted once), plus the compositing residual |aF + (1-a)B - I| (eq. 1) over
- * the fractional pixels 0 < a < 1.  All buffers are device buffers in p->storage type (W x H
+ * the fractional pixels 0 < a < 1.  All buffers are device buffers in p->storage type (H x W
  * planes as for fge_estimate_foreground); p supplies omega, eps_r and the storage type (NULL =
  * defaults).  `out` is a DEVICE array of 6 doubles: E, the data term, the smoothness term, the mean
  * and the max |residual| over fractional pixels, and their count.  The workspace (256-byte
- * aligned) holds fge_energy_workspace_bytes(W, H) bytes of partial sums.  Asynchronous. */
-size_t fge_energy_workspace_bytes(int32_t W, int32_t H);
-fge_status fge_energy(const void *I, const void *alpha, const void *F, const void *B, int32_t W,
-                      int32_t H, const fge_params *p, double *out, void *workspace,
+ * aligned) holds fge_energy_workspace_bytes(H, W) bytes of partial sums.  Asynchronous. */
+size_t fge_energy_workspace_bytes(int32_t H, int32_t W);
+fge_status fge_energy(const void *I, const void *alpha, const void *F, const void *B, int32_t H,
+                      int32_t W, const fge_params *p, double *out, void *workspace,
                       size_t workspace_bytes, void *stream);
 
-/* The paper's error measures of a foreground estimate F against a reference G (Section V): over
+/* The paper's error measures of a foreground estimate F against a reference G (Section IV,
+ * "Error Measures"): over
  * the translucent pixels 0 < a_i < 1 of the reference matte `alpha`, each weighted by a_i,
  *   SAD = sum a_i |F_i - G_i|_1,  MSE = sum a_i |F_i - G_i|_2^2,
  *   GRAD = sum a_i |grad F_i - grad G_i|_2^2,
  * gradients from first-order Gaussian derivative filters of standard deviation `sigma` (the
  * paper's 1.4): the sampled Gaussian of radius int(4 sigma + 0.5) <= 16, normalised to sum 1,
  * times x / sigma^2 along the derivative axis, with mirrored borders, for x and y and every
- * channel.  F, G (3 planes) and alpha (1 plane) are W x H device buffers of type dtype (F32 or
+ * channel.  F, G (3 planes) and alpha (1 plane) are H x W device buffers of type dtype (F32 or
  * F16).  `out` is a DEVICE array of 4 doubles: SAD, MSE, GRAD and the number of translucent
  * pixels.  All arithmetic in float64; the reduction order is fixed.  Workspace:
  * fge_quality_workspace_bytes (256-byte aligned). */
-size_t fge_quality_workspace_bytes(int32_t W, int32_t H);
-fge_status fge_quality(const void *F, const void *G, const void *alpha, int32_t W, int32_t H,
+size_t fge_quality_workspace_bytes(int32_t H, int32_t W);
+fge_status fge_quality(const void *F, const void *G, const void *alpha, int32_t H, int32_t W,
                        int32_t dtype, double sigma, double *out, void *workspace,
                        size_t workspace_bytes, void *stream);
 
 /* Composite onto a new background (eq. 1 used forward): C = alpha F + (1 - alpha) B, computed in
  * float64 (each product and the sum rounded once) and rounded to dtype.  Planar device buffers. */
-fge_status fge_composite(const void *F, const void *alpha, const void *B, int32_t W, int32_t H,
+fge_status fge_composite(const void *F, const void *alpha, const void *B, int32_t H, int32_t W,
                          int32_t dtype, void *C, void *stream);
 
 /* Interleaved H x W x C images (C = 3: RGB, or 4: RGBA) to planar: 3 colour planes into `planes`
  * and, for C = 4, the fourth channel into `alpha` (one plane).  Element types are fge_dtype
  * values: U8 maps v to v / 255 (float32 division); a float maps to U8 as
  * round-half-even(clamp(v, 0, 1) * 255); F32 -> F16 rounds to nearest even.  Device buffers. */
-fge_status fge_hwc_to_planar(const void *src, int32_t src_dtype, int32_t channels, int32_t W,
-                             int32_t H, void *planes, void *alpha, int32_t dst_dtype, void *stream);
+fge_status fge_hwc_to_planar(const void *src, int32_t src_dtype, int32_t channels, int32_t H,
+                             int32_t W, void *planes, void *alpha, int32_t dst_dtype, void *stream);
 /* Planar 3 x H x W to interleaved H x W x 3, with the same conversions. */
-fge_status fge_planar_to_hwc(const void *planes, int32_t src_dtype, int32_t W, int32_t H,
+fge_status fge_planar_to_hwc(const void *planes, int32_t src_dtype, int32_t H, int32_t W,
                              void *dst, int32_t dst_dtype, void *stream);
 
 /* ---- autotuner ------------------------------------------------------------------------- */
@@ -294,18 +307,18 @@ typedef struct fge_tune_entry {
 } fge_tune_entry;
 
 int32_t fge_tune_candidates(void);
-size_t fge_tune_workspace_bytes(int32_t W, int32_t H, const fge_params *p);
-fge_status fge_autotune(const void *I, const void *alpha, int32_t W, int32_t H, const fge_params *p,
+size_t fge_tune_workspace_bytes(int32_t H, int32_t W, const fge_params *p);
+fge_status fge_autotune(const void *I, const void *alpha, int32_t H, int32_t W, const fge_params *p,
                         void *F, void *B, void *workspace, size_t workspace_bytes, void *stream,
                         int32_t reps, fge_params *best, fge_tune_entry *entries,
                         int32_t max_entries, int32_t *n_entries);
 
 /* The same search for a batch: each candidate is a batch plan (fge_batch_create) run with
  * fge_batch_run.  The workspace must hold fge_batch_tune_workspace_bytes. */
-size_t fge_batch_tune_workspace_bytes(int32_t n, const int32_t *W, const int32_t *H,
+size_t fge_batch_tune_workspace_bytes(int32_t n, const int32_t *H, const int32_t *W,
                                       const fge_params *p);
 fge_status fge_batch_autotune(int32_t n, const void *const *I, const void *const *alpha,
-                              const int32_t *W, const int32_t *H, const fge_params *p,
+                              const int32_t *H, const int32_t *W, const fge_params *p,
                               void *const *F, void *const *B, void *workspace,
                               size_t workspace_bytes, void *stream, int32_t reps, fge_params *best,
                               fge_tune_entry *entries, int32_t max_entries, int32_t *n_entries);
@@ -369,8 +382,8 @@ typedef struct fge_server_stats {
 /* Fill *c with the defaults above. */
 void fge_server_default_config(fge_server_config *c);
 
-/* Footprint a W x H request is charged against the budget under *p (0 on bad arguments). */
-size_t fge_server_request_bytes(int32_t W, int32_t H, const fge_params *p);
+/* Footprint an H x W request is charged against the budget under *p (0 on bad arguments). */
+size_t fge_server_request_bytes(int32_t H, int32_t W, const fge_params *p);
 
 /* Arena bytes the server keeps for its tick tables under *c (the rest holds workspaces). */
 size_t fge_server_reserved_bytes(const fge_server_config *c);
@@ -389,7 +402,7 @@ fge_status fge_server_create(const fge_params *p, const fge_server_config *c, vo
  * request is reported complete.  Returns at once.  FGE_EBUDGET if the request could never be
  * admitted; FGE_EINVAL / FGE_EUNSUPPORTED on bad arguments; FGE_EHIP if the server has failed. */
 fge_status fge_server_submit(fge_server *s, int64_t id, const void *I, const void *alpha,
-                             int32_t W, int32_t H, void *F, void *B);
+                             int32_t H, int32_t W, void *F, void *B);
 
 /* Move up to `cap` completed requests (completion order) into out[]; returns how many, or a
  * negative status if the server has failed.  Never blocks. */

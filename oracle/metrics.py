@@ -1,8 +1,8 @@
 """Quality measures of an estimated foreground, and compositing -- TEST INFRASTRUCTURE ONLY.
 
 Plain float64 NumPy (plus SciPy's Gaussian derivative filter as a library step) following the
-paper's error measures (Section V, evaluation): over the translucent pixels 0 < alpha_i < 1 of the
-reference matte, each weighted by alpha_i,
+paper's error measures (Section IV, "Error Measures"): over the translucent pixels
+0 < alpha_i < 1 of the reference matte, each weighted by alpha_i,
 
     SAD  = sum alpha_i |F_i - G_i|_1           (L1 over the colour channels)
     MSE  = sum alpha_i |F_i - G_i|_2^2

@@ -10,7 +10,7 @@
 
 namespace {
 
-constexpr int32_t kAbiVersion = 3;
+constexpr int32_t kAbiVersion = 4;
 
 struct ProfileRecord {
     int level;          // 0 = finest
@@ -89,7 +89,7 @@ const char *fge_status_string(int status) {
 
 int32_t fge_version(void) { return kAbiVersion; }
 
-int32_t fge_num_levels(int32_t W, int32_t H) {
+int32_t fge_num_levels(int32_t H, int32_t W) {
     if (W < 1 || H < 1 || W > fge::kMaxSide || H > fge::kMaxSide) return 0;
     return fge::num_levels(W, H);
 }
@@ -101,7 +101,7 @@ int32_t fge_level_size(int32_t full, int32_t level, int32_t n_levels) {
     return fge::level_size(full, level, n_levels);
 }
 
-fge_status fge_plan(int32_t W, int32_t H, const fge_params *p, int32_t max_levels, int32_t *w_out,
+fge_status fge_plan(int32_t H, int32_t W, const fge_params *p, int32_t max_levels, int32_t *w_out,
                     int32_t *h_out, int32_t *iters_out, int32_t *n_levels_out,
                     int32_t *n_coarse_out) {
     fge_params tmp;
@@ -119,7 +119,7 @@ fge_status fge_plan(int32_t W, int32_t H, const fge_params *p, int32_t max_level
     return FGE_OK;
 }
 
-size_t fge_workspace_bytes(int32_t W, int32_t H, const fge_params *p) {
+size_t fge_workspace_bytes(int32_t H, int32_t W, const fge_params *p) {
     fge_params tmp;
     fge::Plan plan;
     const fge_params &prm = resolve(p, tmp);
@@ -128,7 +128,7 @@ size_t fge_workspace_bytes(int32_t W, int32_t H, const fge_params *p) {
     return plan.ws_bytes;
 }
 
-fge_status fge_estimate_foreground(const void *I, const void *alpha, int32_t W, int32_t H,
+fge_status fge_estimate_foreground(const void *I, const void *alpha, int32_t H, int32_t W,
                                    const fge_params *p, void *F, void *B, void *workspace,
                                    size_t workspace_bytes, void *stream) {
     fge_params tmp;
@@ -136,7 +136,9 @@ fge_status fge_estimate_foreground(const void *I, const void *alpha, int32_t W, 
     fge::Plan plan;
     const fge_status st = fge::make_plan(W, H, prm, &plan, fge::kPlanSingle);
     if (st != FGE_OK) return st;
-    if (!I || !alpha || !F || !B || F == B) return FGE_EINVAL;
+    if (!I || !alpha || !F || !B) return FGE_EINVAL;
+    if (fge::outputs_alias(I, alpha, F, B, W, H, plan.elem, workspace, workspace_bytes))
+        return FGE_EINVAL;
     if (prm.order == FGE_JACOBI)   // fixed counts on the per-level Jacobi kernels
         return fge::estimate_converge(I, alpha, W, H, prm, -1.0, 0, F, B, nullptr, workspace,
                                       workspace_bytes, stream);

@@ -59,6 +59,10 @@ struct fge_batch {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     char *graph_staging = nullptr;
+    // Recorded after every replay: the graph's upload node reads graph_staging when it runs, so
+    // a new capture (which refills graph_staging) and destroy wait for it first.
+    hipEvent_t replayed = nullptr;
+    bool replay_pending = false;
 };
 
 namespace {
@@ -153,8 +157,12 @@ fge_status enqueue(fge_batch &b, const void *const *I, const void *const *A, voi
 fge_status check_ptrs(const fge_batch &b, const void *const *I, const void *const *A,
                       void *const *F, void *const *B, const void *workspace, size_t bytes) {
     if (!I || !A || !F || !B) return FGE_EINVAL;
-    for (int i = 0; i < b.n; ++i)
-        if (!I[i] || !A[i] || !F[i] || !B[i] || F[i] == B[i]) return FGE_EINVAL;
+    for (int i = 0; i < b.n; ++i) {
+        if (!I[i] || !A[i] || !F[i] || !B[i]) return FGE_EINVAL;
+        const fge::Plan &pl = b.plans[i];
+        if (fge::outputs_alias(I[i], A[i], F[i], B[i], pl.W, pl.H, pl.elem, workspace, bytes))
+            return FGE_EINVAL;
+    }
     if (!workspace || bytes < b.ws_bytes) return FGE_EWORKSPACE;
     if (reinterpret_cast<uintptr_t>(workspace) & 255) return FGE_EWORKSPACE;
     return FGE_OK;
@@ -164,7 +172,7 @@ fge_status check_ptrs(const fge_batch &b, const void *const *I, const void *cons
 
 extern "C" {
 
-fge_status fge_batch_create(int32_t n, const int32_t *W, const int32_t *H, const fge_params *p,
+fge_status fge_batch_create(int32_t n, const int32_t *H, const int32_t *W, const fge_params *p,
                             fge_batch **out) {
     if (!out || n < 1 || n > (1 << 16) || !W || !H) return FGE_EINVAL;
     *out = nullptr;
@@ -288,6 +296,10 @@ fge_status fge_batch_create(int32_t n, const int32_t *W, const int32_t *H, const
 
 void fge_batch_destroy(fge_batch *b) {
     if (!b) return;
+    if (b->replayed) {
+        if (b->replay_pending) (void)hipEventSynchronize(b->replayed);
+        (void)hipEventDestroy(b->replayed);
+    }
     if (b->staged) {
         if (b->staged_pending) (void)hipEventSynchronize(b->staged);
         (void)hipEventDestroy(b->staged);
@@ -334,6 +346,12 @@ fge_status fge_batch_capture(fge_batch *b, const void *const *I, const void *con
     if (!b || !stream) return FGE_EINVAL;
     const fge_status st = check_ptrs(*b, I, alpha, F, B, workspace, workspace_bytes);
     if (st != FGE_OK) return st;
+    // Replays of the previous graph may still be queued: their upload node reads graph_staging,
+    // which this capture refills.
+    if (b->replay_pending) {
+        if (hipEventSynchronize(b->replayed) != hipSuccess) return FGE_EHIP;
+        b->replay_pending = false;
+    }
     if (b->exec) {
         (void)hipGraphExecDestroy(b->exec);
         b->exec = nullptr;
@@ -362,24 +380,33 @@ fge_status fge_batch_capture(fge_batch *b, const void *const *I, const void *con
 
 fge_status fge_batch_replay(fge_batch *b, void *stream) {
     if (!b || !b->exec) return FGE_EINVAL;
-    return hipGraphLaunch(b->exec, static_cast<hipStream_t>(stream)) == hipSuccess ? FGE_OK : FGE_EHIP;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (!b->replayed && hipEventCreateWithFlags(&b->replayed, hipEventDisableTiming) != hipSuccess)
+        return FGE_EHIP;
+    // Replays share the workspace and its counters, so each one waits for the previous one
+    // (possibly on another stream); the event of the last replay then covers them all.
+    if (b->replay_pending && hipStreamWaitEvent(s, b->replayed, 0) != hipSuccess) return FGE_EHIP;
+    if (hipGraphLaunch(b->exec, s) != hipSuccess) return FGE_EHIP;
+    if (hipEventRecord(b->replayed, s) != hipSuccess) return FGE_EHIP;
+    b->replay_pending = true;
+    return FGE_OK;
 }
 
-size_t fge_batch_workspace_bytes_for(int32_t n, const int32_t *W, const int32_t *H,
+size_t fge_batch_workspace_bytes_for(int32_t n, const int32_t *H, const int32_t *W,
                                      const fge_params *p) {
     fge_batch *b = nullptr;
-    if (fge_batch_create(n, W, H, p, &b) != FGE_OK) return 0;
+    if (fge_batch_create(n, H, W, p, &b) != FGE_OK) return 0;
     const size_t v = b->ws_bytes;
     fge_batch_destroy(b);
     return v;
 }
 
 fge_status fge_estimate_foreground_batch(int32_t n, const void *const *I, const void *const *alpha,
-                                         const int32_t *W, const int32_t *H, const fge_params *p,
+                                         const int32_t *H, const int32_t *W, const fge_params *p,
                                          void *const *F, void *const *B, void *workspace,
                                          size_t workspace_bytes, void *stream) {
     fge_batch *b = nullptr;
-    fge_status st = fge_batch_create(n, W, H, p, &b);
+    fge_status st = fge_batch_create(n, H, W, p, &b);
     if (st != FGE_OK) return st;
     st = fge_batch_run(b, I, alpha, F, B, workspace, workspace_bytes, stream);
     fge_batch_destroy(b);   // waits for the descriptor upload, not for the kernels

@@ -440,7 +440,9 @@ fge_status estimate_levels(const void *I, const void *A, int W, int H, const fge
     Plan pl;
     const fge_status st = cv_plan(W, H, p, &pl);
     if (st != FGE_OK) return st;
-    if (!I || !A || !F || !B || F == B) return FGE_EINVAL;
+    if (!I || !A || !F || !B) return FGE_EINVAL;
+    if (outputs_alias(I, A, F, B, W, H, p.storage == FGE_F16 ? 2 : 4, workspace, workspace_bytes))
+        return FGE_EINVAL;
     if (resize != FGE_RESIZE_NEAREST && resize != FGE_RESIZE_SMOOTH) return FGE_EINVAL;
     if (tol >= 0.0 && (max_sweeps < 1 || max_sweeps > kCvMaxSweeps)) return FGE_EINVAL;
     if (!(tol == tol)) return FGE_EINVAL;   // NaN
@@ -465,7 +467,7 @@ fge_status estimate_converge(const void *I, const void *A, int W, int H, const f
 
 extern "C" {
 
-size_t fge_converge_workspace_bytes(int32_t W, int32_t H, const fge_params *p) {
+size_t fge_converge_workspace_bytes(int32_t H, int32_t W, const fge_params *p) {
     fge_params tmp;
     if (!p) {
         fge_default_params(&tmp);
@@ -474,7 +476,7 @@ size_t fge_converge_workspace_bytes(int32_t W, int32_t H, const fge_params *p) {
     return fge::converge_workspace_bytes(W, H, *p);
 }
 
-size_t fge_levels_workspace_bytes(int32_t W, int32_t H, const fge_params *p,
+size_t fge_levels_workspace_bytes(int32_t H, int32_t W, const fge_params *p,
                                   const fge_level_options *o) {
     fge_params tmp;
     if (!p) {
@@ -485,7 +487,7 @@ size_t fge_levels_workspace_bytes(int32_t W, int32_t H, const fge_params *p,
     return fge::levels_workspace_bytes(W, H, *p, o->resize);
 }
 
-fge_status fge_estimate_foreground_levels(const void *I, const void *alpha, int32_t W, int32_t H,
+fge_status fge_estimate_foreground_levels(const void *I, const void *alpha, int32_t H, int32_t W,
                                           const fge_params *p, const fge_level_options *o,
                                           void *F, void *B, int32_t *sweeps_out, void *workspace,
                                           size_t workspace_bytes, void *stream) {
@@ -499,7 +501,7 @@ fge_status fge_estimate_foreground_levels(const void *I, const void *alpha, int3
                                 sweeps_out, workspace, workspace_bytes, stream);
 }
 
-fge_status fge_estimate_foreground_converge(const void *I, const void *alpha, int32_t W, int32_t H,
+fge_status fge_estimate_foreground_converge(const void *I, const void *alpha, int32_t H, int32_t W,
                                             const fge_params *p, double tol, int32_t max_sweeps,
                                             void *F, void *B, int32_t *sweeps_out, void *workspace,
                                             size_t workspace_bytes, void *stream) {

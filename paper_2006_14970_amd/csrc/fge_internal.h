@@ -56,6 +56,27 @@ struct Plan {
     size_t pyr_lv[kMaxLevels] = {};
 };
 
+// Whether the byte ranges [a, a + na) and [b, b + nb) share a byte (a null or empty range never
+// does).
+inline bool overlaps(const void *a, size_t na, const void *b, size_t nb) {
+    if (!a || !b || na == 0 || nb == 0) return false;
+    const uintptr_t x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
+    return x < y + nb && y < x + na;
+}
+
+// The output rule of every estimation entry point: F and B (3 planes of W*H elements of `elem`
+// bytes each) share no byte with each other, with I (3 planes), alpha (1 plane) or the workspace.
+inline bool outputs_alias(const void *I, const void *A, const void *F, const void *B, int W, int H,
+                          int elem, const void *ws, size_t ws_bytes) {
+    const size_t plane = static_cast<size_t>(W) * H * elem;
+    const void *in[3] = {I, A, ws};
+    const size_t in_n[3] = {3 * plane, plane, ws_bytes};
+    for (int k = 0; k < 3; ++k)
+        if (overlaps(F, 3 * plane, in[k], in_n[k]) || overlaps(B, 3 * plane, in[k], in_n[k]))
+            return true;
+    return overlaps(F, 3 * plane, B, 3 * plane);
+}
+
 int num_levels(int W, int H);
 int level_size(int full, int level, int n);
 bool params_valid(const fge_params &p);

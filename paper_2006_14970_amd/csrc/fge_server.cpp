@@ -556,7 +556,7 @@ void fge_server_default_config(fge_server_config *c) {
     c->tick_table_bytes = kDefaultTableBytes;
 }
 
-size_t fge_server_request_bytes(int32_t W, int32_t H, const fge_params *p) {
+size_t fge_server_request_bytes(int32_t H, int32_t W, const fge_params *p) {
     fge_params prm;
     if (p) prm = *p; else fge_default_params(&prm);
     fge::Plan pl;
@@ -633,14 +633,18 @@ fge_status fge_server_create(const fge_params *p, const fge_server_config *c, vo
 }
 
 fge_status fge_server_submit(fge_server *s, int64_t id, const void *I, const void *alpha,
-                             int32_t W, int32_t H, void *F, void *B) {
-    if (!s || !I || !alpha || !F || !B || F == B) return FGE_EINVAL;
+                             int32_t H, int32_t W, void *F, void *B) {
+    if (!s || !I || !alpha || !F || !B) return FGE_EINVAL;
     Request *r = new (std::nothrow) Request();
     if (!r) return FGE_ENOMEM;
     const fge_status st = request_plan(s->prm, W, H, &r->plan);
     if (st != FGE_OK) {
         delete r;
         return st;
+    }
+    if (fge::outputs_alias(I, alpha, F, B, W, H, r->plan.elem, s->arena, s->arena_bytes)) {
+        delete r;
+        return FGE_EINVAL;
     }
     r->charge = footprint(r->plan);
     if (r->charge > s->budget || max_tick_bytes(r->plan, s->prm.strip_rows) > s->cfg.tick_table_bytes ||

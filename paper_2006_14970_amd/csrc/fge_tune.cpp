@@ -101,7 +101,7 @@ int32_t fge_tune_candidates(void) {
     return static_cast<int32_t>(sizeof(kRows) / sizeof(kRows[0]) * sizeof(kTileMax) / sizeof(kTileMax[0]));
 }
 
-size_t fge_tune_workspace_bytes(int32_t W, int32_t H, const fge_params *p) {
+size_t fge_tune_workspace_bytes(int32_t H, int32_t W, const fge_params *p) {
     fge_params tmp;
     const fge_params &base = resolve(p, tmp);
     size_t need = 0;
@@ -113,7 +113,7 @@ size_t fge_tune_workspace_bytes(int32_t W, int32_t H, const fge_params *p) {
     return need;
 }
 
-fge_status fge_autotune(const void *I, const void *alpha, int32_t W, int32_t H, const fge_params *p,
+fge_status fge_autotune(const void *I, const void *alpha, int32_t H, int32_t W, const fge_params *p,
                         void *F, void *B, void *workspace, size_t workspace_bytes, void *stream,
                         int32_t reps, fge_params *best, fge_tune_entry *entries,
                         int32_t max_entries, int32_t *n_entries) {
@@ -123,24 +123,27 @@ fge_status fge_autotune(const void *I, const void *alpha, int32_t W, int32_t H, 
     fge::Plan pl;
     const fge_status st = fge::make_plan(W, H, base, &pl);
     if (st != FGE_OK) return st;
-    if (!I || !alpha || !F || !B || F == B) return FGE_EINVAL;
-    const size_t need = fge_tune_workspace_bytes(W, H, &base);
+    if (!I || !alpha || !F || !B) return FGE_EINVAL;
+    if (fge::outputs_alias(I, alpha, F, B, W, H, base.storage == FGE_F16 ? 2 : 4, workspace,
+                           workspace_bytes))
+        return FGE_EINVAL;
+    const size_t need = fge_tune_workspace_bytes(H, W, &base);
     if (need > 0 && (!workspace || workspace_bytes < need)) return FGE_EWORKSPACE;
     return search(base, reps, stream,
                   [&](size_t, const fge_params &q) {
-                      return fge_estimate_foreground(I, alpha, W, H, &q, F, B, workspace,
+                      return fge_estimate_foreground(I, alpha, H, W, &q, F, B, workspace,
                                                      workspace_bytes, stream);
                   },
                   best, entries, max_entries, n_entries);
 }
 
-size_t fge_batch_tune_workspace_bytes(int32_t n, const int32_t *W, const int32_t *H,
+size_t fge_batch_tune_workspace_bytes(int32_t n, const int32_t *H, const int32_t *W,
                                       const fge_params *p) {
     fge_params tmp;
     const fge_params &base = resolve(p, tmp);
     size_t need = 0;
     for (const Candidate &c : candidates(base)) {
-        const size_t v = fge_batch_workspace_bytes_for(n, W, H, &c.p);
+        const size_t v = fge_batch_workspace_bytes_for(n, H, W, &c.p);
         if (v == 0) return 0;
         if (v > need) need = v;
     }
@@ -148,21 +151,21 @@ size_t fge_batch_tune_workspace_bytes(int32_t n, const int32_t *W, const int32_t
 }
 
 fge_status fge_batch_autotune(int32_t n, const void *const *I, const void *const *alpha,
-                              const int32_t *W, const int32_t *H, const fge_params *p,
+                              const int32_t *H, const int32_t *W, const fge_params *p,
                               void *const *F, void *const *B, void *workspace,
                               size_t workspace_bytes, void *stream, int32_t reps, fge_params *best,
                               fge_tune_entry *entries, int32_t max_entries, int32_t *n_entries) {
     fge_params tmp;
     const fge_params &base = resolve(p, tmp);
     if (!best || reps < 0 || reps > 1000) return FGE_EINVAL;
-    const size_t need = fge_batch_tune_workspace_bytes(n, W, H, &base);
+    const size_t need = fge_batch_tune_workspace_bytes(n, H, W, &base);
     if (need == 0) return FGE_EINVAL;
     if (!workspace || workspace_bytes < need) return FGE_EWORKSPACE;
     std::vector<fge_batch *> plans;
     fge_status st = FGE_OK;
     for (const Candidate &c : candidates(base)) {
         fge_batch *b = nullptr;
-        st = fge_batch_create(n, W, H, &c.p, &b);
+        st = fge_batch_create(n, H, W, &c.p, &b);
         if (st != FGE_OK) break;
         plans.push_back(b);
     }

@@ -137,10 +137,11 @@ __global__ __launch_bounds__(kRedThreads) void energy_final_kernel(const double 
 
 // ---- quality measures and compositing -------------------------------------------------------
 //
-// The paper's error measures of a foreground estimate F against a reference G (Section V): over
-// the translucent pixels 0 < a_i < 1 of the reference matte, weighted by a_i, SAD = sum a_i
-// |F_i - G_i|_1, MSE = sum a_i |F_i - G_i|_2^2 and GRAD = sum a_i |grad F_i - grad G_i|_2^2, the
-// gradients from first-order Gaussian derivative filters.  The filter is the sampled Gaussian of
+// The paper's error measures of a foreground estimate F against a reference G (Section IV,
+// "Error Measures"): over the translucent pixels 0 < a_i < 1 of the reference matte, weighted by
+// a_i, SAD = sum a_i |F_i - G_i|_1, MSE = sum a_i |F_i - G_i|_2^2 and
+// GRAD = sum a_i |grad F_i - grad G_i|_2^2, the gradients from first-order Gaussian derivative
+// filters.  The filter is the sampled Gaussian of
 // radius int(4 sigma + 0.5) normalised to sum 1; the x derivative at pixel (x, y) is
 // sum_a phi(a) sum_b (b / sigma^2) phi(b) D(x + b, y + a), the y derivative likewise with the
 // roles swapped, D = F - G (the filters are linear), with mirrored borders (d c b a | a b c d).
@@ -374,13 +375,13 @@ int launch_energy(const void *I, const void *A, int W, int H, const void *F, con
 
 extern "C" {
 
-size_t fge_energy_workspace_bytes(int32_t W, int32_t H) {
+size_t fge_energy_workspace_bytes(int32_t H, int32_t W) {
     if (W < 1 || H < 1 || W > fge::kMaxSide || H > fge::kMaxSide) return 0;
     return (static_cast<size_t>(fge::energy_blocks(W, H)) * 5 * sizeof(double) + 255) & ~static_cast<size_t>(255);
 }
 
-fge_status fge_energy(const void *I, const void *alpha, const void *F, const void *B, int32_t W,
-                      int32_t H, const fge_params *p, double *out, void *workspace,
+fge_status fge_energy(const void *I, const void *alpha, const void *F, const void *B, int32_t H,
+                      int32_t W, const fge_params *p, double *out, void *workspace,
                       size_t workspace_bytes, void *stream) {
     fge_params tmp;
     if (!p) {
@@ -390,7 +391,7 @@ fge_status fge_energy(const void *I, const void *alpha, const void *F, const voi
     if (!fge::params_valid(*p)) return FGE_EINVAL;
     if (W < 1 || H < 1 || W > fge::kMaxSide || H > fge::kMaxSide) return FGE_EINVAL;
     if (!I || !alpha || !F || !B || !out) return FGE_EINVAL;
-    const size_t need = fge_energy_workspace_bytes(W, H);
+    const size_t need = fge_energy_workspace_bytes(H, W);
     if (!workspace || workspace_bytes < need || (reinterpret_cast<uintptr_t>(workspace) & 255))
         return FGE_EWORKSPACE;
     return fge::launch_energy(I, alpha, W, H, F, B, W, H, p->omega, p->eps_r, p->storage,
@@ -399,12 +400,12 @@ fge_status fge_energy(const void *I, const void *alpha, const void *F, const voi
                : FGE_OK;
 }
 
-size_t fge_quality_workspace_bytes(int32_t W, int32_t H) {
+size_t fge_quality_workspace_bytes(int32_t H, int32_t W) {
     if (W < 1 || H < 1 || W > fge::kMaxSide || H > fge::kMaxSide) return 0;
     return (static_cast<size_t>(fge::energy_blocks(W, H)) * 4 * sizeof(double) + 255) & ~static_cast<size_t>(255);
 }
 
-fge_status fge_quality(const void *F, const void *G, const void *alpha, int32_t W, int32_t H,
+fge_status fge_quality(const void *F, const void *G, const void *alpha, int32_t H, int32_t W,
                        int32_t dtype, double sigma, double *out, void *workspace,
                        size_t workspace_bytes, void *stream) {
     if (!F || !G || !alpha || !out || W < 1 || H < 1 || W > fge::kMaxSide || H > fge::kMaxSide)
@@ -412,7 +413,7 @@ fge_status fge_quality(const void *F, const void *G, const void *alpha, int32_t 
     if (dtype != FGE_F32 && dtype != FGE_F16) return FGE_EINVAL;
     const int r = static_cast<int>(4.0 * sigma + 0.5);
     if (!(sigma > 0.0) || r < 1 || r > fge::kGradMaxR) return FGE_EINVAL;
-    const size_t need = fge_quality_workspace_bytes(W, H);
+    const size_t need = fge_quality_workspace_bytes(H, W);
     if (!workspace || workspace_bytes < need || (reinterpret_cast<uintptr_t>(workspace) & 255))
         return FGE_EWORKSPACE;
     fge::GradFilter K{};
@@ -439,7 +440,7 @@ fge_status fge_quality(const void *F, const void *G, const void *alpha, int32_t 
     return hipGetLastError() == hipSuccess ? FGE_OK : FGE_EHIP;
 }
 
-fge_status fge_composite(const void *F, const void *alpha, const void *B, int32_t W, int32_t H,
+fge_status fge_composite(const void *F, const void *alpha, const void *B, int32_t H, int32_t W,
                          int32_t dtype, void *C, void *stream) {
     if (!F || !alpha || !B || !C || W < 1 || H < 1 || W > fge::kMaxSide || H > fge::kMaxSide)
         return FGE_EINVAL;
@@ -458,8 +459,8 @@ fge_status fge_composite(const void *F, const void *alpha, const void *B, int32_
     return hipGetLastError() == hipSuccess ? FGE_OK : FGE_EHIP;
 }
 
-fge_status fge_hwc_to_planar(const void *src, int32_t src_dtype, int32_t channels, int32_t W,
-                             int32_t H, void *planes, void *alpha, int32_t dst_dtype,
+fge_status fge_hwc_to_planar(const void *src, int32_t src_dtype, int32_t channels, int32_t H,
+                             int32_t W, void *planes, void *alpha, int32_t dst_dtype,
                              void *stream) {
     if (!src || !planes || W < 1 || H < 1 || W > fge::kMaxSide || H > fge::kMaxSide) return FGE_EINVAL;
     if (channels != 3 && channels != 4) return FGE_EINVAL;
@@ -477,7 +478,7 @@ fge_status fge_hwc_to_planar(const void *src, int32_t src_dtype, int32_t channel
     return err ? FGE_EHIP : FGE_OK;
 }
 
-fge_status fge_planar_to_hwc(const void *planes, int32_t src_dtype, int32_t W, int32_t H,
+fge_status fge_planar_to_hwc(const void *planes, int32_t src_dtype, int32_t H, int32_t W,
                              void *dst, int32_t dst_dtype, void *stream) {
     if (!planes || !dst || W < 1 || H < 1 || W > fge::kMaxSide || H > fge::kMaxSide) return FGE_EINVAL;
     if (!fge::dtype_ok(src_dtype) || !fge::dtype_ok(dst_dtype)) return FGE_EINVAL;

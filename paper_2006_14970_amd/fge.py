@@ -247,8 +247,8 @@ def default_params(**overrides) -> Params:
     return p
 
 
-def num_levels(W: int, H: int) -> int:
-    return _lib().fge_num_levels(W, H)
+def num_levels(H: int, W: int) -> int:
+    return _lib().fge_num_levels(H, W)
 
 
 def level_size(full: int, level: int, n_levels: int) -> int:
@@ -261,18 +261,18 @@ class PlanInfo:
     n_coarse: int         # leading levels run by the LDS-resident coarse kernel
 
 
-def plan(W: int, H: int, params: Params | None = None) -> PlanInfo:
+def plan(H: int, W: int, params: Params | None = None) -> PlanInfo:
     arr = ctypes.c_int32 * MAX_LEVELS
     w, h, it = arr(), arr(), arr()
     n, nc = ctypes.c_int32(), ctypes.c_int32()
-    st = _lib().fge_plan(W, H, ctypes.byref(params) if params else None, MAX_LEVELS, w, h, it,
+    st = _lib().fge_plan(H, W, ctypes.byref(params) if params else None, MAX_LEVELS, w, h, it,
                          ctypes.byref(n), ctypes.byref(nc))
     _check(st, "fge_plan")
     return PlanInfo([(w[i], h[i], it[i]) for i in range(n.value)], nc.value)
 
 
-def workspace_bytes(W: int, H: int, params: Params | None = None) -> int:
-    return _lib().fge_workspace_bytes(W, H, ctypes.byref(params) if params else None)
+def workspace_bytes(H: int, W: int, params: Params | None = None) -> int:
+    return _lib().fge_workspace_bytes(H, W, ctypes.byref(params) if params else None)
 
 
 def _stream_ptr(stream):
@@ -281,11 +281,35 @@ def _stream_ptr(stream):
     return ctypes.c_void_p(s.cuda_stream)
 
 
+def _on_stream(fn):
+    """Run a binding function with `stream` (when given) as torch's current stream, so that every
+    tensor it allocates -- outputs and scratch workspaces -- comes from that stream's pool of
+    PyTorch's caching allocator.  A scratch tensor dropped on return is then only handed out again
+    to work ordered after what was enqueued on `stream`; tensors allocated on another stream and
+    used on `stream` could be reused while the kernels still run.  Tensors the caller passes in
+    follow PyTorch's usual rule: ready before the call, and kept (or record_stream'ed) by the
+    caller while `stream` uses them."""
+    import functools
+    import inspect
+    sig = inspect.signature(fn)
+
+    @functools.wraps(fn)
+    def wrapper(*args, **kwargs):
+        stream = sig.bind(*args, **kwargs).arguments.get("stream")
+        if stream is None:
+            return fn(*args, **kwargs)
+        import torch
+        with torch.cuda.stream(stream):
+            return fn(*args, **kwargs)
+    return wrapper
+
+
 def storage_dtype(params: Params):
     import torch
     return torch.float16 if params.storage == F16 else torch.float32
 
 
+@_on_stream
 def estimate_foreground(I, alpha, params: Params | None = None, F=None, B=None, workspace=None,
                         stream=None):
     """Algorithm 1 on the GPU.  Returns (F, B); the work is enqueued on `stream` (default: the
@@ -308,12 +332,12 @@ def estimate_foreground(I, alpha, params: Params | None = None, F=None, B=None, 
     for name, t in (("F", F), ("B", B)):
         if tuple(t.shape) != (3, H, W) or t.dtype != dt or not t.is_contiguous() or not t.is_cuda:
             raise ValueError(f"{name} must be a contiguous (3, H, W) CUDA tensor of dtype {dt}")
-    need = workspace_bytes(W, H, p)
+    need = workspace_bytes(H, W, p)
     if workspace is None and need > 0:
         workspace = torch.empty(need, dtype=torch.uint8, device=I.device)
     ws_ptr = workspace.data_ptr() if workspace is not None else None
     ws_len = workspace.numel() * workspace.element_size() if workspace is not None else 0
-    st = _lib().fge_estimate_foreground(I.data_ptr(), alpha.data_ptr(), W, H, ctypes.byref(p),
+    st = _lib().fge_estimate_foreground(I.data_ptr(), alpha.data_ptr(), H, W, ctypes.byref(p),
                                         F.data_ptr(), B.data_ptr(), ws_ptr, ws_len,
                                         _stream_ptr(stream))
     _check(st, "fge_estimate_foreground")
@@ -341,17 +365,18 @@ def _ptr_array(tensors):
 
 
 class Batch:
-    """A batch plan for images of sizes [(W, H), ...] (fge_batch_create).  Every image follows
-    its own level plan, so its result is bit-identical to estimate_foreground's."""
+    """A batch plan for images of shapes [(H, W), ...], height first as in the C ABI
+    (fge_batch_create).  Every image follows its own level plan, so its result is bit-identical
+    to estimate_foreground's."""
 
-    def __init__(self, sizes, params: Params | None = None):
-        self.sizes = [(int(w), int(h)) for w, h in sizes]
+    def __init__(self, shapes, params: Params | None = None):
+        self.shapes = [(int(h), int(w)) for h, w in shapes]
         self.params = params if params is not None else default_params()
-        n = len(self.sizes)
-        W = (ctypes.c_int32 * n)(*[w for w, _ in self.sizes])
-        H = (ctypes.c_int32 * n)(*[h for _, h in self.sizes])
+        n = len(self.shapes)
+        H = (ctypes.c_int32 * n)(*[h for h, _ in self.shapes])
+        W = (ctypes.c_int32 * n)(*[w for _, w in self.shapes])
         handle = ctypes.c_void_p()
-        _check(_lib().fge_batch_create(n, W, H, ctypes.byref(self.params), ctypes.byref(handle)),
+        _check(_lib().fge_batch_create(n, H, W, ctypes.byref(self.params), ctypes.byref(handle)),
                "fge_batch_create")
         self._h = handle
         self._keep = None
@@ -382,14 +407,14 @@ class Batch:
     def _args(self, Is, alphas, Fs, Bs, workspace):
         import torch
         dt = storage_dtype(self.params)
-        n = len(self.sizes)
+        n = len(self.shapes)
         if not (len(Is) == len(alphas) == n):
             raise ValueError("one I and one alpha per image")
         if Fs is None:
-            Fs = [torch.empty((3, h, w), dtype=dt, device=Is[0].device) for w, h in self.sizes]
+            Fs = [torch.empty((3, h, w), dtype=dt, device=Is[0].device) for h, w in self.shapes]
         if Bs is None:
-            Bs = [torch.empty((3, h, w), dtype=dt, device=Is[0].device) for w, h in self.sizes]
-        for (w, h), I, a, F, B in zip(self.sizes, Is, alphas, Fs, Bs):
+            Bs = [torch.empty((3, h, w), dtype=dt, device=Is[0].device) for h, w in self.shapes]
+        for (h, w), I, a, F, B in zip(self.shapes, Is, alphas, Fs, Bs):
             for name, t, shp in (("I", I, (3, h, w)), ("alpha", a, (h, w)), ("F", F, (3, h, w)),
                                  ("B", B, (3, h, w))):
                 if tuple(t.shape) != shp or t.dtype != dt or not t.is_cuda or not t.is_contiguous():
@@ -399,6 +424,7 @@ class Batch:
                                     device=Is[0].device)
         return Fs, Bs, workspace
 
+    @_on_stream
     def run(self, Is, alphas, Fs=None, Bs=None, workspace=None, stream=None):
         """Enqueue the batch; returns (Fs, Bs).  Does not synchronise."""
         Fs, Bs, workspace = self._args(Is, alphas, Fs, Bs, workspace)
@@ -409,6 +435,7 @@ class Batch:
         self._keep = (Is, alphas, Fs, Bs, workspace)
         return Fs, Bs
 
+    @_on_stream
     def capture(self, Is, alphas, Fs=None, Bs=None, workspace=None, stream=None):
         """Capture one run with these buffers into a hipGraph; replay() launches it."""
         Fs, Bs, workspace = self._args(Is, alphas, Fs, Bs, workspace)
@@ -434,9 +461,9 @@ def server_config(**overrides) -> ServerConfig:
     return c
 
 
-def server_request_bytes(W: int, H: int, params: Params | None = None) -> int:
-    """Footprint a W x H request is charged against a server's budget."""
-    return _lib().fge_server_request_bytes(W, H, ctypes.byref(params) if params else None)
+def server_request_bytes(H: int, W: int, params: Params | None = None) -> int:
+    """Footprint an H x W request is charged against a server's budget."""
+    return _lib().fge_server_request_bytes(H, W, ctypes.byref(params) if params else None)
 
 
 def server_reserved_bytes(config: ServerConfig | None = None) -> int:
@@ -485,13 +512,13 @@ class Server:
                              ("B", B, (3, H, W))):
             if tuple(t.shape) != shp or t.dtype != dt or not t.is_cuda or not t.is_contiguous():
                 raise ValueError(f"{name} must be a contiguous CUDA tensor {shp} of dtype {dt}")
-        self.submit_ptrs(rid, I.data_ptr(), alpha.data_ptr(), W, H, F.data_ptr(), B.data_ptr())
+        self.submit_ptrs(rid, I.data_ptr(), alpha.data_ptr(), H, W, F.data_ptr(), B.data_ptr())
         self._held[rid] = (I, alpha, F, B)
         return F, B
 
-    def submit_ptrs(self, rid: int, I: int, alpha: int, W: int, H: int, F: int, B: int):
+    def submit_ptrs(self, rid: int, I: int, alpha: int, H: int, W: int, F: int, B: int):
         """Raw form: device addresses the caller keeps alive until the request completes."""
-        _check(_lib().fge_server_submit(self._h, rid, I, alpha, W, H, F, B), "fge_server_submit")
+        _check(_lib().fge_server_submit(self._h, rid, I, alpha, H, W, F, B), "fge_server_submit")
 
     def poll(self, cap: int = 4096):
         """Completed requests since the last poll: a list of ServerResult records."""
@@ -571,6 +598,7 @@ def _entries(buf, n):
              "ms": buf[i].ms, "status": buf[i].status} for i in range(n)]
 
 
+@_on_stream
 def autotune(I, alpha, params: Params | None = None, reps: int = 3, stream=None,
              cache_path: str | None = None):
     """Search strip height and tile threshold for this image size on the device (fge_autotune).
@@ -579,20 +607,20 @@ def autotune(I, alpha, params: Params | None = None, reps: int = 3, stream=None,
     import torch
     p = params if params is not None else default_params()
     _, H, W = I.shape
-    key = _tune_key("single", p, [(W, H)])
+    key = _tune_key("single", p, [(H, W)])
     hit = _cache_get(cache_path, key)
     if hit is not None:
         return _tuned(p, hit["strip_rows"], hit["tile_max_px"]), hit.get("entries", [])
     dt = storage_dtype(p)
     F = torch.empty((3, H, W), dtype=dt, device=I.device)
     B = torch.empty_like(F)
-    need = _lib().fge_tune_workspace_bytes(W, H, ctypes.byref(p))
+    need = _lib().fge_tune_workspace_bytes(H, W, ctypes.byref(p))
     ws = torch.empty(max(1, need), dtype=torch.uint8, device=I.device)
     nc = _lib().fge_tune_candidates()
     buf = (TuneEntry * nc)()
     n = ctypes.c_int32()
     best = Params()
-    _check(_lib().fge_autotune(I.data_ptr(), alpha.data_ptr(), W, H, ctypes.byref(p), F.data_ptr(),
+    _check(_lib().fge_autotune(I.data_ptr(), alpha.data_ptr(), H, W, ctypes.byref(p), F.data_ptr(),
                                B.data_ptr(), ws.data_ptr(), ws.numel(), _stream_ptr(stream), reps,
                                ctypes.byref(best), buf, nc, ctypes.byref(n)), "fge_autotune")
     ent = _entries(buf, n.value)
@@ -601,23 +629,24 @@ def autotune(I, alpha, params: Params | None = None, reps: int = 3, stream=None,
     return best, ent
 
 
-def autotune_batch(sizes, Is, alphas, params: Params | None = None, reps: int = 3, stream=None,
+@_on_stream
+def autotune_batch(shapes, Is, alphas, params: Params | None = None, reps: int = 3, stream=None,
                    cache_path: str | None = None):
-    """The same search for a batch of sizes [(W, H), ...] (fge_batch_autotune)."""
+    """The same search for a batch of shapes [(H, W), ...] (fge_batch_autotune)."""
     import torch
     p = params if params is not None else default_params()
-    sizes = [(int(w), int(h)) for w, h in sizes]
-    key = _tune_key("batch", p, sizes)
+    shapes = [(int(h), int(w)) for h, w in shapes]
+    key = _tune_key("batch", p, shapes)
     hit = _cache_get(cache_path, key)
     if hit is not None:
         return _tuned(p, hit["strip_rows"], hit["tile_max_px"]), hit.get("entries", [])
-    n = len(sizes)
-    W = (ctypes.c_int32 * n)(*[w for w, _ in sizes])
-    H = (ctypes.c_int32 * n)(*[h for _, h in sizes])
+    n = len(shapes)
+    H = (ctypes.c_int32 * n)(*[h for h, _ in shapes])
+    W = (ctypes.c_int32 * n)(*[w for _, w in shapes])
     dt = storage_dtype(p)
-    Fs = [torch.empty((3, h, w), dtype=dt, device=Is[0].device) for w, h in sizes]
+    Fs = [torch.empty((3, h, w), dtype=dt, device=Is[0].device) for h, w in shapes]
     Bs = [torch.empty_like(f) for f in Fs]
-    need = _lib().fge_batch_tune_workspace_bytes(n, W, H, ctypes.byref(p))
+    need = _lib().fge_batch_tune_workspace_bytes(n, H, W, ctypes.byref(p))
     if need == 0:
         raise FgeError(FGE_EINVAL, "fge_batch_tune_workspace_bytes")
     ws = torch.empty(need, dtype=torch.uint8, device=Is[0].device)
@@ -625,7 +654,7 @@ def autotune_batch(sizes, Is, alphas, params: Params | None = None, reps: int = 
     buf = (TuneEntry * nc)()
     cnt = ctypes.c_int32()
     best = Params()
-    _check(_lib().fge_batch_autotune(n, _ptr_array(Is), _ptr_array(alphas), W, H, ctypes.byref(p),
+    _check(_lib().fge_batch_autotune(n, _ptr_array(Is), _ptr_array(alphas), H, W, ctypes.byref(p),
                                      _ptr_array(Fs), _ptr_array(Bs), ws.data_ptr(), ws.numel(),
                                      _stream_ptr(stream), reps, ctypes.byref(best), buf, nc,
                                      ctypes.byref(cnt)), "fge_batch_autotune")
@@ -650,6 +679,7 @@ def _torch_dtype(code):
     return {F32: torch.float32, F16: torch.float16, U8: torch.uint8}[code]
 
 
+@_on_stream
 def energy(I, alpha, F, B, params: Params | None = None, stream=None, out=None):
     """Energy E of (F, B) and the compositing residual, reduced on the device (fge_energy).
     Returns a float64 CUDA tensor of 6: E, data term, smoothness term, mean and max |residual|
@@ -664,13 +694,14 @@ def energy(I, alpha, F, B, params: Params | None = None, stream=None, out=None):
             raise ValueError(f"{name} must be a contiguous CUDA tensor {shp} of dtype {dt}")
     if out is None:
         out = torch.empty(6, dtype=torch.float64, device=I.device)
-    ws = torch.empty(_lib().fge_energy_workspace_bytes(W, H), dtype=torch.uint8, device=I.device)
-    _check(_lib().fge_energy(I.data_ptr(), alpha.data_ptr(), F.data_ptr(), B.data_ptr(), W, H,
+    ws = torch.empty(_lib().fge_energy_workspace_bytes(H, W), dtype=torch.uint8, device=I.device)
+    _check(_lib().fge_energy(I.data_ptr(), alpha.data_ptr(), F.data_ptr(), B.data_ptr(), H, W,
                              ctypes.byref(p), out.data_ptr(), ws.data_ptr(), ws.numel(),
                              _stream_ptr(stream)), "fge_energy")
     return out
 
 
+@_on_stream
 def hwc_to_planar(img, dtype=None, stream=None):
     """(H, W, 3|4) CUDA tensor (uint8, float32 or float16) -> (I (3, H, W), alpha (H, W) or None)
     in `dtype` (default float32); uint8 maps to v / 255 (fge_hwc_to_planar)."""
@@ -681,12 +712,13 @@ def hwc_to_planar(img, dtype=None, stream=None):
     H, W, C = img.shape
     I = torch.empty((3, H, W), dtype=dtype, device=img.device)
     a = torch.empty((H, W), dtype=dtype, device=img.device) if C == 4 else None
-    _check(_lib().fge_hwc_to_planar(img.data_ptr(), _dtype_code(img.dtype), C, W, H, I.data_ptr(),
+    _check(_lib().fge_hwc_to_planar(img.data_ptr(), _dtype_code(img.dtype), C, H, W, I.data_ptr(),
                                     a.data_ptr() if a is not None else None, _dtype_code(dtype),
                                     _stream_ptr(stream)), "fge_hwc_to_planar")
     return I, a
 
 
+@_on_stream
 def planar_to_hwc(planes, dtype=None, stream=None):
     """(3, H, W) CUDA tensor -> (H, W, 3) in `dtype` (default uint8: round(clamp(v) * 255))."""
     import torch
@@ -695,12 +727,13 @@ def planar_to_hwc(planes, dtype=None, stream=None):
         raise ValueError("planes must be a contiguous CUDA tensor (3, H, W)")
     _, H, W = planes.shape
     out = torch.empty((H, W, 3), dtype=dtype, device=planes.device)
-    _check(_lib().fge_planar_to_hwc(planes.data_ptr(), _dtype_code(planes.dtype), W, H,
+    _check(_lib().fge_planar_to_hwc(planes.data_ptr(), _dtype_code(planes.dtype), H, W,
                                     out.data_ptr(), _dtype_code(dtype), _stream_ptr(stream)),
            "fge_planar_to_hwc")
     return out
 
 
+@_on_stream
 def estimate_foreground_converge(I, alpha, params: Params | None = None, tol: float = 1e-4,
                                  max_sweeps: int = 100, F=None, B=None, stream=None):
     """Algorithm 1's "while not converged" level loop on the device (fge_estimate_foreground_converge):
@@ -720,17 +753,18 @@ def estimate_foreground_converge(I, alpha, params: Params | None = None, tol: fl
         F = torch.empty((3, H, W), dtype=dt, device=I.device)
     if B is None:
         B = torch.empty((3, H, W), dtype=dt, device=I.device)
-    n = num_levels(W, H)
+    n = num_levels(H, W)
     sweeps = torch.zeros(max(1, n), dtype=torch.int32, device=I.device)
-    need = _lib().fge_converge_workspace_bytes(W, H, ctypes.byref(p))
+    need = _lib().fge_converge_workspace_bytes(H, W, ctypes.byref(p))
     ws = torch.empty(max(1, need), dtype=torch.uint8, device=I.device)
     _check(_lib().fge_estimate_foreground_converge(
-        I.data_ptr(), alpha.data_ptr(), W, H, ctypes.byref(p), float(tol), int(max_sweeps),
+        I.data_ptr(), alpha.data_ptr(), H, W, ctypes.byref(p), float(tol), int(max_sweeps),
         F.data_ptr(), B.data_ptr(), sweeps.data_ptr(), ws.data_ptr(), ws.numel(),
         _stream_ptr(stream)), "fge_estimate_foreground_converge")
     return F, B, sweeps[:n]
 
 
+@_on_stream
 def quality(F, G, alpha, sigma: float = 1.4, stream=None, out=None):
     """The paper's error measures of F against the reference G over the translucent pixels of
     `alpha`, weighted by alpha (fge_quality): a float64 CUDA tensor [SAD, MSE, GRAD, count]."""
@@ -743,13 +777,14 @@ def quality(F, G, alpha, sigma: float = 1.4, stream=None, out=None):
             raise ValueError(f"{name} must be a contiguous CUDA tensor {shp} of dtype {F.dtype}")
     if out is None:
         out = torch.empty(4, dtype=torch.float64, device=F.device)
-    ws = torch.empty(_lib().fge_quality_workspace_bytes(W, H), dtype=torch.uint8, device=F.device)
-    _check(_lib().fge_quality(F.data_ptr(), G.data_ptr(), alpha.data_ptr(), W, H,
+    ws = torch.empty(_lib().fge_quality_workspace_bytes(H, W), dtype=torch.uint8, device=F.device)
+    _check(_lib().fge_quality(F.data_ptr(), G.data_ptr(), alpha.data_ptr(), H, W,
                               _dtype_code(F.dtype), float(sigma), out.data_ptr(), ws.data_ptr(),
                               ws.numel(), _stream_ptr(stream)), "fge_quality")
     return out
 
 
+@_on_stream
 def composite(F, alpha, B, stream=None):
     """alpha F + (1 - alpha) B on the device (fge_composite)."""
     import torch
@@ -760,7 +795,7 @@ def composite(F, alpha, B, stream=None):
         if tuple(t.shape) != shp or t.dtype != F.dtype or not t.is_cuda or not t.is_contiguous():
             raise ValueError(f"{name} must be a contiguous CUDA tensor {shp} of dtype {F.dtype}")
     C = torch.empty_like(F)
-    _check(_lib().fge_composite(F.data_ptr(), alpha.data_ptr(), B.data_ptr(), W, H,
+    _check(_lib().fge_composite(F.data_ptr(), alpha.data_ptr(), B.data_ptr(), H, W,
                                 _dtype_code(F.dtype), C.data_ptr(), _stream_ptr(stream)),
            "fge_composite")
     return C
@@ -775,6 +810,7 @@ def level_options(resize: str = "smooth", tol: float = -1.0, max_sweeps: int = 1
     return o
 
 
+@_on_stream
 def estimate_foreground_levels(I, alpha, params: Params | None = None, resize: str = "smooth",
                                tol: float = -1.0, max_sweeps: int = 100, F=None, B=None,
                                stream=None):
@@ -795,12 +831,12 @@ def estimate_foreground_levels(I, alpha, params: Params | None = None, resize: s
         F = torch.empty((3, H, W), dtype=dt, device=I.device)
     if B is None:
         B = torch.empty((3, H, W), dtype=dt, device=I.device)
-    n = num_levels(W, H)
+    n = num_levels(H, W)
     sweeps = torch.zeros(max(1, n), dtype=torch.int32, device=I.device)
-    need = _lib().fge_levels_workspace_bytes(W, H, ctypes.byref(p), ctypes.byref(o))
+    need = _lib().fge_levels_workspace_bytes(H, W, ctypes.byref(p), ctypes.byref(o))
     ws = torch.empty(max(1, need), dtype=torch.uint8, device=I.device)
     _check(_lib().fge_estimate_foreground_levels(
-        I.data_ptr(), alpha.data_ptr(), W, H, ctypes.byref(p), ctypes.byref(o), F.data_ptr(),
+        I.data_ptr(), alpha.data_ptr(), H, W, ctypes.byref(p), ctypes.byref(o), F.data_ptr(),
         B.data_ptr(), sweeps.data_ptr(), ws.data_ptr(), ws.numel(), _stream_ptr(stream)),
         "fge_estimate_foreground_levels")
     return F, B, sweeps[:n]

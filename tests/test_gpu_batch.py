@@ -57,7 +57,7 @@ def test_pyramid_bit_identical_to_per_level_tiles(gpu, storage):
         s = synth.smooth(w, h, seed=950 + k)
         Is, As = inputs(torch, fge, [s], p)
         F1, B1 = single(torch, fge, Is[0], As[0], p)
-        b = fge.Batch([(w, h)], p)
+        b = fge.Batch([(h, w)], p)
         Fs, Bs = b.run(Is, As)
         torch.cuda.synchronize()
         assert torch.equal(Fs[0], F1) and torch.equal(Bs[0], B1), (w, h)
@@ -76,7 +76,7 @@ def test_batch_bit_identical_to_single(gpu, storage):
     samples = [synth.strands(w, h, seed=60 + i, n_strands=max(1, w * h // 3000))
                for i, (w, h) in enumerate(SIZES)]
     Is, As = inputs(torch, fge, samples, p)
-    b = fge.Batch(SIZES, p)
+    b = fge.Batch([(h, w) for w, h in SIZES], p)
     Fs, Bs = b.run(Is, As)
     torch.cuda.synchronize()
     for i in range(len(SIZES)):
@@ -98,7 +98,7 @@ def test_batch_run_twice_reuses_plan(gpu):
     sizes = SIZES[:6]
     samples = [synth.smooth(w, h, seed=80 + i) for i, (w, h) in enumerate(sizes)]
     Is, As = inputs(torch, fge, samples, p)
-    b = fge.Batch(sizes, p)
+    b = fge.Batch([(h, w) for w, h in sizes], p)
     Fs1, Bs1 = b.run(Is, As)
     Is2 = [I.flip(-1).contiguous() for I in Is]
     Fs2, Bs2 = b.run(Is2, As)
@@ -119,7 +119,7 @@ def test_batch_graph_replays(gpu):
     sizes = [(300, 200), (129, 300), (700, 421), (64, 37)]
     samples = [synth.smooth(w, h, seed=90 + i) for i, (w, h) in enumerate(sizes)]
     Is, As = inputs(torch, fge, samples, p)
-    b = fge.Batch(sizes, p)
+    b = fge.Batch([(h, w) for w, h in sizes], p)
     ref = b.run(Is, As)
     torch.cuda.synchronize()
     ref = ([F.clone() for F in ref[0]], [B.clone() for B in ref[1]])
@@ -149,7 +149,7 @@ def test_uneven_batch_workload_f16(gpu):
     sizes = synth.batch_sizes()
     samples = [synth.batch_image(i, w, h) for i, (w, h) in enumerate(sizes)]
     Is, As = inputs(torch, fge, samples, p)
-    b = fge.Batch(sizes, p)
+    b = fge.Batch([(h, w) for w, h in sizes], p)
     Fs, Bs = b.run(Is, As)
     torch.cuda.synchronize()
     order = sorted(range(len(sizes)), key=lambda i: sizes[i][0] * sizes[i][1])
@@ -166,4 +166,36 @@ def test_uneven_batch_workload_f16(gpu):
         worst = max(worst, err)
         assert err <= TOL["f16"], (i, sizes[i], err)
     print(f"64 batch images: worst f16 max-abs vs oracle {worst:.2e}")
+    b.close()
+
+
+def test_batch_recapture_waits_for_queued_replays(gpu):
+    """Capture, queue replays, re-capture the same plan with other buffers at once (the new
+    capture refills the pinned table buffer the first graph's upload reads), replay the new
+    graph: both graphs' results must be bit-identical to eager runs of their own inputs."""
+    torch, fge = gpu
+    p = fge.default_params(storage=fge.F16)
+    sizes = [(300, 200), (129, 300), (700, 421)]
+    shapes = [(h, w) for w, h in sizes]
+    sa = [synth.smooth(w, h, seed=300 + i) for i, (w, h) in enumerate(sizes)]
+    sb = [synth.smooth(w, h, seed=400 + i) for i, (w, h) in enumerate(sizes)]
+    Ia, Aa = inputs(torch, fge, sa, p)
+    Ib, Ab = inputs(torch, fge, sb, p)
+    b = fge.Batch(shapes, p)
+    ws_a = torch.empty(b.workspace_bytes, dtype=torch.uint8, device="cuda")
+    ws_b = torch.empty(b.workspace_bytes, dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        Fa, Ba = b.capture(Ia, Aa, workspace=ws_a, stream=stream)
+        for _ in range(3):
+            b.replay(stream)
+        Fb, Bb = b.capture(Ib, Ab, workspace=ws_b, stream=stream)
+        b.replay(stream)
+    stream.synchronize()
+    for i in range(len(sizes)):
+        F1, B1 = single(torch, fge, Ia[i], Aa[i], p)
+        F2, B2 = single(torch, fge, Ib[i], Ab[i], p)
+        torch.cuda.synchronize()
+        assert torch.equal(Fa[i], F1) and torch.equal(Ba[i], B1), ("first graph", i)
+        assert torch.equal(Fb[i], F2) and torch.equal(Bb[i], B2), ("second graph", i)
     b.close()

@@ -85,7 +85,7 @@ def test_converge_limits_and_fixed_form(gpu):
     p = fge.default_params()
     s = synth.smooth(200, 150, seed=5)
     I, a = to_dev(torch, fge, p, s)
-    n = fge.num_levels(200, 150)
+    n = fge.num_levels(150, 200)
     F, B, sw = fge.estimate_foreground_converge(I, a, p, tol=1.0, max_sweeps=50)
     torch.cuda.synchronize()
     assert sw.cpu().tolist() == [1] * n

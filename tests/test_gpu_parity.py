@@ -258,3 +258,66 @@ def test_paired_input_path_odd_width(gpu, storage):
         F, B = run(gpu, s.I, s.alpha, storage=fge.F16 if storage == "f16" else fge.F32)
         err = max(maxabs(F, Fo), maxabs(B, Bo))
         assert err <= TOL[storage], (W, H, err)
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_raw_abi_non_square_height_first(gpu, storage):
+    """The C symbol called through ctypes directly (not the Python wrapper), with a non-square
+    image whose sizes are passed in the ABI's (H, W) order: 301 rows of 700 pixels.  A caller
+    that swapped them would get a transposed plan; the result must match the oracle."""
+    import ctypes
+    torch, fge = gpu
+    H, W = 301, 700
+    s = synth.smooth(W, H, seed=4242)
+    assert s.I.shape == (3, H, W)
+    Fo, Bo = oracle.ml(s.I, s.alpha)
+    p = fge.default_params(storage=fge.F16 if storage == "f16" else fge.F32)
+    dt = fge.storage_dtype(p)
+    It = torch.from_numpy(np.ascontiguousarray(s.I)).to(dt).cuda()
+    at = torch.from_numpy(np.ascontiguousarray(s.alpha)).to(dt).cuda()
+    F = torch.empty((3, H, W), dtype=dt, device="cuda")
+    B = torch.empty_like(F)
+    lib = ctypes.CDLL(fge.LIB_PATH)
+    lib.fge_workspace_bytes.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p]
+    lib.fge_workspace_bytes.restype = ctypes.c_size_t
+    lib.fge_estimate_foreground.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                            ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                            ctypes.c_void_p]
+    lib.fge_estimate_foreground.restype = ctypes.c_int
+    need = lib.fge_workspace_bytes(H, W, ctypes.addressof(p))
+    ws = torch.empty(max(1, need), dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream().cuda_stream
+    st = lib.fge_estimate_foreground(It.data_ptr(), at.data_ptr(), H, W, ctypes.addressof(p),
+                                     F.data_ptr(), B.data_ptr(), ws.data_ptr(), need, stream)
+    assert st == 0, st
+    torch.cuda.synchronize()
+    err = max(maxabs(F.double().cpu().numpy(), Fo), maxabs(B.double().cpu().numpy(), Bo))
+    print(f"raw ABI {H}x{W} {storage}: max-abs vs oracle {err:.3e}")
+    assert err <= TOL[storage]
+
+
+def test_side_stream_scratch_survives_default_stream_allocations(gpu):
+    """estimate_foreground on a side stream with a library-allocated workspace: after the call
+    returns, memory freed and reallocated on the default stream must not reuse the workspace
+    while the side stream still runs (the binding marks it in use by that stream)."""
+    torch, fge = gpu
+    s = sample_of("c2")
+    Fo, Bo = oracle_of("c2")
+    p = fge.default_params()
+    It = torch.from_numpy(np.ascontiguousarray(s.I)).float().cuda()
+    at = torch.from_numpy(np.ascontiguousarray(s.alpha)).float().cuda()
+    side = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    # keep the side stream busy first so the estimation is still queued when the scratch is freed
+    with torch.cuda.stream(side):
+        busy = torch.randn(1 << 24, device="cuda")
+        for _ in range(20):
+            busy = busy * 1.0000001 + 0.5
+    F, B = fge.estimate_foreground(It, at, p, stream=side)
+    junk = [torch.full((1 << 22,), 7.0, device="cuda") for _ in range(8)]   # default stream
+    side.synchronize()
+    torch.cuda.synchronize()
+    err = max(maxabs(F.double().cpu().numpy(), Fo), maxabs(B.double().cpu().numpy(), Bo))
+    assert err <= TOL["f32"], err
+    del junk, busy

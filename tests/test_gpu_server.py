@@ -150,7 +150,7 @@ def test_budget_admission(gpu):
     sizes = SIZES[:10]
     inputs = make_inputs(torch, fge, p, sizes, seed0=6200)
     ref = alone(torch, fge, p, inputs)
-    fp = sorted(fge.server_request_bytes(w, h, p) for w, h in sizes)
+    fp = sorted(fge.server_request_bytes(h, w, p) for w, h in sizes)
     budget = fp[-1] + fp[-2] + 4096
     srv = new_server(torch, fge, p, budget_bytes=budget)
     served = [srv.submit(k, I, a) for k, (I, a) in enumerate(inputs)]
@@ -188,7 +188,7 @@ def test_reuse_after_drain_and_rejections(gpu):
     p = fge.default_params(storage=fge.F16)
     inputs = make_inputs(torch, fge, p, [(500, 400), (200, 100)], seed0=6400)
     ref = alone(torch, fge, p, inputs)
-    budget = fge.server_request_bytes(500, 400, p)
+    budget = fge.server_request_bytes(400, 500, p)
     srv = new_server(torch, fge, p, arena_gb=0.25, budget_bytes=budget)
     for rnd in range(3):   # the arena and the slots are reused across drains
         served = [srv.submit(10 * rnd + k, I, a) for k, (I, a) in enumerate(inputs)]

@@ -55,9 +55,9 @@ def test_autotune_batch_matches_single(gpu):
     torch.cuda.synchronize()
     Is = [x[0] for x in imgs]
     As = [x[1] for x in imgs]
-    best, ent = fge.autotune_batch(sizes, Is, As, p, reps=2)
+    best, ent = fge.autotune_batch([(h, w) for w, h in sizes], Is, As, p, reps=2)
     assert len(ent) == 21 and all(e["status"] == 0 for e in ent)
-    b = fge.Batch(sizes, best)
+    b = fge.Batch([(h, w) for w, h in sizes], best)
     Fs, Bs = b.run(Is, As)
     torch.cuda.synchronize()
     for (I, a), F, B in zip(imgs, Fs, Bs):
