@@ -102,8 +102,8 @@ void fge_default_params(fge_params *p);
 /* Human-readable name of a status code (static string). */
 const char *fge_status_string(int status);
 
-/* Library ABI version (increments when fge_params or a signature changes); this header is 4
- * (4 moved every size argument to height-first order). */
+/* Library ABI version (increments when fge_params or a signature changes); this header is 5
+ * (4 moved every size argument to height-first order, 5 added fge_estimate_foreground_noalloc). */
 int32_t fge_version(void);
 
 /* ---- host-only planning (no GPU needed) ---------------------------------------------- */
@@ -139,6 +139,23 @@ size_t fge_workspace_bytes(int32_t H, int32_t W, const fge_params *p);
 fge_status fge_estimate_foreground(const void *I, const void *alpha, int32_t H, int32_t W,
                                    const fge_params *p, void *F, void *B, void *workspace,
                                    size_t workspace_bytes, void *stream);
+
+/* The same computation as fge_estimate_foreground with no workspace argument, for callers that
+ * cannot allocate device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid allocation).  The workspace is a file-scope device array of
+ * FGE_NOALLOC_SCRATCH_BYTES bytes inside the library, one per device, held from the first call on
+ * that device until the process ends; the call allocates nothing, host or device.  It runs on
+ * the device current at the call (which must be `stream`'s device).  Results are bit-identical
+ * to fge_estimate_foreground's under the same parameters.  Inputs whose fge_workspace_bytes
+ * exceeds FGE_NOALLOC_SCRATCH_BYTES are rejected with FGE_EWORKSPACE (at a 4:3 aspect that
+ * admits images up to about 8.3 MP in float32 and 15.6 MP in binary16 storage: 4096 x 3072 fits
+ * in binary16 only);
+ * order FGE_JACOBI is FGE_EUNSUPPORTED.  Every call on a device shares that device's array and
+ * leaves its contents behind: calls that overlap in time on one device (different streams, or
+ * threads whose launches are not ordered) race and give undefined results. */
+#define FGE_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+fge_status fge_estimate_foreground_noalloc(const void *I, const void *alpha, int32_t H, int32_t W,
+                                           const fge_params *p, void *F, void *B, void *stream);
 
 /* Algorithm 1's level loop in its "while not converged" form: at every level, after the resize,
  * sweep (in p->order) until the level's energy -- fge_energy's quadratic on the level's F, B

@@ -10,7 +10,7 @@
 
 namespace {
 
-constexpr int32_t kAbiVersion = 4;
+constexpr int32_t kAbiVersion = 5;
 
 struct ProfileRecord {
     int level;          // 0 = finest
@@ -46,6 +46,86 @@ struct LaunchTimer {
         if (rec) (void)hipEventRecord(rec->stop, s);
     }
 };
+
+// The launch sequence of Algorithm 1's levels for one image under `plan`, with the workspace at
+// `ws` (plan.ws_bytes bytes, 256-byte aligned), on stream `s`.
+fge_status run_single(const fge::Plan &plan, const fge_params &prm, const void *I, const void *alpha,
+                      void *F, void *B, char *ws, hipStream_t s) {
+    const int n = plan.n;
+    if (plan.ng > 0 && !plan.gather_in_coarse) {
+        LaunchTimer timer(n, s);   // recorded under index n_levels
+        if (fge::launch_gather(plan, I, alpha, fge::pyr_base(plan, ws, F), prm.storage, s))
+            return FGE_EHIP;
+    }
+    if (plan.nc > 0) {
+        void *fo, *bo;
+        fge::level_state(plan, ws, plan.nc - 1, F, B, &fo, &bo);
+        const fge::LevelSrc src = fge::coarse_src(plan, ws, F, I, alpha);
+        LaunchTimer timer(n - plan.nc, s);
+        const int err = plan.gather_in_coarse
+                            ? fge::launch_coarse_gather(plan, src, fo, bo, prm.omega, prm.eps_r, I,
+                                                        alpha, fge::pyr_base(plan, ws, F),
+                                                        prm.storage, s)
+                            : fge::launch_coarse(plan, src, fo, bo, prm.omega, prm.eps_r,
+                                                 prm.storage, s);
+        if (err) return FGE_EHIP;
+    }
+    for (int i = plan.nc; i < n; ++i) {
+        if (i == plan.pyr_first) {   // the run of tile levels in one launch
+            LaunchTimer timer(n - 1 - plan.pyr_last, s);   // recorded under the run's last level
+            if (fge::launch_pyramid(plan, ws, I, alpha, F, B, prm.omega, prm.eps_r, prm.storage, s))
+                return FGE_EHIP;
+            i = plan.pyr_last;
+            continue;
+        }
+        const fge::LevelIO io = fge::level_io(plan, ws, i, I, alpha, F, B, prm.omega, prm.eps_r);
+        LaunchTimer timer(n - 1 - i, s);
+        int err = 0;
+        switch (plan.kind[i]) {
+            case fge::kKindStream: err = fge::launch_fine_fused(io, prm.strip_rows, prm.storage, s); break;
+            case fge::kKindTile: err = fge::launch_fine_tile(io, prm.storage, s); break;
+            default: err = fge::launch_naive_level(io, plan.lv[i].iters, prm.storage, s); break;
+        }
+        if (err) return FGE_EHIP;
+    }
+    return FGE_OK;
+}
+
+// ---- the allocation-free single-image call -----------------------------------------------
+//
+// fge_estimate_foreground_noalloc keeps the single-image workspace in this file-scope device
+// array instead of a caller buffer.  In host code `scratch` names a host-side stand-in, not device
+// memory: its device address is looked up once per device with hipGetSymbolAddress (each device
+// holds its own copy of the array) and only that address is passed to kernels.
+constexpr size_t kScratchBytes = FGE_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+
+struct ScratchTable {
+    std::mutex mu;
+    void *ptr[kMaxDevices] = {};
+};
+
+ScratchTable &scratch_table() {
+    static ScratchTable t;
+    return t;
+}
+
+// The device address of `scratch` on the current device (looked up on the first call there).
+fge_status scratch_on_current_device(char **out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return FGE_EHIP;
+    ScratchTable &t = scratch_table();
+    std::lock_guard<std::mutex> g(t.mu);
+    if (!t.ptr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return FGE_EHIP;
+        t.ptr[dev] = p;
+    }
+    *out = static_cast<char *>(t.ptr[dev]);
+    return FGE_OK;
+}
 
 const fge_params &resolve(const fge_params *p, fge_params &tmp) {
     if (p) return *p;
@@ -145,46 +225,25 @@ fge_status fge_estimate_foreground(const void *I, const void *alpha, int32_t H, 
     if (plan.ws_bytes > 0 && (!workspace || workspace_bytes < plan.ws_bytes)) return FGE_EWORKSPACE;
     if (workspace && (reinterpret_cast<uintptr_t>(workspace) & 255)) return FGE_EWORKSPACE;
 
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    char *ws = static_cast<char *>(workspace);
-    const int n = plan.n;
-    if (plan.ng > 0 && !plan.gather_in_coarse) {
-        LaunchTimer timer(n, s);   // recorded under index n_levels
-        if (fge::launch_gather(plan, I, alpha, fge::pyr_base(plan, ws, F), prm.storage, s))
-            return FGE_EHIP;
-    }
-    if (plan.nc > 0) {
-        void *fo, *bo;
-        fge::level_state(plan, ws, plan.nc - 1, F, B, &fo, &bo);
-        const fge::LevelSrc src = fge::coarse_src(plan, ws, F, I, alpha);
-        LaunchTimer timer(n - plan.nc, s);
-        const int err = plan.gather_in_coarse
-                            ? fge::launch_coarse_gather(plan, src, fo, bo, prm.omega, prm.eps_r, I,
-                                                        alpha, fge::pyr_base(plan, ws, F),
-                                                        prm.storage, s)
-                            : fge::launch_coarse(plan, src, fo, bo, prm.omega, prm.eps_r,
-                                                 prm.storage, s);
-        if (err) return FGE_EHIP;
-    }
-    for (int i = plan.nc; i < n; ++i) {
-        if (i == plan.pyr_first) {   // the run of tile levels in one launch
-            LaunchTimer timer(n - 1 - plan.pyr_last, s);   // recorded under the run's last level
-            if (fge::launch_pyramid(plan, ws, I, alpha, F, B, prm.omega, prm.eps_r, prm.storage, s))
-                return FGE_EHIP;
-            i = plan.pyr_last;
-            continue;
-        }
-        const fge::LevelIO io = fge::level_io(plan, ws, i, I, alpha, F, B, prm.omega, prm.eps_r);
-        LaunchTimer timer(n - 1 - i, s);
-        int err = 0;
-        switch (plan.kind[i]) {
-            case fge::kKindStream: err = fge::launch_fine_fused(io, prm.strip_rows, prm.storage, s); break;
-            case fge::kKindTile: err = fge::launch_fine_tile(io, prm.storage, s); break;
-            default: err = fge::launch_naive_level(io, plan.lv[i].iters, prm.storage, s); break;
-        }
-        if (err) return FGE_EHIP;
-    }
-    return FGE_OK;
+    return run_single(plan, prm, I, alpha, F, B, static_cast<char *>(workspace),
+                      static_cast<hipStream_t>(stream));
+}
+
+fge_status fge_estimate_foreground_noalloc(const void *I, const void *alpha, int32_t H, int32_t W,
+                                           const fge_params *p, void *F, void *B, void *stream) {
+    fge_params tmp;
+    const fge_params &prm = resolve(p, tmp);
+    fge::Plan plan;
+    const fge_status st = fge::make_plan(W, H, prm, &plan, fge::kPlanSingle);
+    if (st != FGE_OK) return st;
+    if (prm.order == FGE_JACOBI) return FGE_EUNSUPPORTED;   // the per-level path's workspace
+    if (!I || !alpha || !F || !B) return FGE_EINVAL;
+    if (plan.ws_bytes > kScratchBytes) return FGE_EWORKSPACE;
+    char *ws = nullptr;
+    const fge_status sst = scratch_on_current_device(&ws);
+    if (sst != FGE_OK) return sst;
+    if (fge::outputs_alias(I, alpha, F, B, W, H, plan.elem, ws, plan.ws_bytes)) return FGE_EINVAL;
+    return run_single(plan, prm, I, alpha, F, B, ws, static_cast<hipStream_t>(stream));
 }
 
 fge_status fge_profile_start(int32_t capacity) {
