@@ -15,6 +15,9 @@ builds that file and marshals numpy arrays to it.  Functions and the paper passa
 * :func:`ml` -- Algorithm 1 end to end.
 * :func:`energy` -- the global quadratic energy whose stationarity conditions are eq. 9.
 
+The module :mod:`oracle.closed_form` (NumPy / SciPy) is the minimiser of the global closed-form
+cost of Section III-B (eq. 2, with the eps regulariser of Section III-C) by a sparse direct solve.
+
 Layout everywhere: ``I``, ``F``, ``B`` are float64 arrays of shape (3, H, W) (planar RGB), the
 matte is (H, W).
 """
