@@ -13,9 +13,9 @@
  *     full-resolution image and matte and of the previous level's F and B to every level, and a
  *     fixed number of sweeps per level (10 when the level is at most 32x32, else 2; Section III-D
  *     text before Algorithm 1).
- *   - The per-pixel update of Algorithm 1's inner loop: the 2x2 system of eq. 9 built from the
- *     compositing data term (eq. 1) and the four clamped neighbours with weights
- *     eps_r + omega |alpha_i - alpha_j| (eq. 3), solved by Cramer's rule, then clamped to [0, 1].
+ *   - The per-pixel update: the 2x2 system of eq. 9 in its matrix form (data term of eq. 1 plus
+ *     the neighbour sums with weights eps_r + omega |alpha_i - alpha_j| of eq. 3 over the four
+ *     clamped neighbours), solved by Cramer's rule, then clamped to [0, 1].
  *   - The global quadratic energy whose stationarity conditions are the per-pixel equations.
  *
  * Readings where the paper is silent (each is listed with its reason in the design notes):
@@ -90,10 +90,12 @@ static int clampi(int v, int lo, int hi)
  * Solve the per-pixel system of eq. 9 for pixel (x, y), reading F and B from (Fs, Bs) and the
  * input I and matte a, and return the clamped solution in fout[3], bout[3].
  *
- * Following Algorithm 1's inner loop: U = [a, 1 - a]^T, A = U U^T, b_c = U I_c; every clamped
- * neighbour j adds Delta = eps + omega |a_i - a_j| to both diagonal entries of A and Delta F_j,
- * Delta B_j to the two rows of b_c; then g_c = A^{-1} b_c (Cramer's rule) and both components are
- * clamped to [0, 1].
+ * Eq. 9 in matrix form: with U = [a_i, 1 - a_i]^T, the weights s_j = eps + omega |a_i - a_j| of
+ * the four clamped neighbours (eq. 3), S = sum_j s_j, P_c = sum_j s_j F_j^c and
+ * Q_c = sum_j s_j B_j^c, the unknown g_c = (F_i^c, B_i^c) solves
+ *     (U U^T + S Id) g_c = U I_i^c + (P_c, Q_c)^T,
+ * the same 2x2 matrix for the three channels.  It is solved by Cramer's rule, and each component
+ * is then clamped to [0, 1] (the clamp that follows the solve in Algorithm 1).
  */
 static void solve_pixel(const double *Fs, const double *Bs, const double *I, const double *a,
                         int w, int h, int x, int y, double omega, double eps,
@@ -101,37 +103,30 @@ static void solve_pixel(const double *Fs, const double *Bs, const double *I, con
 {
     const size_t plane = (size_t)w * h;
     const size_t i = (size_t)y * w + x;
-    const double ai = a[i];
-    const double u0 = ai, u1 = 1.0 - ai;
+    const double u0 = a[i], u1 = 1.0 - a[i];
 
-    double A00 = u0 * u0, A01 = u0 * u1, A11 = u1 * u1;
-    double b0[3], b1[3];
-    for (int c = 0; c < 3; c++) {
-        b0[c] = u0 * I[c * plane + i];
-        b1[c] = u1 * I[c * plane + i];
-    }
-
-    const int dx[4] = {-1, 1, 0, 0};
-    const int dy[4] = {0, 0, -1, 1};
+    /* neighbour sums: left, right, up, down, each coordinate clamped to the image */
+    const int nx[4] = {clampi(x - 1, 0, w - 1), clampi(x + 1, 0, w - 1), x, x};
+    const int ny[4] = {y, y, clampi(y - 1, 0, h - 1), clampi(y + 1, 0, h - 1)};
+    double S = 0.0, P[3] = {0.0, 0.0, 0.0}, Q[3] = {0.0, 0.0, 0.0};
     for (int k = 0; k < 4; k++) {
-        int xj = clampi(x + dx[k], 0, w - 1);
-        int yj = clampi(y + dy[k], 0, h - 1);
-        size_t j = (size_t)yj * w + xj;
-        double d = eps + omega * fabs(ai - a[j]);
-        A00 += d;
-        A11 += d;
+        const size_t j = (size_t)ny[k] * w + nx[k];
+        const double s = eps + omega * fabs(u0 - a[j]);
+        S += s;
         for (int c = 0; c < 3; c++) {
-            b0[c] += d * Fs[c * plane + j];
-            b1[c] += d * Bs[c * plane + j];
+            P[c] += s * Fs[c * plane + j];
+            Q[c] += s * Bs[c * plane + j];
         }
     }
 
-    double det = A00 * A11 - A01 * A01;
+    /* M = U U^T + S Id */
+    const double m00 = u0 * u0 + S, m01 = u0 * u1, m11 = u1 * u1 + S;
+    const double det = m00 * m11 - m01 * m01;
     for (int c = 0; c < 3; c++) {
-        double f = (A11 * b0[c] - A01 * b1[c]) / det;
-        double g = (A00 * b1[c] - A01 * b0[c]) / det;
-        fout[c] = clamp01(f);
-        bout[c] = clamp01(g);
+        const double r0 = u0 * I[c * plane + i] + P[c];
+        const double r1 = u1 * I[c * plane + i] + Q[c];
+        fout[c] = clamp01((m11 * r0 - m01 * r1) / det);
+        bout[c] = clamp01((m00 * r1 - m01 * r0) / det);
     }
 }
 
