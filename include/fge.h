@@ -59,8 +59,8 @@ typedef enum fge_status {
 } fge_status;
 
 /* Element types.  F32 and F16 are storage types of the estimator; U8 (values 0..255 standing
- * for [0, 1]) appears only in the layout conversions below. */
-typedef enum fge_dtype { FGE_F32 = 0, FGE_F16 = 1, FGE_U8 = 2 } fge_dtype;
+ * for [0, 1]) appears only in the layout conversions below; F64 only in the closed-form solve. */
+typedef enum fge_dtype { FGE_F32 = 0, FGE_F16 = 1, FGE_U8 = 2, FGE_F64 = 3 } fge_dtype;
 
 /* Sweep order on the device.  Red-black (pixels with (x + y) even, then odd, each in place) runs
  * on every kernel.  Jacobi (every pixel from the previous sweep's values) runs on per-level
@@ -102,8 +102,9 @@ void fge_default_params(fge_params *p);
 /* Human-readable name of a status code (static string). */
 const char *fge_status_string(int status);
 
-/* Library ABI version (increments when fge_params or a signature changes); this header is 5
- * (4 moved every size argument to height-first order, 5 added fge_estimate_foreground_noalloc). */
+/* Library ABI version (increments when fge_params or a signature changes); this header is 6
+ * (4 moved every size argument to height-first order, 5 added fge_estimate_foreground_noalloc,
+ * 6 added the closed-form solve fge_closed_form). */
 int32_t fge_version(void);
 
 /* ---- host-only planning (no GPU needed) ---------------------------------------------- */
@@ -196,6 +197,63 @@ fge_status fge_estimate_foreground_levels(const void *I, const void *alpha, int3
                                           const fge_params *p, const fge_level_options *o,
                                           void *F, void *B, int32_t *sweeps_out, void *workspace,
                                           size_t workspace_bytes, void *stream);
+
+/* ---- closed-form global solve (Section III-B, eq. 2) ----------------------------------- */
+
+/* The closed-form estimate the paper compares against (Section III-B): the minimiser of eq. 2,
+ * per colour channel
+ *   sum_i (a_i F_i + (1 - a_i) B_i - I_i)^2
+ *     + sum over horizontal and vertical neighbour pairs {i, j} of
+ *       w_ij ((F_i - F_j)^2 + (B_i - B_j)^2),   w_ij = eps + omega |a_i - a_j|,
+ * with eq. 2's gradient magnitudes |alpha_x|, |alpha_y| read as forward differences.  omega = 1
+ * is eq. 2 as printed; eps > 0 is the regulariser of Section III-C, without which F is free where
+ * alpha = 0 and B where alpha = 1 (the system is then singular).  No clamp: the unconstrained
+ * minimiser.  The 2n x 2n normal equations A x = b (x_i = (F_i, B_i), the same A for the three
+ * channels) are solved by conjugate gradients with a block-Jacobi preconditioner (the exact
+ * inverse of A's 2x2 diagonal blocks; the paper's remark after eq. 2 uses a thresholded
+ * incomplete Cholesky factor, whose triangular solves are sequential), in float64 on the device,
+ * until every channel's relative residual |b - A x| / |b| is at most tol (the remark quotes
+ * 1e-6) or max_iter iterations have run.  A is positive definite unless alpha is constant over
+ * the whole image. */
+typedef struct fge_cf_params {
+    uint32_t size;        /* sizeof(fge_cf_params) */
+    int32_t storage;      /* fge_dtype of I, alpha, F, B: FGE_F32, FGE_F16 or FGE_F64 */
+    double omega;         /* weight of |alpha_i - alpha_j| (1.0, eq. 2) */
+    double eps;           /* regulariser added to every edge weight, > 0 (5e-3, Section III-C) */
+    double tol;           /* relative residual per channel, > 0 (1e-6) */
+    int32_t max_iter;     /* iteration cap, 0..1000000; 0 = 20000 */
+    int32_t warm_start;   /* 1: start from the F, B the output buffers hold; 0: from zero */
+} fge_cf_params;
+
+typedef struct fge_cf_info {
+    int32_t iterations;            /* iterations of the slowest channel */
+    int32_t converged;             /* 1 when every channel reached tol */
+    int32_t channel_iterations[3]; /* iterations each channel ran until it converged */
+    int32_t breakdown;             /* 1 if a search direction had p.Ap <= 0 (singular A) */
+    double rel_residual[3];        /* |b - A x~| / |b| of the stored F, B (x~: x rounded to the
+                                      storage type), recomputed after the last iteration */
+    double recursive_rel_residual[3]; /* the CG recurrence's own residual at its stop */
+} fge_cf_info;
+
+/* Fill *p with the defaults above (omega 1, eps 5e-3, tol 1e-6, 20000 iterations, float32). */
+void fge_cf_default_params(fge_cf_params *p);
+
+/* Workspace bytes of fge_closed_form for an H x W input (0 on bad sizes): five float64 vectors of
+ * 6 planes (x, r, two search directions, A p) plus scalars and partial sums, about 240 B/px. */
+size_t fge_cf_workspace_bytes(int32_t H, int32_t W);
+
+/* Solve for F, B (3 x H x W each) from I (3 x H x W) and alpha (H x W), all device buffers in
+ * p->storage type (p == NULL: the defaults), on `stream`.  Unlike the estimation calls this one
+ * BLOCKS the calling thread until the solve has finished on the device: the iteration count
+ * depends on the data, so the host enqueues iterations in chunks and reads a device flag
+ * between them (pinned host memory and two events are created per call; no device memory is
+ * allocated).  *info (may be NULL) receives the iteration counts and residuals.  FGE_EINVAL on
+ * bad sizes (H * W >= 2 is required), parameters, or outputs overlapping the inputs or the
+ * workspace; FGE_EWORKSPACE if the workspace is missing, unaligned or smaller than
+ * fge_cf_workspace_bytes; FGE_ENOMEM if the pinned host words cannot be allocated. */
+fge_status fge_closed_form(const void *I, const void *alpha, int32_t H, int32_t W,
+                           const fge_cf_params *p, void *F, void *B, void *workspace,
+                           size_t workspace_bytes, void *stream, fge_cf_info *info);
 
 /* ---- batches of images of different sizes ---------------------------------------------- */
 

@@ -19,7 +19,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libfge.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 
-SOURCES = ["fge_plan.cpp", "fge_api.cpp", "fge_batch.cpp", "fge_server.cpp", "fge_tune.cpp", "fge_kernels.hip", "fge_util.hip", "fge_converge.hip"]
+SOURCES = ["fge_plan.cpp", "fge_api.cpp", "fge_batch.cpp", "fge_server.cpp", "fge_tune.cpp", "fge_kernels.hip", "fge_util.hip", "fge_converge.hip", "fge_closed_form.hip"]
 ARCH = "gfx950"
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libfge.so")
 
 FGE_OK, FGE_EINVAL, FGE_ENOMEM, FGE_EHIP, FGE_EUNSUPPORTED, FGE_EWORKSPACE = 0, -1, -2, -3, -4, -5
 FGE_EBUDGET = -6
-F32, F16, U8 = 0, 1, 2
+F32, F16, U8, F64 = 0, 1, 2, 3
 REDBLACK, JACOBI = 0, 1
 KERNEL_AUTO, KERNEL_FUSED, KERNEL_NAIVE = 0, 1, 2
 MAX_LEVELS = 16
@@ -59,6 +59,29 @@ class LevelOptions(ctypes.Structure):
 
 
 RESIZE_NEAREST, RESIZE_SMOOTH = 0, 1
+
+
+class CfParams(ctypes.Structure):
+    _fields_ = [
+        ("size", ctypes.c_uint32),
+        ("storage", ctypes.c_int32),
+        ("omega", ctypes.c_double),
+        ("eps", ctypes.c_double),
+        ("tol", ctypes.c_double),
+        ("max_iter", ctypes.c_int32),
+        ("warm_start", ctypes.c_int32),
+    ]
+
+
+class CfInfo(ctypes.Structure):
+    _fields_ = [
+        ("iterations", ctypes.c_int32),
+        ("converged", ctypes.c_int32),
+        ("channel_iterations", ctypes.c_int32 * 3),
+        ("breakdown", ctypes.c_int32),
+        ("rel_residual", ctypes.c_double * 3),
+        ("recursive_rel_residual", ctypes.c_double * 3),
+    ]
 
 
 class TuneEntry(ctypes.Structure):
@@ -190,6 +213,14 @@ def _lib():
     lib.fge_levels_workspace_bytes.restype = sz
     lib.fge_estimate_foreground_levels.argtypes = [vp, vp, i32, i32, pp, op, vp, vp, vp, vp, sz, vp]
     lib.fge_estimate_foreground_levels.restype = ctypes.c_int
+    cfp = ctypes.POINTER(CfParams)
+    lib.fge_cf_default_params.argtypes = [cfp]
+    lib.fge_cf_default_params.restype = None
+    lib.fge_cf_workspace_bytes.argtypes = [i32, i32]
+    lib.fge_cf_workspace_bytes.restype = sz
+    lib.fge_closed_form.argtypes = [vp, vp, i32, i32, cfp, vp, vp, vp, sz, vp,
+                                    ctypes.POINTER(CfInfo)]
+    lib.fge_closed_form.restype = ctypes.c_int
     tp = ctypes.POINTER(TuneEntry)
     lib.fge_tune_candidates.argtypes = []
     lib.fge_tune_candidates.restype = i32
@@ -342,6 +373,68 @@ def estimate_foreground(I, alpha, params: Params | None = None, F=None, B=None, 
                                         _stream_ptr(stream))
     _check(st, "fge_estimate_foreground")
     return F, B
+
+
+def cf_default_params(**overrides) -> CfParams:
+    """Defaults of the closed-form solve (omega 1, eps 5e-3, tol 1e-6, 20000 iterations,
+    float32), with optional overrides."""
+    p = CfParams()
+    _lib().fge_cf_default_params(ctypes.byref(p))
+    for k, v in overrides.items():
+        if not hasattr(p, k):
+            raise KeyError(k)
+        setattr(p, k, v)
+    return p
+
+
+def cf_workspace_bytes(H: int, W: int) -> int:
+    return _lib().fge_cf_workspace_bytes(H, W)
+
+
+@_on_stream
+def closed_form(I, alpha, params: CfParams | None = None, F=None, B=None, workspace=None,
+                stream=None):
+    """The closed-form solve of eq. 2 (fge_closed_form): block-Jacobi preconditioned CG in
+    float64 on the device.  Returns (F, B, info) with info a dict of the iteration counts and
+    residuals.  Blocks until the solve has finished.  With params.warm_start the solve starts
+    from the F, B passed in."""
+    import torch
+    p = params if params is not None else cf_default_params()
+    dt = {F16: torch.float16, F64: torch.float64}.get(p.storage, torch.float32)
+    if I.dim() != 3 or I.shape[0] != 3:
+        raise ValueError("I must be (3, H, W)")
+    _, H, W = I.shape
+    if tuple(alpha.shape) != (H, W):
+        raise ValueError("alpha must be (H, W) matching I")
+    for name, t in (("I", I), ("alpha", alpha)):
+        if not t.is_cuda or t.dtype != dt or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous CUDA tensor of dtype {dt}")
+    if p.warm_start and (F is None or B is None):
+        raise ValueError("warm_start needs the starting F and B")
+    if F is None:
+        F = torch.empty((3, H, W), dtype=dt, device=I.device)
+    if B is None:
+        B = torch.empty((3, H, W), dtype=dt, device=I.device)
+    for name, t in (("F", F), ("B", B)):
+        if tuple(t.shape) != (3, H, W) or t.dtype != dt or not t.is_contiguous() or not t.is_cuda:
+            raise ValueError(f"{name} must be a contiguous (3, H, W) CUDA tensor of dtype {dt}")
+    need = cf_workspace_bytes(H, W)
+    if workspace is None:
+        workspace = torch.empty(max(1, need), dtype=torch.uint8, device=I.device)
+    info = CfInfo()
+    st = _lib().fge_closed_form(I.data_ptr(), alpha.data_ptr(), H, W, ctypes.byref(p),
+                                F.data_ptr(), B.data_ptr(), workspace.data_ptr(),
+                                workspace.numel() * workspace.element_size(), _stream_ptr(stream),
+                                ctypes.byref(info))
+    _check(st, "fge_closed_form")
+    return F, B, {
+        "iterations": info.iterations,
+        "converged": bool(info.converged),
+        "channel_iterations": list(info.channel_iterations),
+        "breakdown": bool(info.breakdown),
+        "rel_residual": list(info.rel_residual),
+        "recursive_rel_residual": list(info.recursive_rel_residual),
+    }
 
 
 def profile_start(capacity: int = 4096):

@@ -44,7 +44,7 @@ def test_params_layout_and_defaults(fge):
     assert abs(p.omega - 0.1) < 1e-7 and abs(p.eps_r - 5e-3) < 1e-9
     assert (p.small_size, p.iters_small, p.iters_big) == (32, 10, 2)
     assert (p.storage, p.order, p.kernel, p.strip_rows, p.coarse_max_px, p.tile_max_px) == (0,) * 6
-    assert fge.load().fge_version() == 5
+    assert fge.load().fge_version() == 6
 
 
 def test_plan_matches_golden(fge):
@@ -430,3 +430,41 @@ def test_non_square_plan_order(fge):
     n, nc = ctypes.c_int32(), ctypes.c_int32()
     assert lib.fge_plan(301, 700, None, 16, wo, ho, it, ctypes.byref(n), ctypes.byref(nc)) == 0
     assert (wo[n.value - 1], ho[n.value - 1]) == (700, 301)
+
+
+def test_closed_form_params_and_argument_errors(fge):
+    """fge_closed_form: the parameter block's layout and defaults (omega 1 as eq. 2 prints it,
+    the eps regulariser, the 1e-6 residual of the remark after eq. 2), the workspace size, and
+    every argument error returned before anything is enqueued."""
+    p = fge.cf_default_params()
+    assert p.size == ctypes.sizeof(fge.CfParams) == 40
+    assert (p.omega, p.eps, p.tol, p.max_iter, p.storage, p.warm_start) == (1.0, 5e-3, 1e-6,
+                                                                            20000, fge.F32, 0)
+    assert ctypes.sizeof(fge.CfInfo) == 72
+    lib = fge.load()
+    H, W = 300, 700
+    need = fge.cf_workspace_bytes(H, W)
+    assert need >= 5 * 6 * 8 * H * W and need % 256 == 0
+    assert fge.cf_workspace_bytes(0, 5) == 0 and fge.cf_workspace_bytes(5, 40000) == 0
+
+    def call(H=H, W=W, p=p, I=I0, A=A0, F=F0, B=B0, ws=WS0, ws_len=None):
+        info = fge.CfInfo()
+        return lib.fge_closed_form(I, A, H, W, ctypes.byref(p) if p is not None else None, F, B,
+                                   ws, need if ws_len is None else ws_len, None,
+                                   ctypes.byref(info))
+
+    assert call(ws_len=need - 1) == fge.FGE_EWORKSPACE            # passes every other check
+    assert call(ws=None) == fge.FGE_EWORKSPACE
+    assert call(ws=WS0 + 8) == fge.FGE_EWORKSPACE                 # unaligned
+    assert call(H=1, W=1, ws_len=0) == fge.FGE_EINVAL             # one pixel: no edge, singular
+    assert call(H=0) == fge.FGE_EINVAL
+    assert call(I=None) == fge.FGE_EINVAL
+    assert call(F=I0 + 8) == fge.FGE_EINVAL                       # output overlaps the input
+    assert call(B=F0) == fge.FGE_EINVAL
+    for field, bad in (("eps", 0.0), ("eps", float("nan")), ("omega", -1.0), ("tol", 0.0),
+                       ("tol", float("inf")), ("max_iter", -1), ("storage", fge.U8), ("size", 8)):
+        q = fge.cf_default_params()
+        setattr(q, field, bad)
+        assert call(p=q) == fge.FGE_EINVAL, field
+    # the estimation entry points do not take float64 storage
+    assert _call(fge, 64, 64, fge.default_params(storage=fge.F64)) == fge.FGE_EINVAL
