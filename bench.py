@@ -192,6 +192,109 @@ def run_variants(torch, fge, sample):
                         "the smooth resize variant", "unit": "MP/s", **out}
 
 
+CF_BYTES_PER_PX_F32 = 488   # per pixel and PCG iteration, float32 matte: see run_closed_form
+
+
+def run_closed_form(torch, fge, synth, check_oracle, big=None):
+    """The closed-form solve of eq. 2 (omega 1, eps 5e-3) on the 1024x768 strand workload to the
+    paper's relative residual of 1e-6 per channel: block-Jacobi PCG in float64 on the device,
+    float32 storage.  Reports the iterations, the device time (events around the solve), the
+    time per iteration and the HBM rate of the iterations' algorithmic bytes.  Per pixel and
+    iteration the two launches move, in float64: spmv reads r and the previous direction
+    (2 x 48 B) and the matte (4 B), writes the direction and A p (2 x 48 B); update reads x, the
+    direction, r and A p (4 x 48 B) and the matte, writes x and r (2 x 48 B): 488 B with a
+    float32 matte.  Also: a warm start from the multi-level estimate (Algorithm 1 on the GPU,
+    omega 1), and the oracle's sparse direct solve timed on a 256x192 sample."""
+    s = synth.config2()
+    H, W = s.alpha.shape
+    dev = torch.device("cuda:0")
+    I = torch.from_numpy(s.I).float().to(dev).contiguous()
+    a = torch.from_numpy(s.alpha).float().to(dev).contiguous()
+    p = fge.cf_default_params(storage=fge.F32, tol=1e-6)
+    ws = torch.empty(fge.cf_workspace_bytes(H, W), dtype=torch.uint8, device=dev)
+    F = torch.empty((3, H, W), dtype=torch.float32, device=dev)
+    B = torch.empty_like(F)
+    fge.closed_form(I, a, p, F=F, B=B, workspace=ws)
+    runs = []
+    for _ in range(5):
+        t0 = time.perf_counter()
+        _, _, info = fge.closed_form(I, a, p, F=F, B=B, workspace=ws)
+        runs.append((info["device_ms"], (time.perf_counter() - t0) * 1e3, info))
+    runs.sort(key=lambda r: r[0])
+    dev_ms, wall_ms, info = runs[len(runs) // 2]
+    n = H * W
+    iters = info["iterations"]
+    bpi = CF_BYTES_PER_PX_F32 * n
+    achieved = bpi * iters / (dev_ms * 1e-3) / 1e9
+    out = {
+        "workload": "1024x768 strand image (seed 2), closed-form cost of eq. 2 with omega 1 and "
+                    "eps 5e-3, block-Jacobi PCG in float64, float32 storage, relative residual "
+                    "1e-6 per channel",
+        "iterations": info["channel_iterations"],
+        "device_ms": dev_ms, "wall_ms": wall_ms,
+        "ms_per_iteration": dev_ms / iters,
+        "rel_residual": info["rel_residual"],
+        "value": n / 1e6 / (dev_ms * 1e-3), "unit": "MP/s (to residual 1e-6)",
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "algorithmic_bytes_per_iteration": bpi},
+    }
+    log(f"  closed form: {iters} iterations, {dev_ms:.2f} ms on the device ({wall_ms:.2f} wall), "
+        f"{dev_ms / iters * 1e3:.1f} us/iteration, {achieved:.0f} GB/s algorithmic")
+    # The 1024x768 solve's vectors (30 float64 planes, 189 MB) fit the 256 MB memory-side cache,
+    # so its rate is partly a cache rate.  The HBM rate of an iteration is taken at 4096x3072
+    # (3.0 GB of vectors): the difference of two capped runs (120 and 20 iterations, tolerance
+    # unreachable) divided by 100 is the time of one iteration without the start and result
+    # launches.
+    if big is not None:
+        Hb, Wb = big.alpha.shape
+        Ib = torch.from_numpy(big.I).float().to(dev).contiguous()
+        ab = torch.from_numpy(big.alpha).float().to(dev).contiguous()
+        wsb = torch.empty(fge.cf_workspace_bytes(Hb, Wb), dtype=torch.uint8, device=dev)
+        Fb = torch.empty((3, Hb, Wb), dtype=torch.float32, device=dev)
+        Bb = torch.empty_like(Fb)
+        t = {}
+        for cap in (20, 120):
+            pc = fge.cf_default_params(storage=fge.F32, tol=1e-300, max_iter=cap)
+            fge.closed_form(Ib, ab, pc, F=Fb, B=Bb, workspace=wsb)
+            ms = sorted(fge.closed_form(Ib, ab, pc, F=Fb, B=Bb, workspace=wsb)[2]["device_ms"]
+                        for _ in range(3))
+            t[cap] = ms[1]
+        it_ms = (t[120] - t[20]) / 100
+        bpi_big = CF_BYTES_PER_PX_F32 * Hb * Wb
+        ach = bpi_big / (it_ms * 1e-3) / 1e9
+        out["iteration_hbm_4096x3072"] = {
+            "ms_per_iteration": it_ms, "algorithmic_bytes_per_iteration": bpi_big,
+            "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": ach / HBM_PEAK_GBS},
+            "method": "(device time of 120 iterations - of 20) / 100, float32 storage"}
+        log(f"  4096x3072: {it_ms * 1e3:.1f} us per iteration, {ach:.0f} GB/s ({ach / HBM_PEAK_GBS:.3f} of peak)")
+        del Ib, ab, wsb, Fb, Bb
+    # warm start from Algorithm 1's estimate with the same omega
+    pm = fge.default_params(omega=1.0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    Fm, Bm = fge.estimate_foreground(I, a, pm, F=F, B=B)
+    pw = fge.cf_default_params(storage=fge.F32, tol=1e-6, warm_start=1)
+    _, _, winfo = fge.closed_form(I, a, pw, F=Fm, B=Bm, workspace=ws)
+    warm_wall = (time.perf_counter() - t0) * 1e3
+    out["warm_start_from_multilevel"] = {"iterations": winfo["channel_iterations"],
+                                         "device_ms": winfo["device_ms"], "wall_ms": warm_wall,
+                                         "rel_residual": winfo["rel_residual"]}
+    log(f"  warm start from the multi-level estimate: {winfo['iterations']} iterations, "
+        f"{winfo['device_ms']:.2f} ms")
+    if check_oracle:
+        from oracle import closed_form as cf
+        sm = synth.strands(256, 192, seed=2, n_strands=13)
+        t0 = time.perf_counter()
+        cf.solve(sm.I, sm.alpha, 1.0, 5e-3)
+        cpu_s = time.perf_counter() - t0
+        out["cpu_oracle_direct_solve"] = {
+            "value": 256 * 192 / 1e6 / cpu_s, "unit": "MP/s", "cores": 1, "kind": "oracle",
+            "sample": f"256x192 strand image, SciPy sparse LU of the normal equations, three "
+                      f"channels, {cpu_s:.2f} s"}
+    return out
+
+
 def time_batch(torch, fge, sizes, p, Is, As, steps, warmup, stream):
     """One batch plan timed as plain runs (wall clock) and as hipGraph replays (events)."""
     b = fge.Batch([(h, w) for w, h in sizes], p)
@@ -397,6 +500,12 @@ def main():
                          "default 2^16, the limit the batch autotuner picks for batched launches")
     ap.add_argument("--no-converge", action="store_true",
                     help="skip the level-loop variants leg (convergence form, smooth resize)")
+    ap.add_argument("--no-closed-form", action="store_true",
+                    help="skip the closed-form (eq. 2) PCG leg")
+    ap.add_argument("--closed-form-only", action="store_true",
+                    help="run only the closed-form leg and print its JSON (for profiling)")
+    ap.add_argument("--closed-form-big", action="store_true",
+                    help="with --closed-form-only: also the 4096x3072 per-iteration HBM rate")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 512 MiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -411,6 +520,12 @@ def main():
     from paper_2006_14970_amd import fge, synth
     fge.load()
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+
+    if args.closed_form_only:
+        log("closed-form solve (eq. 2), 1024x768")
+        big = synth.config3() if args.closed_form_big else None
+        print(json.dumps({"closed_form_fp32": run_closed_form(torch, fge, synth, False, big)}), flush=True)
+        return
 
     log("generating the 4096x3072 strands workload (seed 3)")
     t = time.perf_counter()
@@ -486,6 +601,10 @@ def main():
     if not args.no_converge:
         log("level-loop variants: convergence form, smooth resize (float16 storage)")
         variants = run_variants(torch, fge, sample)
+    closed = None
+    if not args.no_closed_form:
+        log("closed-form solve (eq. 2), 1024x768, PCG to relative residual 1e-6")
+        closed = run_closed_form(torch, fge, synth, not args.no_cpu_baseline, sample)
     batch = None if args.no_batch else run_batch(torch, fge, synth, args, s32["value"],
                                                    not args.no_cpu_baseline)
     serving = None if args.no_serving else run_serving(torch, fge, synth, args, s32["value"],
@@ -513,6 +632,7 @@ def main():
         "level_ms_finest_first": s32["level_ms_finest_first"],
         "quality_vs_ground_truth": s32["quality_vs_ground_truth"],
         "variants_fp16": variants,
+        "closed_form_fp32": closed,
         "batch_fp16": batch,
         "serving_fp16": serving,
         "cpu_baseline": cpu,

@@ -81,6 +81,7 @@ class CfInfo(ctypes.Structure):
         ("breakdown", ctypes.c_int32),
         ("rel_residual", ctypes.c_double * 3),
         ("recursive_rel_residual", ctypes.c_double * 3),
+        ("device_ms", ctypes.c_double),
     ]
 
 
@@ -143,6 +144,11 @@ def _lib():
         raise RuntimeError(
             f"libfge.so not found at {LIB_PATH}: build it with "
             "`python -m paper_2006_14970_amd.build` (no CPU fallback exists)")
+    # libfge needs libamdhip64.so.7, the soname of PyTorch's bundled HIP runtime too: loading
+    # torch first makes the library bind to that same runtime, so the streams and device memory
+    # the binding passes in belong to the runtime that executes the calls.  (Loaded the other way
+    # round, the process would end up with the system runtime under torch.)
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
     vp, i32, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_size_t
     pp = ctypes.POINTER(Params)
@@ -434,6 +440,7 @@ def closed_form(I, alpha, params: CfParams | None = None, F=None, B=None, worksp
         "breakdown": bool(info.breakdown),
         "rel_residual": list(info.rel_residual),
         "recursive_rel_residual": list(info.recursive_rel_residual),
+        "device_ms": info.device_ms,
     }
 
 

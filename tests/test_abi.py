@@ -440,7 +440,7 @@ def test_closed_form_params_and_argument_errors(fge):
     assert p.size == ctypes.sizeof(fge.CfParams) == 40
     assert (p.omega, p.eps, p.tol, p.max_iter, p.storage, p.warm_start) == (1.0, 5e-3, 1e-6,
                                                                             20000, fge.F32, 0)
-    assert ctypes.sizeof(fge.CfInfo) == 72
+    assert ctypes.sizeof(fge.CfInfo) == 80
     lib = fge.load()
     H, W = 300, 700
     need = fge.cf_workspace_bytes(H, W)
