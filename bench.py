@@ -31,6 +31,31 @@ HBM_PEAK_GBS = 8000.0
 W_IMG, H_IMG = 4096, 3072
 
 
+def _kernel_sha():
+    import hashlib
+    root = os.path.dirname(os.path.abspath(__file__))
+    src = os.path.join(root, "paper_2006_14970_amd", "csrc", "fge_kernels.hip")
+    return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+
+
+def profiled_sq(kernel, grid):
+    """SQ-counter figures of one launch from the committed summary (VALU issue time, TA address
+    FIFO full time per CU), or None when the kernel source has changed since they were taken."""
+    root = os.path.dirname(os.path.abspath(__file__))
+    path = os.path.join(root, "profiles", "fine_kernel_4096x3072_sq_counters.txt")
+    if not os.path.exists(path):
+        return None
+    sha = _kernel_sha()
+    for line in open(path):
+        f = line.split()
+        if len(f) >= 4 and f[0] == "SQ" and f[1] == kernel and f[2] == str(grid):
+            kv = dict(x.split("=", 1) for x in f[3:])
+            if kv.get("sha") != sha:
+                return None
+            return {k: float(v) for k, v in kv.items() if k != "sha"}
+    return None
+
+
 def profiled_traffic(kernel):
     """HBM bytes per launch of `kernel` at 4096x3072 from the committed rocprofv3 counter summary
     (FETCH_SIZE and WRITE_SIZE runs, scaled by a plain copy's readings), or None when the kernel
@@ -575,7 +600,9 @@ def main():
 
     def summary(r, elem):
         lb = level_bytes(plan.levels, elem)
-        traffic = profiled_traffic("fge::fine_kernel<float>" if elem == 4 else "fge::fine_kernel<_Float16>")
+        kname = "fge::fine_kernel<float>" if elem == 4 else "fge::fine_kernel<_Float16>"
+        traffic = profiled_traffic(kname)
+        sq = profiled_sq(kname, 430080)
         fin_ms = r["level_ms"][0]
         achieved = lb[-1] / (fin_ms * 1e-3) / 1e9
         return {
@@ -587,7 +614,9 @@ def main():
             "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                          "kernel": "fine_kernel, finest level 4096x3072",
-                         "kernel_ms": fin_ms, "algorithmic_bytes": lb[-1]},
+                         "kernel_ms": fin_ms, "algorithmic_bytes": lb[-1],
+                         "sq_counters": None if sq is None else {
+                             **sq, "valu_issue_share": sq["valu_issue_us"] / (fin_ms * 1e3)}},
             "level_ms_finest_first": [round(x, 5) if x is not None else None
                                       for x in r["level_ms"][:len(plan.levels) - plan.n_coarse + 1]],
         }
