@@ -55,7 +55,8 @@ typedef enum fge_status {
     FGE_EHIP = -3,          /* a HIP runtime call or kernel launch failed */
     FGE_EUNSUPPORTED = -4,  /* valid request this build does not implement */
     FGE_EWORKSPACE = -5,    /* workspace missing or smaller than fge_workspace_bytes */
-    FGE_EBUDGET = -6        /* a request that can never fit a server's budget or arena */
+    FGE_EBUDGET = -6,       /* a request that can never fit a server's budget or arena */
+    FGE_ECANCELED = -7      /* a server request cancelled before admission */
 } fge_status;
 
 /* Element types.  F32 and F16 are storage types of the estimator; U8 (values 0..255 standing
@@ -102,9 +103,10 @@ void fge_default_params(fge_params *p);
 /* Human-readable name of a status code (static string). */
 const char *fge_status_string(int status);
 
-/* Library ABI version (increments when fge_params or a signature changes); this header is 6
+/* Library ABI version (increments when fge_params or a signature changes); this header is 7
  * (4 moved every size argument to height-first order, 5 added fge_estimate_foreground_noalloc,
- * 6 added the closed-form solve fge_closed_form). */
+ * 6 added the closed-form solve fge_closed_form, 7 the server's failure counters, cancellation
+ * and simulated executor). */
 int32_t fge_version(void);
 
 /* ---- host-only planning (no GPU needed) ---------------------------------------------- */
@@ -233,6 +235,9 @@ typedef struct fge_cf_info {
     double rel_residual[3];        /* |b - A x~| / |b| of the stored F, B (x~: x rounded to the
                                       storage type), recomputed after the last iteration */
     double recursive_rel_residual[3]; /* the CG recurrence's own residual at its stop */
+    double device_ms;              /* event time on `stream` from the start of the first kernel
+                                      to the end of the last (includes the launches enqueued
+                                      after convergence, which return at once) */
 } fge_cf_info;
 
 /* Fill *p with the defaults above (omega 1, eps 5e-3, tol 1e-6, 20000 iterations, float32). */
@@ -444,7 +449,8 @@ typedef struct fge_server_result {
 } fge_server_result;
 
 typedef struct fge_server_stats {
-    int64_t submitted, completed, ticks, launches;
+    int64_t submitted, completed, ticks, launches;   /* completed counts every result, failed
+                                                        and cancelled ones too */
     int64_t mixed_ticks;       /* ticks that advanced requests at two or more different levels */
     int64_t admitted_while_busy; /* requests admitted while other requests were on the device */
     int32_t peak_active;
@@ -452,6 +458,8 @@ typedef struct fge_server_stats {
     uint64_t peak_charged_bytes; /* peak sum of admitted footprints (<= budget_bytes) */
     uint64_t peak_arena_bytes;   /* peak arena bytes in use (tables included) */
     double mean_active;        /* admitted requests per tick, averaged over ticks */
+    int64_t failed;            /* requests completed with an error */
+    int64_t cancelled;         /* requests cancelled before admission */
 } fge_server_stats;
 
 /* Fill *c with the defaults above. */
@@ -479,8 +487,17 @@ fge_status fge_server_create(const fge_params *p, const fge_server_config *c, vo
 fge_status fge_server_submit(fge_server *s, int64_t id, const void *I, const void *alpha,
                              int32_t H, int32_t W, void *F, void *B);
 
+/* Cancel a request that is still queued (submitted, not yet admitted): it completes at once with
+ * status FGE_ECANCELED and is reported by fge_server_poll like any other.  FGE_EINVAL if no
+ * queued request has this id (unknown, already admitted -- it then runs to completion -- or
+ * completed). */
+fge_status fge_server_cancel(fge_server *s, int64_t id);
+
 /* Move up to `cap` completed requests (completion order) into out[]; returns how many, or a
- * negative status if the server has failed.  Never blocks. */
+ * negative status if the server has failed.  Never blocks.  A request's status is FGE_OK, the
+ * error of a tick whose launch failed (FGE_EHIP: that tick's requests fail, the server goes on),
+ * FGE_ECANCELED, or the error that ended the server (an error of the device itself: every request
+ * not yet completed fails with it). */
 int32_t fge_server_poll(fge_server *s, fge_server_result *out, int32_t cap);
 
 /* Block until every request submitted so far has completed (results stay pollable). */
@@ -491,6 +508,41 @@ fge_status fge_server_get_stats(fge_server *s, fge_server_stats *out);
 
 /* Drain, stop the scheduler thread and free the server's host resources (not the arena). */
 void fge_server_destroy(fge_server *s);
+
+/* A server whose device is a host model, for testing schedules without a GPU and under host
+ * sanitizers: the same scheduler (admission, budget, tick tables, failures, cancellation) drives
+ * a simulated executor that uploads and launches nothing and touches no buffer -- the arena is a
+ * reserved range of the address space and request pointers are only stored.  A tick takes
+ * us_per_launch per launch (the upload counts as one) plus us_per_mpx per megapixel of the fine
+ * levels it advances; ticks run one after another.  Failure injection: the k-th tick's launch
+ * fails (fail_launch_tick = k; its requests fail with FGE_EHIP, the server goes on), or the k-th
+ * tick reports a device error when it completes (fail_device_tick = k; the server fails).
+ * manual = 1: no scheduler thread and a clock that only moves when the caller calls
+ * fge_server_sim_step, so a schedule is reproducible exactly; fge_server_drain and
+ * fge_server_destroy then step the server themselves until every request has completed.
+ * manual = 0: a scheduler thread and the host clock, as with the HIP executor. */
+typedef struct fge_server_sim {
+    uint32_t size;             /* sizeof(fge_server_sim) */
+    int32_t manual;            /* 1 (default): stepped by the caller; 0: own thread */
+    double us_per_launch;      /* modelled time per launch (3.0) */
+    double us_per_mpx;         /* modelled time per megapixel of fine levels (8.0) */
+    int32_t fail_launch_tick;  /* 0 = none */
+    int32_t fail_device_tick;  /* 0 = none */
+} fge_server_sim;
+
+void fge_server_sim_default(fge_server_sim *m);
+fge_status fge_server_create_simulated(const fge_params *p, const fge_server_config *c,
+                                       size_t arena_bytes, const fge_server_sim *m,
+                                       fge_server **out);
+
+/* Manual mode: advance the clock by advance_ms, complete the `complete` oldest ticks in flight
+ * (at the later of their modelled end and the clock), then run the scheduler until it has
+ * nothing more to enqueue.  Returns the ticks enqueued, or a negative status (the error that
+ * ended the server, FGE_EINVAL for bad arguments or a server not in manual mode). */
+int32_t fge_server_sim_step(fge_server *s, int32_t complete, double advance_ms);
+
+/* Ticks of a simulated server launched and not yet completed (manual) or reported (thread). */
+int32_t fge_server_sim_inflight(fge_server *s);
 
 /* ---- profiling ------------------------------------------------------------------------- */
 

@@ -10,7 +10,7 @@
 
 namespace {
 
-constexpr int32_t kAbiVersion = 6;
+constexpr int32_t kAbiVersion = 7;
 
 struct ProfileRecord {
     int level;          // 0 = finest
@@ -163,6 +163,7 @@ const char *fge_status_string(int status) {
         case FGE_EUNSUPPORTED: return "FGE_EUNSUPPORTED: not implemented for these parameters";
         case FGE_EWORKSPACE: return "FGE_EWORKSPACE: workspace missing or too small";
         case FGE_EBUDGET: return "FGE_EBUDGET: request larger than the server budget or arena";
+        case FGE_ECANCELED: return "FGE_ECANCELED: request cancelled before admission";
         default: return "unknown fge status";
     }
 }

@@ -17,6 +17,15 @@
 // The kernels are the batched kernels of the uneven-batch path; only the schedule differs: there,
 // all images' levels are aligned from the finest once; here each request advances one level per
 // tick from the tick that admits it, so requests at different levels share launches.
+//
+// The scheduler talks to the device through an executor: the HIP one (pinned staging, the
+// server's stream, an event per tick slot) or a host model of it (fge_server_create_simulated:
+// modelled tick durations, injectable launch and device failures, and a manual mode in which the
+// caller's thread runs the scheduler step by step), which the CPU tests and sanitizer builds drive.
+// Failures: a tick whose launch fails fails only the requests in that tick (after everything
+// already enqueued has finished) and the server goes on; an error reported by the device itself
+// fails every request not yet completed and ends the server.  Queued requests (not yet admitted)
+// can be cancelled.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -25,6 +34,7 @@
 #include <cstring>
 #include <deque>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <new>
 #include <thread>
@@ -161,111 +171,358 @@ size_t max_tick_bytes(const fge::Plan &pl, int strip_rows) {
 
 }  // namespace
 
+namespace fge {
+namespace serve {
+
+// What one tick asks of the device: the size of its tables and where each launch's descriptors
+// and work items sit, as byte offsets from the slot's table base.
+struct TickWork {
+    size_t bytes = 0;
+    size_t g_desc = 0, g_first = 0;
+    int n_gather = 0;
+    long long g_total = 0;
+    size_t c_desc = 0;
+    int n_coarse = 0;
+    size_t t_desc = 0, t_items = 0;
+    int t_n = 0;
+    size_t s_desc = 0, s_items = 0;
+    int s_n = 0;
+    long long px = 0;   // fine-level pixels the tick advances (the simulated executor's cost)
+};
+
+// The device side of a server.  The scheduler owns the schedule (admission, the tick tables, the
+// arena); an executor uploads a tick's tables, runs its launches and reports completion.  Slots
+// 0 .. depth-1 each hold one tick at a time; ticks complete in the order they were launched.
+class Executor {
+  public:
+    virtual ~Executor() = default;
+    virtual fge_status init(int depth, size_t table_bytes) = 0;
+    virtual char *staging(int slot) = 0;             // host image of the slot's tables
+    virtual fge_status start_clock() = 0;            // time origin of now_ms and ready times
+    virtual double now_ms() = 0;                     // host clock, ms after the origin
+    virtual fge_status bind_thread() = 0;            // on the scheduler thread, before any launch
+    // Upload the slot's tables to `dev` and enqueue the tick's launches and completion marker.
+    // After a failure, an unknown part of the tick may have been enqueued.
+    virtual fge_status launch(int slot, char *dev, const TickWork &w, int *launches) = 0;
+    // 1: the slot's tick is done (*ready_ms: device completion time); 0: not yet; < 0: an error of
+    // the device itself (the server cannot go on).
+    virtual int poll(int slot, bool block, double *ready_ms) = 0;
+    virtual void quiesce() = 0;                      // wait for everything enqueued so far
+};
+
+double ms_since(Clock::time_point t0) {
+    return std::chrono::duration<double, std::milli>(Clock::now() - t0).count();
+}
+
+// The MI355X: pinned staging and an event per slot, every launch on the server's stream.
+class HipExecutor final : public Executor {
+  public:
+    HipExecutor(hipStream_t stream, int storage) : stream_(stream), storage_(storage) {}
+    ~HipExecutor() override {
+        for (Slot &sl : slots_) {
+            if (sl.done) (void)hipEventDestroy(sl.done);
+            if (sl.staging) (void)hipHostFree(sl.staging);
+        }
+        if (start_) (void)hipEventDestroy(start_);
+    }
+    fge_status init(int depth, size_t table_bytes) override {
+        if (hipGetDevice(&device_) != hipSuccess || hipEventCreate(&start_) != hipSuccess)
+            return FGE_EHIP;
+        slots_.resize(depth);
+        for (Slot &sl : slots_)
+            if (hipHostMalloc(reinterpret_cast<void **>(&sl.staging), table_bytes,
+                              hipHostMallocDefault) != hipSuccess ||
+                hipEventCreate(&sl.done) != hipSuccess)
+                return FGE_EHIP;
+        return FGE_OK;
+    }
+    char *staging(int slot) override { return slots_[slot].staging; }
+    fge_status start_clock() override {
+        // the start event on the idle stream, and the host clock right after it
+        if (hipStreamSynchronize(stream_) != hipSuccess || hipEventRecord(start_, stream_) != hipSuccess ||
+            hipEventSynchronize(start_) != hipSuccess)
+            return FGE_EHIP;
+        t0_ = Clock::now();
+        return FGE_OK;
+    }
+    double now_ms() override { return ms_since(t0_); }
+    fge_status bind_thread() override {
+        return hipSetDevice(device_) == hipSuccess ? FGE_OK : FGE_EHIP;
+    }
+    fge_status launch(int slot, char *dev, const TickWork &w, int *launches) override {
+        *launches = 0;
+        hipStream_t st = stream_;
+        if (hipMemcpyAsync(dev, slots_[slot].staging, w.bytes, hipMemcpyHostToDevice, st) != hipSuccess)
+            return FGE_EHIP;
+        int *cnt = reinterpret_cast<int *>(dev);
+        if (w.n_gather > 0) {
+            if (launch_gather_batch(reinterpret_cast<const GatherArgs *>(dev + w.g_desc),
+                                    reinterpret_cast<const long long *>(dev + w.g_first), w.n_gather,
+                                    w.g_total, storage_, st))
+                return FGE_EHIP;
+            ++*launches;
+        }
+        if (w.n_coarse > 0) {
+            if (launch_coarse_batch(reinterpret_cast<const CoarseArgs *>(dev + w.c_desc), w.n_coarse,
+                                    storage_, st))
+                return FGE_EHIP;
+            ++*launches;
+        }
+        if (w.t_n > 0) {
+            if (launch_tile_batch(reinterpret_cast<const TileArgs *>(dev + w.t_desc),
+                                  reinterpret_cast<const WorkItem *>(dev + w.t_items), w.t_n, cnt,
+                                  storage_, st))
+                return FGE_EHIP;
+            ++*launches;
+        }
+        if (w.s_n > 0) {
+            if (launch_fine_batch(reinterpret_cast<const FineArgs *>(dev + w.s_desc),
+                                  reinterpret_cast<const WorkItem *>(dev + w.s_items), w.s_n, cnt + 1,
+                                  storage_, st))
+                return FGE_EHIP;
+            ++*launches;
+        }
+        return hipEventRecord(slots_[slot].done, st) == hipSuccess ? FGE_OK : FGE_EHIP;
+    }
+    int poll(int slot, bool block, double *ready_ms) override {
+        hipEvent_t e = slots_[slot].done;
+        const hipError_t r = block ? hipEventSynchronize(e) : hipEventQuery(e);
+        if (r == hipErrorNotReady) return 0;
+        float ms = 0.0f;
+        if (r != hipSuccess || hipEventElapsedTime(&ms, start_, e) != hipSuccess) return FGE_EHIP;
+        *ready_ms = ms;
+        return 1;
+    }
+    void quiesce() override { (void)hipStreamSynchronize(stream_); }
+
+  private:
+    struct Slot {
+        char *staging = nullptr;
+        hipEvent_t done = nullptr;
+    };
+    hipStream_t stream_;
+    int storage_;
+    int device_ = 0;
+    hipEvent_t start_ = nullptr;
+    Clock::time_point t0_;
+    std::vector<Slot> slots_;
+};
+
+// A host model of the device for the scheduler's tests: nothing is uploaded or launched and no
+// buffer is touched; a tick takes us_per_launch per launch plus us_per_mpx per megapixel of its
+// fine levels, ticks run one after another.  Manual mode: the clock and the completions move only
+// when the caller says so (fge_server_sim_step), so every schedule is reproducible.
+class SimExecutor final : public Executor {
+  public:
+    explicit SimExecutor(const fge_server_sim &c) : cfg_(c) {}
+    fge_status init(int depth, size_t table_bytes) override {
+        slots_.resize(depth);
+        for (Slot &sl : slots_) sl.staging.assign(table_bytes, 0);
+        return FGE_OK;
+    }
+    char *staging(int slot) override { return slots_[slot].staging.data(); }
+    fge_status start_clock() override {
+        std::lock_guard<std::mutex> g(mu_);
+        t0_ = Clock::now();
+        clock_ = 0.0;
+        return FGE_OK;
+    }
+    double now_ms() override {
+        std::lock_guard<std::mutex> g(mu_);
+        return cfg_.manual ? clock_ : ms_since(t0_);
+    }
+    fge_status bind_thread() override { return FGE_OK; }
+    fge_status launch(int slot, char *, const TickWork &w, int *launches) override {
+        std::lock_guard<std::mutex> g(mu_);
+        const int k = ++ticks_;
+        *launches = 0;
+        if (k == cfg_.fail_launch_tick) return FGE_EHIP;
+        *launches = (w.n_gather > 0) + (w.n_coarse > 0) + (w.t_n > 0) + (w.s_n > 0);
+        Slot &sl = slots_[slot];
+        sl.busy = true;
+        sl.done = false;
+        sl.fail = k == cfg_.fail_device_tick;
+        const double cost_ms = (cfg_.us_per_launch * (*launches + 1) +
+                                cfg_.us_per_mpx * static_cast<double>(w.px) * 1e-6) * 1e-3;
+        const double begin = std::max(cfg_.manual ? clock_ : ms_since(t0_), last_end_);
+        sl.end = begin + cost_ms;
+        last_end_ = sl.end;
+        order_.push_back(slot);
+        return FGE_OK;
+    }
+    int poll(int slot, bool block, double *ready_ms) override {
+        std::unique_lock<std::mutex> g(mu_);
+        Slot &sl = slots_[slot];
+        if (!sl.busy) return 0;
+        if (cfg_.manual) {
+            if (!sl.done) return 0;
+        } else {
+            const double wait = sl.end - ms_since(t0_);
+            if (wait > 0.0) {
+                if (!block) return 0;
+                g.unlock();
+                std::this_thread::sleep_for(std::chrono::duration<double, std::milli>(wait));
+                g.lock();
+            }
+            if (!order_.empty() && order_.front() == slot) order_.pop_front();
+        }
+        if (sl.fail) return FGE_EHIP;
+        *ready_ms = sl.end;
+        sl.busy = false;
+        return 1;
+    }
+    void quiesce() override {}
+    // Manual mode: move the clock, then complete the oldest `n` ticks at their modelled end or
+    // the clock, whichever is later.
+    void step(int n, double advance_ms) {
+        std::lock_guard<std::mutex> g(mu_);
+        clock_ += advance_ms;
+        for (; n > 0 && !order_.empty(); --n) {
+            Slot &sl = slots_[order_.front()];
+            order_.pop_front();
+            sl.end = std::max(sl.end, clock_);
+            clock_ = sl.end;
+            sl.done = true;
+        }
+    }
+    int outstanding() {
+        std::lock_guard<std::mutex> g(mu_);
+        return static_cast<int>(order_.size());
+    }
+
+  private:
+    struct Slot {
+        std::vector<char> staging;
+        bool busy = false, done = false, fail = false;
+        double end = 0.0;
+    };
+    fge_server_sim cfg_;
+    std::mutex mu_;
+    Clock::time_point t0_ = Clock::now();
+    double clock_ = 0.0, last_end_ = 0.0;
+    int ticks_ = 0;
+    std::deque<int> order_;   // launched, not yet completed (manual) / not yet polled (auto)
+    std::vector<Slot> slots_;
+};
+
+struct Slot {
+    size_t dev_off = 0;                 // the slot's tick tables in the arena
+    std::vector<Request *> finishing;   // requests whose last level is in this tick
+};
+
+}  // namespace serve
+}  // namespace fge
+
 struct fge_server {
     fge_params prm{};
     fge_server_config cfg{};
     char *arena = nullptr;
     size_t arena_bytes = 0, reserved = 0, budget = 0;
-    hipStream_t stream = nullptr;
-    int device = 0;
-    hipEvent_t start_ev = nullptr;
-    Clock::time_point t0;
+    std::unique_ptr<fge::serve::Executor> exec;
+    fge::serve::SimExecutor *sim = nullptr;   // exec, when simulated
+    bool manual = false;                      // simulated, driven by fge_server_sim_step
+    std::mutex step_mu;                       // one manual driver at a time
 
     // shared with the API threads, guarded by mu
     std::mutex mu;
     std::condition_variable cv_work, cv_idle;
     std::deque<Request *> incoming;
+    std::deque<Request *> pending;   // taken in by the scheduler, not admitted yet (cancellable)
     std::deque<fge_server_result> results;
     int64_t submitted = 0, completed = 0;
     bool stop = false;
     int error = FGE_OK;
     fge_server_stats stats{};
 
-    // owned by the scheduler thread
+    // owned by the scheduler
     std::thread worker;
     ArenaAlloc alloc;
     size_t charged = 0, arena_used = 0;
-    std::deque<Request *> pending;
     std::vector<Request *> active;
-    std::vector<Slot> slots;
+    std::vector<fge::serve::Slot> slots;
     std::deque<int> inflight;       // slot indices, oldest first
     std::vector<int> free_slots;
     double active_sum = 0;
-
-    double now_ms() const {
-        return std::chrono::duration<double, std::milli>(Clock::now() - t0).count();
-    }
 };
 
 namespace {
 
-void publish(fge_server *s, std::vector<fge_server_result> &out) {
+using fge::serve::TickWork;
+
+fge_server_result make_result(const Request *r, int status, double ready_ms) {
+    fge_server_result res{};
+    res.id = r->id;
+    res.status = status;
+    res.ticks = r->ticks;
+    res.submit_ms = r->submit_ms;
+    res.admit_ms = r->admit_ms;
+    res.ready_ms = ready_ms;
+    res.latency_ms = ready_ms - r->submit_ms;
+    return res;
+}
+
+void publish(fge_server *s, std::vector<fge_server_result> &out, int64_t failed = 0) {
     if (out.empty()) return;
     std::lock_guard<std::mutex> g(s->mu);
     for (auto &r : out) s->results.push_back(r);
     s->completed += static_cast<int64_t>(out.size());
     s->stats.completed = s->completed;
+    s->stats.failed += failed;
     out.clear();
     s->cv_idle.notify_all();
 }
 
-// The device has finished slot si: complete its requests and free the slot.
-fge_status retire(fge_server *s, int si) {
-    Slot &sl = s->slots[si];
-    float ms = 0.0f;
-    const bool ok = hipEventElapsedTime(&ms, s->start_ev, sl.done) == hipSuccess;
+// A request leaves the device: its workspace returns to the arena, its footprint to the budget.
+void release(fge_server *s, Request *r) {
+    if (r->plan.ws_bytes) s->alloc.release(r->ws_off, r->plan.ws_bytes);
+    s->arena_used -= align256(r->plan.ws_bytes);
+    s->charged -= r->charge;
+}
+
+// The device has finished slot si at ready_ms: complete its requests and free the slot.
+void retire(fge_server *s, int si, double ready_ms) {
+    fge::serve::Slot &sl = s->slots[si];
     std::vector<fge_server_result> out;
     for (Request *r : sl.finishing) {
-        fge_server_result res{};
-        res.id = r->id;
-        res.status = ok ? FGE_OK : FGE_EHIP;
-        res.ticks = r->ticks;
-        res.submit_ms = r->submit_ms;
-        res.admit_ms = r->admit_ms;
-        res.ready_ms = ms;
-        res.latency_ms = ms - r->submit_ms;
-        out.push_back(res);
-        if (r->plan.ws_bytes) s->alloc.release(r->ws_off, r->plan.ws_bytes);
-        s->arena_used -= align256(r->plan.ws_bytes);
-        s->charged -= r->charge;
+        out.push_back(make_result(r, FGE_OK, ready_ms));
+        release(s, r);
         delete r;
     }
     sl.finishing.clear();
     s->free_slots.push_back(si);
     publish(s, out);
-    return ok ? FGE_OK : FGE_EHIP;
 }
 
 // Retire every finished tick in order; with `block`, wait for the oldest one first.
 fge_status retire_done(fge_server *s, bool block) {
     while (!s->inflight.empty()) {
         const int si = s->inflight.front();
-        hipError_t e = block ? hipEventSynchronize(s->slots[si].done) : hipEventQuery(s->slots[si].done);
-        if (e == hipErrorNotReady) return FGE_OK;
-        if (e != hipSuccess) return FGE_EHIP;
+        double ready = 0.0;
+        const int r = s->exec->poll(si, block, &ready);
+        if (r == 0) return FGE_OK;
+        if (r < 0) return static_cast<fge_status>(r);
         s->inflight.pop_front();
         block = false;
-        const fge_status st = retire(s, si);
-        if (st != FGE_OK) return st;
+        retire(s, si, ready);
     }
     return FGE_OK;
 }
 
 void admit(fge_server *s) {
     const size_t max_active = static_cast<size_t>(s->cfg.max_active);
+    std::lock_guard<std::mutex> g(s->mu);
     while (!s->pending.empty() && s->active.size() < max_active) {
         Request *r = s->pending.front();
         if (s->charged + r->charge > s->budget) break;
         size_t off = 0;
         if (r->plan.ws_bytes && !s->alloc.alloc(r->plan.ws_bytes, &off)) break;
         r->ws_off = off;
-        r->admit_ms = s->now_ms();
+        r->admit_ms = s->exec->now_ms();
         const bool busy = !s->active.empty() || !s->inflight.empty();
         s->charged += r->charge;
         s->arena_used += align256(r->plan.ws_bytes);
         s->pending.pop_front();
         s->active.push_back(r);
-        std::lock_guard<std::mutex> g(s->mu);
         if (busy) ++s->stats.admitted_while_busy;
         s->stats.peak_active = std::max<int32_t>(s->stats.peak_active, static_cast<int32_t>(s->active.size()));
         s->stats.peak_charged_bytes = std::max<uint64_t>(s->stats.peak_charged_bytes, s->charged);
@@ -273,10 +530,26 @@ void admit(fge_server *s) {
     }
 }
 
-// Build and enqueue one tick in a free slot.
+// A tick whose launch failed: its requests fail with the error and leave the server, the rest go
+// on.  Everything already enqueued is waited for first, so no launch still uses their memory.
+void fail_tick(fge_server *s, const std::vector<Request *> &ran, int err) {
+    s->exec->quiesce();
+    const double now = s->exec->now_ms();
+    std::vector<fge_server_result> out;
+    for (Request *r : ran) {
+        out.push_back(make_result(r, err, now));
+        release(s, r);
+        s->active.erase(std::remove(s->active.begin(), s->active.end(), r), s->active.end());
+        delete r;
+    }
+    publish(s, out, static_cast<int64_t>(ran.size()));
+}
+
+// Build one tick in a free slot and hand it to the executor.  A failed launch fails the tick's
+// requests only (fail_tick) and returns FGE_OK; other errors are the server's.
 fge_status enqueue_tick(fge_server *s) {
     const int si = s->free_slots.back();
-    Slot &sl = s->slots[si];
+    fge::serve::Slot &sl = s->slots[si];
     const size_t cap = s->cfg.tick_table_bytes;
     // Strip height of this tick's streaming launch: the caller's, else one for all the streaming
     // levels the admitted requests run next.
@@ -335,7 +608,7 @@ fge_status enqueue_tick(fge_server *s) {
     std::stable_sort(stream.begin(), stream.end(), larger);
 
     // Lay out and fill the tables (staging image; counters at offset 0 stay zero).
-    char *tab = sl.staging;
+    char *tab = s->exec->staging(si);
     std::memset(tab, 0, 256);
     size_t off = 256;
     auto region = [&](size_t bytes) {
@@ -343,18 +616,19 @@ fge_status enqueue_tick(fge_server *s) {
         off = align256(off + bytes);
         return at;
     };
+    TickWork w;
     const float om = s->prm.omega, ep = s->prm.eps_r;
-    const size_t g_desc = region(gathered.size() * sizeof(fge::GatherArgs));
-    const size_t g_first = region(gathered.size() * sizeof(long long));
-    long long g_total = 0;
+    w.g_desc = region(gathered.size() * sizeof(fge::GatherArgs));
+    w.g_first = region(gathered.size() * sizeof(long long));
     for (size_t k = 0; k < gathered.size(); ++k) {
         Request *r = gathered[k];
-        auto *gd = reinterpret_cast<fge::GatherArgs *>(tab + g_desc) + k;
+        auto *gd = reinterpret_cast<fge::GatherArgs *>(tab + w.g_desc) + k;
         fge::make_gather_args(r->plan, r->I, r->A, s->arena + r->ws_off + r->plan.pyr_off, gd);
-        reinterpret_cast<long long *>(tab + g_first)[k] = g_total;
-        g_total += fge::gather_units(*gd);
+        reinterpret_cast<long long *>(tab + w.g_first)[k] = w.g_total;
+        w.g_total += fge::gather_units(*gd);
     }
-    const size_t c_desc = region(fresh.size() * sizeof(fge::CoarseArgs));
+    w.n_gather = static_cast<int>(gathered.size());
+    w.c_desc = region(fresh.size() * sizeof(fge::CoarseArgs));
     for (size_t k = 0; k < fresh.size(); ++k) {
         Request *r = fresh[k];
         char *ws = s->arena + r->ws_off;
@@ -362,72 +636,39 @@ fge_status enqueue_tick(fge_server *s) {
         void *fo, *bo;
         fge::level_state(r->plan, ws, r->plan.nc - 1, r->F, r->B, &fo, &bo);
         fge::make_coarse_args(r->plan, src, fo, bo, om, ep,
-                              reinterpret_cast<fge::CoarseArgs *>(tab + c_desc) + k);
+                              reinterpret_cast<fge::CoarseArgs *>(tab + w.c_desc) + k);
     }
-    struct Lay {
-        size_t desc, items;
-        int nitems;
-    };
-    auto lay_out = [&](const std::vector<Entry> &es, bool is_tile) {
-        Lay L{};
-        L.desc = region(es.size() * (is_tile ? sizeof(fge::TileArgs) : sizeof(fge::FineArgs)));
+    w.n_coarse = static_cast<int>(fresh.size());
+    auto lay_out = [&](const std::vector<Entry> &es, bool is_tile, size_t *desc, size_t *items_at) {
+        *desc = region(es.size() * (is_tile ? sizeof(fge::TileArgs) : sizeof(fge::FineArgs)));
         size_t nit = 0;
         for (const Entry &e : es) nit += static_cast<size_t>(e.units);
-        L.items = region(nit * sizeof(fge::WorkItem));
-        auto *items = reinterpret_cast<fge::WorkItem *>(tab + L.items);
+        *items_at = region(nit * sizeof(fge::WorkItem));
+        auto *items = reinterpret_cast<fge::WorkItem *>(tab + *items_at);
         int m = 0;
         for (size_t d = 0; d < es.size(); ++d) {
             Request *r = es[d].r;
             const fge::LevelIO io = fge::level_io(r->plan, s->arena + r->ws_off, es[d].j, r->I, r->A,
                                                   r->F, r->B, om, ep);
             if (is_tile)
-                fge::make_tile_args(io, reinterpret_cast<fge::TileArgs *>(tab + L.desc) + d);
+                fge::make_tile_args(io, reinterpret_cast<fge::TileArgs *>(tab + *desc) + d);
             else
-                fge::make_fine_args(io, strip_rows, reinterpret_cast<fge::FineArgs *>(tab + L.desc) + d);
+                fge::make_fine_args(io, strip_rows, reinterpret_cast<fge::FineArgs *>(tab + *desc) + d);
             for (int u = 0; u < es[d].units; ++u) items[m++] = fge::WorkItem{static_cast<int>(d), u};
+            w.px += es[d].px;
         }
-        L.nitems = m;
-        return L;
+        return m;
     };
-    const Lay lt = lay_out(tile, true);
-    const Lay ls = lay_out(stream, false);
-    const size_t used = off;
+    w.t_n = lay_out(tile, true, &w.t_desc, &w.t_items);
+    w.s_n = lay_out(stream, false, &w.s_desc, &w.s_items);
+    w.bytes = off;
 
-    // Enqueue: upload, gather, coarse, tile, streaming, event.
-    hipStream_t st = s->stream;
-    char *dev = s->arena + sl.dev_off;
-    const int storage = s->prm.storage;
-    if (hipMemcpyAsync(dev, tab, used, hipMemcpyHostToDevice, st) != hipSuccess) return FGE_EHIP;
-    int *cnt = reinterpret_cast<int *>(dev);
     int launches = 0;
-    if (!gathered.empty()) {
-        if (fge::launch_gather_batch(reinterpret_cast<const fge::GatherArgs *>(dev + g_desc),
-                                     reinterpret_cast<const long long *>(dev + g_first),
-                                     static_cast<int>(gathered.size()), g_total, storage, st))
-            return FGE_EHIP;
-        ++launches;
+    const fge_status st = s->exec->launch(si, s->arena + sl.dev_off, w, &launches);
+    if (st != FGE_OK) {
+        fail_tick(s, ran, st);
+        return FGE_OK;
     }
-    if (!fresh.empty()) {
-        if (fge::launch_coarse_batch(reinterpret_cast<const fge::CoarseArgs *>(dev + c_desc),
-                                     static_cast<int>(fresh.size()), storage, st))
-            return FGE_EHIP;
-        ++launches;
-    }
-    if (lt.nitems > 0) {
-        if (fge::launch_tile_batch(reinterpret_cast<const fge::TileArgs *>(dev + lt.desc),
-                                   reinterpret_cast<const fge::WorkItem *>(dev + lt.items),
-                                   lt.nitems, cnt, storage, st))
-            return FGE_EHIP;
-        ++launches;
-    }
-    if (ls.nitems > 0) {
-        if (fge::launch_fine_batch(reinterpret_cast<const fge::FineArgs *>(dev + ls.desc),
-                                   reinterpret_cast<const fge::WorkItem *>(dev + ls.items),
-                                   ls.nitems, cnt + 1, storage, st))
-            return FGE_EHIP;
-        ++launches;
-    }
-    if (hipEventRecord(sl.done, st) != hipSuccess) return FGE_EHIP;
     s->free_slots.pop_back();
     s->inflight.push_back(si);
 
@@ -458,20 +699,17 @@ fge_status enqueue_tick(fge_server *s) {
     return FGE_OK;
 }
 
-// After a failure: every request not yet completed completes with the error.
+// After an error of the device itself: every request not yet completed completes with the error,
+// and the server accepts nothing more.
 void fail_all(fge_server *s, int err) {
     std::vector<fge_server_result> out;
+    const double now = s->exec->now_ms();
     auto fail = [&](Request *r) {
-        fge_server_result res{};
-        res.id = r->id;
-        res.status = err;
-        res.ticks = r->ticks;
-        res.submit_ms = r->submit_ms;
-        res.admit_ms = r->admit_ms;
+        fge_server_result res = make_result(r, err, now);
         out.push_back(res);
         delete r;
     };
-    (void)hipStreamSynchronize(s->stream);
+    s->exec->quiesce();
     for (int si : s->inflight) {
         for (Request *r : s->slots[si].finishing) fail(r);
         s->slots[si].finishing.clear();
@@ -480,55 +718,87 @@ void fail_all(fge_server *s, int err) {
     s->inflight.clear();
     for (Request *r : s->active) fail(r);
     s->active.clear();
-    for (Request *r : s->pending) fail(r);
-    s->pending.clear();
     {
         std::lock_guard<std::mutex> g(s->mu);
         s->error = err;
+        for (Request *r : s->pending) fail(r);
+        s->pending.clear();
         for (Request *r : s->incoming) fail(r);
         s->incoming.clear();
     }
-    publish(s, out);
+    publish(s, out, static_cast<int64_t>(out.size()));
+}
+
+// One pass of the scheduler: take new submissions, retire finished ticks, admit, enqueue one
+// tick.  kBusy: requests wait for the device (no free slot, or ticks in flight).
+enum Pass { kIdle, kProgress, kBusy, kFatal };
+
+Pass pass(fge_server *s) {
+    {
+        std::lock_guard<std::mutex> g(s->mu);
+        while (!s->incoming.empty()) {
+            s->pending.push_back(s->incoming.front());
+            s->incoming.pop_front();
+        }
+    }
+    fge_status st = retire_done(s, false);
+    if (st != FGE_OK) {
+        fail_all(s, st);
+        return kFatal;
+    }
+    admit(s);
+    if (!s->active.empty()) {
+        if (s->free_slots.empty()) return kBusy;
+        st = enqueue_tick(s);
+        if (st != FGE_OK) {
+            fail_all(s, st);
+            return kFatal;
+        }
+        return kProgress;
+    }
+    if (!s->inflight.empty()) return kBusy;
+    bool waiting;
+    {
+        std::lock_guard<std::mutex> g(s->mu);
+        waiting = !s->pending.empty();
+    }
+    if (waiting) {   // idle device, empty arena, and the head does not fit:
+        fail_all(s, FGE_EBUDGET);   // excluded by the checks in fge_server_submit
+        return kFatal;
+    }
+    return kIdle;
+}
+
+void wait_for_stop(fge_server *s) {
+    std::unique_lock<std::mutex> g(s->mu);
+    s->cv_work.wait(g, [&] { return s->stop; });
 }
 
 void worker_main(fge_server *s) {
-    if (hipSetDevice(s->device) != hipSuccess) {
+    if (s->exec->bind_thread() != FGE_OK) {
         fail_all(s, FGE_EHIP);
-        std::unique_lock<std::mutex> g(s->mu);
-        s->cv_work.wait(g, [&] { return s->stop; });
+        wait_for_stop(s);
         return;
     }
     for (;;) {
-        {
-            std::lock_guard<std::mutex> g(s->mu);
-            while (!s->incoming.empty()) {
-                s->pending.push_back(s->incoming.front());
-                s->incoming.pop_front();
-            }
-        }
-        fge_status st = retire_done(s, false);
-        if (st == FGE_OK) {
-            admit(s);
-            if (!s->active.empty()) {
-                st = s->free_slots.empty() ? retire_done(s, true) : enqueue_tick(s);
-                if (st == FGE_OK) continue;
-            }
-        }
-        if (st != FGE_OK) {
-            fail_all(s, st);
-            std::unique_lock<std::mutex> g(s->mu);
-            s->cv_work.wait(g, [&] { return s->stop; });
+        const Pass r = pass(s);
+        if (r == kFatal) {
+            wait_for_stop(s);
             return;
         }
-        if (!s->inflight.empty()) {   // the device is busy and nothing can be enqueued: poll
-            std::this_thread::yield();
+        if (r == kProgress) continue;
+        if (r == kBusy) {
+            if (!s->active.empty() && s->free_slots.empty()) {   // wait for the oldest tick
+                const fge_status st = retire_done(s, true);
+                if (st != FGE_OK) {
+                    fail_all(s, st);
+                    wait_for_stop(s);
+                    return;
+                }
+            } else {
+                std::this_thread::yield();   // ticks in flight, nothing to enqueue: poll
+            }
             continue;
-        }
-        if (!s->pending.empty()) {    // idle device, empty arena, and the head does not fit:
-            fail_all(s, FGE_EBUDGET); // excluded by the checks in fge_server_submit
-            std::unique_lock<std::mutex> g(s->mu);
-            s->cv_work.wait(g, [&] { return s->stop; });
-            return;
         }
         std::unique_lock<std::mutex> g(s->mu);
         if (s->stop && s->incoming.empty() && s->pending.empty()) return;
@@ -541,6 +811,63 @@ fge_status request_plan(const fge_params &p, int W, int H, fge::Plan *pl) {
     if (st != FGE_OK) return st;
     return batchable(*pl);
 }
+
+// Checks shared by both kinds of server; fills *prm and *cfg with the defaults applied.
+fge_status check_config(const fge_params *p, const fge_server_config *c, size_t arena_bytes,
+                        fge_params *prm, fge_server_config *cfg) {
+    if (p) *prm = *p; else fge_default_params(prm);
+    if (!fge::params_valid(*prm)) return FGE_EINVAL;
+    if (prm->kernel == FGE_KERNEL_NAIVE || prm->coarse_max_px < 0 || prm->iters_big != 2 ||
+        prm->order != FGE_REDBLACK)
+        return FGE_EUNSUPPORTED;
+    if (c) *cfg = *c; else fge_server_default_config(cfg);
+    if (cfg->size != sizeof(fge_server_config)) return FGE_EINVAL;
+    if (cfg->max_active == 0) cfg->max_active = kDefaultMaxActive;
+    if (cfg->pipeline_depth == 0) cfg->pipeline_depth = kDefaultDepth;
+    if (cfg->tick_table_bytes == 0) cfg->tick_table_bytes = kDefaultTableBytes;
+    if (cfg->max_active < 1 || cfg->max_active > (1 << 16) || cfg->pipeline_depth < 1 ||
+        cfg->pipeline_depth > kMaxDepth || cfg->tick_table_bytes < kMinTableBytes ||
+        cfg->tick_table_bytes > (1ull << 32))
+        return FGE_EINVAL;
+    cfg->tick_table_bytes = align256(cfg->tick_table_bytes);
+    if (arena_bytes <= fge_server_reserved_bytes(cfg)) return FGE_EWORKSPACE;
+    if (cfg->budget_bytes == 0) cfg->budget_bytes = arena_bytes;
+    return FGE_OK;
+}
+
+fge_status create_with(const fge_params &prm, const fge_server_config &cfg, char *arena,
+                       size_t arena_bytes, std::unique_ptr<fge::serve::Executor> exec,
+                       fge::serve::SimExecutor *sim, bool manual, fge_server **out) {
+    fge_server *s = new (std::nothrow) fge_server();
+    if (!s) return FGE_ENOMEM;
+    s->prm = prm;
+    s->cfg = cfg;
+    s->arena = arena;
+    s->arena_bytes = arena_bytes;
+    s->reserved = fge_server_reserved_bytes(&cfg);
+    s->budget = cfg.budget_bytes;
+    s->exec = std::move(exec);
+    s->sim = sim;
+    s->manual = manual;
+    s->alloc.init(s->reserved, (arena_bytes - s->reserved) & ~static_cast<size_t>(255));
+    s->slots.resize(cfg.pipeline_depth);
+    for (int k = 0; k < cfg.pipeline_depth; ++k) {
+        s->slots[k].dev_off = static_cast<size_t>(k) * cfg.tick_table_bytes;
+        s->free_slots.push_back(cfg.pipeline_depth - 1 - k);
+    }
+    if (s->exec->init(cfg.pipeline_depth, cfg.tick_table_bytes) != FGE_OK ||
+        s->exec->start_clock() != FGE_OK) {
+        fge_server_destroy(s);
+        return FGE_EHIP;
+    }
+    if (!manual) s->worker = std::thread(worker_main, s);
+    *out = s;
+    return FGE_OK;
+}
+
+// Base address of a simulated server's arena: a range of the address space no host or device
+// allocation uses, never dereferenced (descriptors are built but nothing runs).
+char *const kSimArena = reinterpret_cast<char *>(static_cast<uintptr_t>(1) << 46);
 
 }  // namespace
 
@@ -577,59 +904,65 @@ fge_status fge_server_create(const fge_params *p, const fge_server_config *c, vo
     if (!out) return FGE_EINVAL;
     *out = nullptr;
     fge_params prm;
-    if (p) prm = *p; else fge_default_params(&prm);
-    if (!fge::params_valid(prm)) return FGE_EINVAL;
-    if (prm.kernel == FGE_KERNEL_NAIVE || prm.coarse_max_px < 0 || prm.iters_big != 2 ||
-        prm.order != FGE_REDBLACK)
-        return FGE_EUNSUPPORTED;
     fge_server_config cfg;
-    if (c) cfg = *c; else fge_server_default_config(&cfg);
-    if (cfg.size != sizeof(fge_server_config)) return FGE_EINVAL;
-    if (cfg.max_active == 0) cfg.max_active = kDefaultMaxActive;
-    if (cfg.pipeline_depth == 0) cfg.pipeline_depth = kDefaultDepth;
-    if (cfg.tick_table_bytes == 0) cfg.tick_table_bytes = kDefaultTableBytes;
-    if (cfg.max_active < 1 || cfg.max_active > (1 << 16) || cfg.pipeline_depth < 1 ||
-        cfg.pipeline_depth > kMaxDepth || cfg.tick_table_bytes < kMinTableBytes ||
-        cfg.tick_table_bytes > (1ull << 32))
-        return FGE_EINVAL;
-    cfg.tick_table_bytes = align256(cfg.tick_table_bytes);
+    const fge_status st = check_config(p, c, arena_bytes, &prm, &cfg);
+    if (st != FGE_OK) return st;
     if (!arena || (reinterpret_cast<uintptr_t>(arena) & 255) || !stream) return FGE_EINVAL;
-    const size_t reserved = fge_server_reserved_bytes(&cfg);
-    if (arena_bytes <= reserved) return FGE_EWORKSPACE;
-    if (cfg.budget_bytes == 0) cfg.budget_bytes = arena_bytes;
+    std::unique_ptr<fge::serve::Executor> exec(
+        new (std::nothrow) fge::serve::HipExecutor(static_cast<hipStream_t>(stream), prm.storage));
+    if (!exec) return FGE_ENOMEM;
+    return create_with(prm, cfg, static_cast<char *>(arena), arena_bytes, std::move(exec), nullptr,
+                       false, out);
+}
 
-    fge_server *s = new (std::nothrow) fge_server();
-    if (!s) return FGE_ENOMEM;
-    s->prm = prm;
-    s->cfg = cfg;
-    s->arena = static_cast<char *>(arena);
-    s->arena_bytes = arena_bytes;
-    s->reserved = reserved;
-    s->budget = cfg.budget_bytes;
-    s->stream = static_cast<hipStream_t>(stream);
-    s->alloc.init(reserved, (arena_bytes - reserved) & ~static_cast<size_t>(255));
-    bool ok = hipGetDevice(&s->device) == hipSuccess && hipEventCreate(&s->start_ev) == hipSuccess;
-    s->slots.resize(cfg.pipeline_depth);
-    for (int k = 0; ok && k < cfg.pipeline_depth; ++k) {
-        Slot &sl = s->slots[k];
-        sl.dev_off = static_cast<size_t>(k) * cfg.tick_table_bytes;
-        ok = hipHostMalloc(reinterpret_cast<void **>(&sl.staging), cfg.tick_table_bytes,
-                           hipHostMallocDefault) == hipSuccess &&
-             hipEventCreate(&sl.done) == hipSuccess;
-        s->free_slots.push_back(cfg.pipeline_depth - 1 - k);
+void fge_server_sim_default(fge_server_sim *m) {
+    if (!m) return;
+    std::memset(m, 0, sizeof(*m));
+    m->size = sizeof(fge_server_sim);
+    m->manual = 1;
+    m->us_per_launch = 3.0;
+    m->us_per_mpx = 8.0;
+}
+
+fge_status fge_server_create_simulated(const fge_params *p, const fge_server_config *c,
+                                       size_t arena_bytes, const fge_server_sim *m,
+                                       fge_server **out) {
+    if (!out) return FGE_EINVAL;
+    *out = nullptr;
+    fge_server_sim sim;
+    if (m) sim = *m; else fge_server_sim_default(&sim);
+    if (sim.size != sizeof(fge_server_sim) || (sim.manual != 0 && sim.manual != 1) ||
+        !(sim.us_per_launch >= 0.0) || !(sim.us_per_mpx >= 0.0) || sim.fail_launch_tick < 0 ||
+        sim.fail_device_tick < 0)
+        return FGE_EINVAL;
+    if (arena_bytes > (static_cast<size_t>(1) << 45)) return FGE_EINVAL;
+    fge_params prm;
+    fge_server_config cfg;
+    const fge_status st = check_config(p, c, arena_bytes, &prm, &cfg);
+    if (st != FGE_OK) return st;
+    auto *sx = new (std::nothrow) fge::serve::SimExecutor(sim);
+    if (!sx) return FGE_ENOMEM;
+    return create_with(prm, cfg, kSimArena, arena_bytes, std::unique_ptr<fge::serve::Executor>(sx),
+                       sx, sim.manual == 1, out);
+}
+
+int32_t fge_server_sim_step(fge_server *s, int32_t complete, double advance_ms) {
+    if (!s || !s->manual || complete < 0 || !(advance_ms >= 0.0)) return FGE_EINVAL;
+    std::lock_guard<std::mutex> step(s->step_mu);
+    s->sim->step(complete, advance_ms);
+    int32_t enqueued = 0;
+    for (;;) {
+        const Pass r = pass(s);
+        if (r == kFatal) return static_cast<int32_t>(s->error);
+        if (r != kProgress) break;
+        ++enqueued;
     }
-    // Time origin: the start event on the idle stream, and the host clock right after it.
-    ok = ok && hipStreamSynchronize(s->stream) == hipSuccess &&
-         hipEventRecord(s->start_ev, s->stream) == hipSuccess &&
-         hipEventSynchronize(s->start_ev) == hipSuccess;
-    if (!ok) {
-        fge_server_destroy(s);
-        return FGE_EHIP;
-    }
-    s->t0 = Clock::now();
-    s->worker = std::thread(worker_main, s);
-    *out = s;
-    return FGE_OK;
+    return enqueued;
+}
+
+int32_t fge_server_sim_inflight(fge_server *s) {
+    if (!s || !s->sim) return FGE_EINVAL;
+    return s->sim->outstanding();
 }
 
 fge_status fge_server_submit(fge_server *s, int64_t id, const void *I, const void *alpha,
@@ -657,7 +990,7 @@ fge_status fge_server_submit(fge_server *s, int64_t id, const void *I, const voi
     r->A = alpha;
     r->F = F;
     r->B = B;
-    r->submit_ms = s->now_ms();
+    r->submit_ms = s->exec->now_ms();
     std::lock_guard<std::mutex> g(s->mu);
     if (s->error != FGE_OK) {
         delete r;
@@ -674,6 +1007,26 @@ fge_status fge_server_submit(fge_server *s, int64_t id, const void *I, const voi
     return FGE_OK;
 }
 
+fge_status fge_server_cancel(fge_server *s, int64_t id) {
+    if (!s) return FGE_EINVAL;
+    std::lock_guard<std::mutex> g(s->mu);
+    for (std::deque<Request *> *q : {&s->incoming, &s->pending}) {
+        for (auto it = q->begin(); it != q->end(); ++it) {
+            if ((*it)->id != id) continue;
+            Request *r = *it;
+            q->erase(it);
+            s->results.push_back(make_result(r, FGE_ECANCELED, s->exec->now_ms()));
+            ++s->completed;
+            s->stats.completed = s->completed;
+            ++s->stats.cancelled;
+            s->cv_idle.notify_all();
+            delete r;
+            return FGE_OK;
+        }
+    }
+    return FGE_EINVAL;   // unknown, already admitted, or completed
+}
+
 int32_t fge_server_poll(fge_server *s, fge_server_result *out, int32_t cap) {
     if (!s || (cap > 0 && !out) || cap < 0) return FGE_EINVAL;
     std::lock_guard<std::mutex> g(s->mu);
@@ -688,6 +1041,19 @@ int32_t fge_server_poll(fge_server *s, fge_server_result *out, int32_t cap) {
 
 fge_status fge_server_drain(fge_server *s) {
     if (!s) return FGE_EINVAL;
+    if (s->manual) {
+        // The caller's thread is the scheduler: complete ticks until everything is done.
+        for (;;) {
+            {
+                std::lock_guard<std::mutex> g(s->mu);
+                if (s->completed >= s->submitted) return static_cast<fge_status>(s->error);
+            }
+            const int32_t inflight = s->sim->outstanding();
+            const int32_t r = fge_server_sim_step(s, inflight, 0.0);
+            if (r < 0) return static_cast<fge_status>(r);
+            if (r == 0 && inflight == 0) return FGE_EINVAL;   // nothing can move (cannot happen)
+        }
+    }
     std::unique_lock<std::mutex> g(s->mu);
     s->cv_idle.wait(g, [&] { return s->completed >= s->submitted; });
     return static_cast<fge_status>(s->error);
@@ -710,12 +1076,14 @@ void fge_server_destroy(fge_server *s) {
             s->cv_work.notify_all();
         }
         s->worker.join();
+    } else if (s->manual && s->exec) {
+        fge_server_drain(s);
     }
-    for (Slot &sl : s->slots) {
-        if (sl.done) (void)hipEventDestroy(sl.done);
-        if (sl.staging) (void)hipHostFree(sl.staging);
-    }
-    if (s->start_ev) (void)hipEventDestroy(s->start_ev);
+    for (fge::serve::Slot &sl : s->slots)
+        for (Request *r : sl.finishing) delete r;
+    for (Request *r : s->active) delete r;
+    for (Request *r : s->pending) delete r;
+    for (Request *r : s->incoming) delete r;
     delete s;
 }
 

@@ -17,7 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libfge.so")
 
 FGE_OK, FGE_EINVAL, FGE_ENOMEM, FGE_EHIP, FGE_EUNSUPPORTED, FGE_EWORKSPACE = 0, -1, -2, -3, -4, -5
-FGE_EBUDGET = -6
+FGE_EBUDGET, FGE_ECANCELED = -6, -7
 F32, F16, U8, F64 = 0, 1, 2, 3
 REDBLACK, JACOBI = 0, 1
 KERNEL_AUTO, KERNEL_FUSED, KERNEL_NAIVE = 0, 1, 2
@@ -130,6 +130,19 @@ class ServerStats(ctypes.Structure):
         ("peak_charged_bytes", ctypes.c_uint64),
         ("peak_arena_bytes", ctypes.c_uint64),
         ("mean_active", ctypes.c_double),
+        ("failed", ctypes.c_int64),
+        ("cancelled", ctypes.c_int64),
+    ]
+
+
+class ServerSim(ctypes.Structure):
+    _fields_ = [
+        ("size", ctypes.c_uint32),
+        ("manual", ctypes.c_int32),
+        ("us_per_launch", ctypes.c_double),
+        ("us_per_mpx", ctypes.c_double),
+        ("fail_launch_tick", ctypes.c_int32),
+        ("fail_device_tick", ctypes.c_int32),
     ]
 
 
@@ -258,6 +271,17 @@ def _lib():
     lib.fge_server_get_stats.restype = ctypes.c_int
     lib.fge_server_destroy.argtypes = [vp]
     lib.fge_server_destroy.restype = None
+    lib.fge_server_cancel.argtypes = [vp, ctypes.c_int64]
+    lib.fge_server_cancel.restype = ctypes.c_int
+    simp = ctypes.POINTER(ServerSim)
+    lib.fge_server_sim_default.argtypes = [simp]
+    lib.fge_server_sim_default.restype = None
+    lib.fge_server_create_simulated.argtypes = [pp, cp, sz, simp, ctypes.POINTER(ctypes.c_void_p)]
+    lib.fge_server_create_simulated.restype = ctypes.c_int
+    lib.fge_server_sim_step.argtypes = [vp, i32, ctypes.c_double]
+    lib.fge_server_sim_step.restype = i32
+    lib.fge_server_sim_inflight.argtypes = [vp]
+    lib.fge_server_sim_inflight.restype = i32
     _LIB = lib
     return lib
 
@@ -570,6 +594,17 @@ def server_reserved_bytes(config: ServerConfig | None = None) -> int:
     return _lib().fge_server_reserved_bytes(ctypes.byref(config) if config else None)
 
 
+def server_sim(**overrides) -> ServerSim:
+    """fge_server_sim_default with optional overrides, e.g. ``server_sim(fail_launch_tick=3)``."""
+    m = ServerSim()
+    _lib().fge_server_sim_default(ctypes.byref(m))
+    for k, v in overrides.items():
+        if not hasattr(m, k):
+            raise KeyError(k)
+        setattr(m, k, v)
+    return m
+
+
 class Server:
     """Continuous-batching request server (fge_server_*).  `arena` is a CUDA uint8 tensor the
     server carves its tick tables and the requests' workspaces from; `stream` the torch stream
@@ -619,6 +654,46 @@ class Server:
     def submit_ptrs(self, rid: int, I: int, alpha: int, H: int, W: int, F: int, B: int):
         """Raw form: device addresses the caller keeps alive until the request completes."""
         _check(_lib().fge_server_submit(self._h, rid, I, alpha, H, W, F, B), "fge_server_submit")
+
+    def cancel(self, rid: int) -> bool:
+        """Cancel a request still queued; False if it was admitted, completed or unknown."""
+        st = _lib().fge_server_cancel(self._h, rid)
+        if st not in (FGE_OK, FGE_EINVAL):
+            raise FgeError(st, "fge_server_cancel")
+        if st == FGE_OK:
+            self._held.pop(rid, None)
+        return st == FGE_OK
+
+    @classmethod
+    def simulated(cls, params: Params | None = None, config: ServerConfig | None = None,
+                  arena_bytes: int = 1 << 30, sim: ServerSim | None = None):
+        """A server on the host model of the device (fge_server_create_simulated): submit with
+        submit_ptrs (addresses are only stored), drive it with step() in manual mode."""
+        self = cls.__new__(cls)
+        self.params = params if params is not None else default_params()
+        self.config = config if config is not None else server_config()
+        self.stream = None
+        self.arena = None
+        self._held = {}
+        handle = ctypes.c_void_p()
+        _check(_lib().fge_server_create_simulated(ctypes.byref(self.params),
+                                                  ctypes.byref(self.config), arena_bytes,
+                                                  ctypes.byref(sim) if sim is not None else None,
+                                                  ctypes.byref(handle)),
+               "fge_server_create_simulated")
+        self._h = handle
+        return self
+
+    def step(self, complete: int = 0, advance_ms: float = 0.0) -> int:
+        """Manual simulated server: complete the oldest `complete` ticks, run the scheduler;
+        returns the ticks it enqueued (raises if the server has failed)."""
+        n = _lib().fge_server_sim_step(self._h, complete, advance_ms)
+        if n < 0:
+            raise FgeError(n, "fge_server_sim_step")
+        return n
+
+    def inflight(self) -> int:
+        return _lib().fge_server_sim_inflight(self._h)
 
     def poll(self, cap: int = 4096):
         """Completed requests since the last poll: a list of ServerResult records."""

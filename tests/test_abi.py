@@ -44,7 +44,7 @@ def test_params_layout_and_defaults(fge):
     assert abs(p.omega - 0.1) < 1e-7 and abs(p.eps_r - 5e-3) < 1e-9
     assert (p.small_size, p.iters_small, p.iters_big) == (32, 10, 2)
     assert (p.storage, p.order, p.kernel, p.strip_rows, p.coarse_max_px, p.tile_max_px) == (0,) * 6
-    assert fge.load().fge_version() == 6
+    assert fge.load().fge_version() == 7
 
 
 def test_plan_matches_golden(fge):
@@ -183,7 +183,7 @@ def test_server_host_functions(fge):
     """Server configuration, footprints and argument errors (no device call is reached)."""
     assert ctypes.sizeof(fge.ServerConfig) == 32
     assert ctypes.sizeof(fge.ServerResult) == 48
-    assert ctypes.sizeof(fge.ServerStats) == 80
+    assert ctypes.sizeof(fge.ServerStats) == 96
     c = fge.server_config()
     assert (c.size, c.max_active, c.pipeline_depth, c.budget_bytes, c.tick_table_bytes) == \
         (32, 1024, 2, 0, 16 << 20)
