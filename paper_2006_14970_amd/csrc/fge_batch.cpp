@@ -281,7 +281,8 @@ fge_status fge_batch_create(int32_t n, const int32_t *H, const int32_t *W, const
         L.nitems = units;
         L.item_off = t;
         t = align256(t + static_cast<size_t>(units) * sizeof(fge::WorkItem));
-        L.counter = counter++;
+        L.counter = counter;
+        counter += fge::kQueueCounters;
     }
     b->tab_bytes = t;
     b->tab_off = off;

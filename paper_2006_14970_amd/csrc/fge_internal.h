@@ -253,7 +253,9 @@ fge_status estimate_converge(const void *I, const void *A, int W, int H, const f
                              double tol, int max_sweeps, void *F, void *B, int32_t *sweeps_out,
                              void *workspace, size_t workspace_bytes, void *stream);
 
-// Batched launches: descriptor tables, work lists and counters are device pointers.
+// Batched launches: descriptor tables, work lists and counters are device pointers.  Every
+// batched tile or streaming launch uses kQueueCounters counters (one work queue per XCD).
+constexpr int kQueueCounters = 8;
 int launch_zero(int *d, int n, void *stream);
 int launch_gather_batch(const GatherArgs *descs, const long long *first, int n, long long total,
                         int storage, void *stream);

@@ -254,7 +254,7 @@ class HipExecutor final : public Executor {
         hipStream_t st = stream_;
         if (hipMemcpyAsync(dev, slots_[slot].staging, w.bytes, hipMemcpyHostToDevice, st) != hipSuccess)
             return FGE_EHIP;
-        int *cnt = reinterpret_cast<int *>(dev);
+        int *cnt = reinterpret_cast<int *>(dev);   // the tile and the streaming launch's queues
         if (w.n_gather > 0) {
             if (launch_gather_batch(reinterpret_cast<const GatherArgs *>(dev + w.g_desc),
                                     reinterpret_cast<const long long *>(dev + w.g_first), w.n_gather,
@@ -277,7 +277,8 @@ class HipExecutor final : public Executor {
         }
         if (w.s_n > 0) {
             if (launch_fine_batch(reinterpret_cast<const FineArgs *>(dev + w.s_desc),
-                                  reinterpret_cast<const WorkItem *>(dev + w.s_items), w.s_n, cnt + 1,
+                                  reinterpret_cast<const WorkItem *>(dev + w.s_items), w.s_n,
+                                  cnt + kQueueCounters,
                                   storage_, st))
                 return FGE_EHIP;
             ++*launches;
