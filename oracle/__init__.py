@@ -87,6 +87,9 @@ def _load(parallel: bool = False):
     lib.fgo_ml_schedule.restype = i32
     lib.fgo_ml_converge.argtypes = [dp, dp, i32, i32, f64, f64, i32, f64, i32, ip, dp, dp]
     lib.fgo_ml_converge.restype = i32
+    lib.fgo_ml_converge_every.argtypes = [dp, dp, i32, i32, f64, f64, i32, i32, f64, i32, ip, dp,
+                                          i32, dp, dp]
+    lib.fgo_ml_converge_every.restype = i32
     lib.fgo_resize_area.argtypes = [dp, i32, i32, i32, dp, i32, i32]
     lib.fgo_resize_area.restype = None
     lib.fgo_resize_bilinear.argtypes = [dp, i32, i32, i32, dp, i32, i32]
@@ -215,6 +218,29 @@ def ml_converge(I: np.ndarray, alpha: np.ndarray, tol: float, max_sweeps: int,
     _load().fgo_ml_converge(_ptr(I), _ptr(a), W, H, float(omega), float(eps), ORDERS[order],
                             float(tol), int(max_sweeps), sw, _ptr(F), _ptr(B))
     return F, B, list(sw)
+
+
+def ml_converge_every(I: np.ndarray, alpha: np.ndarray, m: int, tol: float, max_checks: int,
+                      omega: float = 0.1, eps: float = 5e-3, order: str = "redblack",
+                      rel_cap: int = 0):
+    """The same loop condition tested every m sweeps: per level, groups of m sweeps until the
+    level energy changes over a group by at most tol (relative) or max_checks groups.  Returns
+    (F, B, groups per level) and, with rel_cap > 0, the relative energy change of each group
+    (levels x rel_cap, NaN past a level's last group)."""
+    I = _f64c(I)
+    a = _f64c(alpha)
+    _, H, W = I.shape
+    n = num_levels(W, H)
+    ch = (ctypes.c_int * n)()
+    F = np.empty((3, H, W), dtype=np.float64)
+    B = np.empty((3, H, W), dtype=np.float64)
+    rel = np.full((n, max(rel_cap, 1)), np.nan)
+    _load().fgo_ml_converge_every(_ptr(I), _ptr(a), W, H, float(omega), float(eps), ORDERS[order],
+                                  int(m), float(tol), int(max_checks), ch,
+                                  _ptr(rel) if rel_cap > 0 else None, int(rel_cap), _ptr(F), _ptr(B))
+    if rel_cap > 0:
+        return F, B, list(ch), rel
+    return F, B, list(ch)
 
 
 RESIZES = {"nearest": 0, "smooth": 1}

@@ -329,14 +329,18 @@ int fgo_ml_schedule(const double *I, const double *a, int W, int H, double omega
 }
 
 /*
- * Algorithm 1's "while not converged" form: at every level, after the resize, sweep until the
- * level's energy (fgo_energy of the level's F, B against its resized image and matte) changes by
- * at most tol times its value before the sweep, or until max_sweeps sweeps have run; at least one
- * sweep runs.  E before the first sweep is the energy of the resized start.  sweeps_out[l-1]
- * receives the sweeps level l ran.  Returns the number of levels.
+ * Algorithm 1's "while not converged" form, the test taken every m sweeps: at every level, after
+ * the resize, run m sweeps at a time until the level's energy (fgo_energy of the level's F, B
+ * against its resized image and matte) changes over those m sweeps by at most tol times its value
+ * before them, or until max_checks groups have run; at least one group runs.  E before the first
+ * group is the energy of the resized start.  checks_out[l-1] receives the groups level l ran.
+ * When rel_out is not NULL, rel_out[(l-1) * rel_cap + k] receives |E_k - E_(k+1)| / E_k of the
+ * (k+1)-th group of level l, for k < rel_cap (the quantity the stopping test compares with tol).
+ * Returns the number of levels.
  */
-int fgo_ml_converge(const double *I, const double *a, int W, int H, double omega, double eps,
-                    int order, double tol, int max_sweeps, int *sweeps_out, double *F, double *B)
+int fgo_ml_converge_every(const double *I, const double *a, int W, int H, double omega, double eps,
+                          int order, int m, double tol, int max_checks, int *checks_out,
+                          double *rel_out, int rel_cap, double *F, double *B)
 {
     const int n = fgo_num_levels(W, H);
     int wp = 1, hp = 1;
@@ -357,13 +361,17 @@ int fgo_ml_converge(const double *I, const double *a, int W, int H, double omega
         double e_prev = fgo_energy(Fl, Bl, Il, al, w, h, omega, eps);
         int k = 0;
         for (;;) {
-            fgo_sweep(Fl, Bl, Il, al, w, h, omega, eps, order);
-            k++;
+            for (int s = 0; s < m; s++)
+                fgo_sweep(Fl, Bl, Il, al, w, h, omega, eps, order);
             double e = fgo_energy(Fl, Bl, Il, al, w, h, omega, eps);
-            if (fabs(e_prev - e) <= tol * e_prev || k >= max_sweeps) break;
+            double rel = fabs(e_prev - e) / e_prev;
+            if (rel_out && k < rel_cap)
+                rel_out[(size_t)(l - 1) * rel_cap + k] = rel;
+            k++;
+            if (fabs(e_prev - e) <= tol * e_prev || k >= max_checks) break;
             e_prev = e;
         }
-        sweeps_out[l - 1] = k;
+        checks_out[l - 1] = k;
         free(Il);
         free(al);
         free(Fp);
@@ -378,6 +386,14 @@ int fgo_ml_converge(const double *I, const double *a, int W, int H, double omega
     free(Fp);
     free(Bp);
     return n;
+}
+
+/* The test after every sweep (m = 1): sweeps_out[l-1] receives the sweeps level l ran. */
+int fgo_ml_converge(const double *I, const double *a, int W, int H, double omega, double eps,
+                    int order, double tol, int max_sweeps, int *sweeps_out, double *F, double *B)
+{
+    return fgo_ml_converge_every(I, a, W, H, omega, eps, order, 1, tol, max_sweeps, sweeps_out,
+                                 NULL, 0, F, B);
 }
 
 /*

@@ -459,3 +459,47 @@ def test_openmp_build_bit_identical(oracle_mod):
             F1, B1 = oracle_mod.ml(s.I, s.alpha, order=order)
             F2, B2 = oracle_mod.ml(s.I, s.alpha, order=order, parallel=True)
             assert np.array_equal(F1, F2) and np.array_equal(B1, B2), (w, h, order)
+
+
+@pytest.mark.parametrize("order", ["redblack", "jacobi"])
+def test_converge_every_two_sweeps_by_hand(oracle_mod, order):
+    """The loop condition tested every 2 sweeps: the last level's group count is the first k with
+    |E_(k-1) - E_k| <= tol E_(k-1) over groups of two sweeps, found by running the pinned
+    single-level sweep and energy by hand from the level's start; the recorded relative changes
+    are those of the hand-run groups."""
+    from paper_2006_14970_amd import synth
+    s = synth.smooth(37, 29, seed=8)
+    tol = 1e-5
+    F, B, ch, rel = oracle_mod.ml_converge_every(s.I, s.alpha, 2, tol, 300, order=order,
+                                                 rel_cap=300)
+    n = oracle_mod.num_levels(37, 29)
+    # the level start: the earlier levels' groups as sweeps, none at the last level
+    F0, B0 = oracle_mod.ml_schedule(s.I, s.alpha, [2 * c for c in ch[:-1]] + [0], order=order)
+    e_prev = oracle_mod.energy(F0, B0, s.I, s.alpha)
+    Fk, Bk, k = F0, B0, 0
+    while True:
+        for _ in range(2):
+            Fk, Bk = oracle_mod.sweep(Fk, Bk, s.I, s.alpha, order=order)
+        k += 1
+        e = oracle_mod.energy(Fk, Bk, s.I, s.alpha)
+        assert rel[n - 1, k - 1] == pytest.approx(abs(e_prev - e) / e_prev, rel=1e-12)
+        if abs(e_prev - e) <= tol * e_prev or k >= 300:
+            break
+        e_prev = e
+    assert k == ch[-1] and k > 1
+    assert np.array_equal(Fk, F) and np.array_equal(Bk, B)
+    assert np.all(rel[:, :][~np.isnan(rel)] >= 0)
+    for lv, c in enumerate(ch):
+        assert rel[lv, c - 1] <= tol and np.all(rel[lv, :c - 1] > tol)
+
+
+def test_converge_every_limits(oracle_mod):
+    from paper_2006_14970_amd import synth
+    s = synth.smooth(50, 40, seed=9)
+    n = oracle_mod.num_levels(50, 40)
+    _, _, ch = oracle_mod.ml_converge_every(s.I, s.alpha, 2, 1e-12, 3)
+    assert ch == [3] * n                       # the cap, in groups
+    F, B, ch = oracle_mod.ml_converge_every(s.I, s.alpha, 2, 1.0, 100)
+    assert ch == [1] * n                       # one group always satisfies tol = 1
+    F1, B1 = oracle_mod.ml_schedule(s.I, s.alpha, [2] * n)
+    assert np.array_equal(F, F1) and np.array_equal(B, B1)
