@@ -103,10 +103,10 @@ void fge_default_params(fge_params *p);
 /* Human-readable name of a status code (static string). */
 const char *fge_status_string(int status);
 
-/* Library ABI version (increments when fge_params or a signature changes); this header is 7
+/* Library ABI version (increments when fge_params or a signature changes); this header is 8
  * (4 moved every size argument to height-first order, 5 added fge_estimate_foreground_noalloc,
  * 6 added the closed-form solve fge_closed_form, 7 the server's failure counters, cancellation
- * and simulated executor). */
+ * and simulated executor, 8 the convergence form in fused passes). */
 int32_t fge_version(void);
 
 /* ---- host-only planning (no GPU needed) ---------------------------------------------- */
@@ -159,6 +159,29 @@ fge_status fge_estimate_foreground(const void *I, const void *alpha, int32_t H, 
 #define FGE_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
 fge_status fge_estimate_foreground_noalloc(const void *I, const void *alpha, int32_t H, int32_t W,
                                            const fge_params *p, void *F, void *B, void *stream);
+
+/* Algorithm 1's "while not converged" form on the fused kernels, the test taken after every pass
+ * of two sweeps: every level runs passes of two red-black sweeps (one memory round trip each: the
+ * LDS tile kernel for levels up to p->tile_max_px, the streaming kernel above; the first pass
+ * resizes from the previous level), and stops when a pass changes the level's energy (fge_energy's
+ * quadratic on the level's F, B against its nearest-resized image and matte) by at most tol times
+ * its value before the pass -- before the first pass: the previous level's result as the resize
+ * leaves it -- or after max_passes passes (1..100000).  Each level thus runs an even number of
+ * sweeps; the CPU oracle's fgo_ml_converge_every with m = 2 is the same loop.  The energies are
+ * reduced on the device and read by the host, which keeps one pass in flight beyond the one it
+ * judges (that pass writes the other state buffer, so the accepted state is never overwritten):
+ * the call BLOCKS until the result is complete.  passes_out (HOST int array of >= n_levels
+ * entries, or NULL) receives the passes each level ran.  The state stays float32 between passes
+ * and levels (float16 inputs are converted once) and F, B are written in p->storage at the end.
+ * Red-black order only (FGE_EUNSUPPORTED for Jacobi).  Workspace:
+ * fge_converge_passes_workspace_bytes (three float32 states at full size, about 72 B/px, plus
+ * 16 B/px of float32 inputs in float16 storage). */
+size_t fge_converge_passes_workspace_bytes(int32_t H, int32_t W, const fge_params *p);
+fge_status fge_estimate_foreground_converge_passes(const void *I, const void *alpha, int32_t H,
+                                                   int32_t W, const fge_params *p, double tol,
+                                                   int32_t max_passes, void *F, void *B,
+                                                   int32_t *passes_out, void *workspace,
+                                                   size_t workspace_bytes, void *stream);
 
 /* Algorithm 1's level loop in its "while not converged" form: at every level, after the resize,
  * sweep (in p->order) until the level's energy -- fge_energy's quadratic on the level's F, B

@@ -22,6 +22,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdint>
 
 #include "fge_internal.h"
@@ -421,6 +422,161 @@ fge_status cv_run(const Plan &pl, const fge_params &p, const void *Iv, const voi
     return FGE_OK;
 }
 
+// ---- the convergence form in passes of two sweeps on the fused kernels -------------------------
+//
+// Every level runs passes of two red-black sweeps on the fused kernels (the LDS tile kernel for
+// levels up to tile_max_px, the streaming kernel above; one memory round trip per pass), the
+// first pass resizing from the previous level.  After each pass the level's energy is reduced on
+// the device and copied to the host, which stops the level when a pass changes it by at most tol
+// times its value before the pass (the energy before the first pass: the previous level's result
+// as the resize leaves it), or after max_passes passes.  The host keeps one pass in flight beyond
+// the one it decides on: that pass writes the other state buffer, so the accepted state is never
+// overwritten.  The state stays float32 from level to level (inputs in float16 storage are
+// converted once) and is converted to the storage type when the last level is done.
+
+struct CpLayout {
+    size_t st[3] = {0, 0, 0}, in = 0, zero = 0, edev = 0, part = 0, total = 0;
+};
+
+CpLayout cp_layout(int W, int H, int storage) {
+    CpLayout L;
+    const size_t n = static_cast<size_t>(W) * H;
+    size_t off = 0;
+    for (int k = 0; k < 3; ++k) {
+        L.st[k] = off;
+        off += a256(6 * n * sizeof(float));
+    }
+    L.in = off;
+    off += storage == FGE_F16 ? a256(4 * n * sizeof(float)) : 0;
+    L.zero = off;   // the 1 x 1 zero start (6 floats)
+    off += 256;
+    L.edev = off;   // two slots of fge_energy's 6 outputs
+    off += 256;
+    L.part = off;
+    off += a256(static_cast<size_t>(energy_blocks(W, H)) * 5 * sizeof(double));
+    L.total = off;
+    return L;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kCvThreads) void cp_to_f32_kernel(const T *I, const T *A, float *out,
+                                                               size_t n) {
+    for (size_t p = static_cast<size_t>(blockIdx.x) * kCvThreads + threadIdx.x; p < 4 * n;
+         p += static_cast<size_t>(gridDim.x) * kCvThreads)
+        out[p] = static_cast<float>(p < 3 * n ? I[p] : A[p - 3 * n]);
+}
+
+__global__ void cp_zero_kernel(float *z) {
+    if (threadIdx.x < 6) z[threadIdx.x] = 0.0f;
+}
+
+template <typename T>
+fge_status cp_run(const void *Iv, const void *Av, int W, int H, const fge_params &p, double tol,
+                  int max_passes, void *F, void *B, int32_t *passes_out, char *ws, hipStream_t s) {
+    const CpLayout L = cp_layout(W, H, p.storage);
+    const size_t N = static_cast<size_t>(W) * H;
+    const float *If = static_cast<const float *>(Iv), *Af = static_cast<const float *>(Av);
+    if (p.storage == FGE_F16) {
+        float *in = reinterpret_cast<float *>(ws + L.in);
+        hipLaunchKernelGGL(cp_to_f32_kernel<T>, dim3(blocks_for(4 * N)), dim3(kCvThreads), 0, s,
+                           static_cast<const T *>(Iv), static_cast<const T *>(Av), in, N);
+        If = in;
+        Af = in + 3 * N;
+    }
+    float *zero = reinterpret_cast<float *>(ws + L.zero);
+    hipLaunchKernelGGL(cp_zero_kernel, dim3(1), dim3(64), 0, s, zero);
+    if (hipGetLastError() != hipSuccess) return FGE_EHIP;
+    double *edev = reinterpret_cast<double *>(ws + L.edev);
+    double *part = reinterpret_cast<double *>(ws + L.part);
+    const long tile_max = p.tile_max_px == 0 ? kTileMaxPxDefault : (p.tile_max_px < 0 ? 0 : p.tile_max_px);
+
+    double *host = nullptr;   // pinned: the energies of the last two measurements
+    if (hipHostMalloc(reinterpret_cast<void **>(&host), 2 * sizeof(double), hipHostMallocDefault) != hipSuccess)
+        return FGE_ENOMEM;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    fge_status ret = FGE_OK;
+    if (hipEventCreateWithFlags(&ev[0], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&ev[1], hipEventDisableTiming) != hipSuccess)
+        ret = FGE_EHIP;
+
+    // measurement m (the energy before pass 1, then after pass m) into slot m % 2
+    auto measure = [&](int m, const float *Fs, int fw, int fh, int w, int h) {
+        const int sl = m & 1;
+        if (launch_energy_mapped(If, Af, W, H, Fs, Fs + 3 * static_cast<size_t>(fw) * fh, fw, fh, w,
+                                 h, p.omega, p.eps_r, FGE_F32, FGE_F32, nullptr, part, edev + 6 * sl,
+                                 s) ||
+            hipMemcpyAsync(host + sl, edev + 6 * sl, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipEventRecord(ev[sl], s) != hipSuccess)
+            ret = FGE_EHIP;
+    };
+    auto wait = [&](int m) {
+        if (ret == FGE_OK && hipEventSynchronize(ev[m & 1]) != hipSuccess) ret = FGE_EHIP;
+        return host[m & 1];
+    };
+
+    const int n = num_levels(W, H);
+    int prev = -1, wp = 1, hp = 1;   // the accepted state: buffer index (-1: the zero start), size
+    for (int j = 0; j < n && ret == FGE_OK; ++j) {
+        const int w = level_size(W, j + 1, n), h = level_size(H, j + 1, n);
+        int outs[2], m = 0;
+        for (int k = 0; k < 3; ++k)
+            if (k != prev && m < 2) outs[m++] = k;
+        auto state = [&](int k) { return reinterpret_cast<float *>(ws + L.st[k]); };
+        const float *Fprev = prev < 0 ? zero : state(prev);
+        const bool tile = static_cast<long>(w) * h <= tile_max;
+        // pass k (1-based): from the accepted previous level or from pass k - 1, into outs[(k - 1) % 2]
+        auto pass = [&](int k) {
+            LevelIO io{};
+            io.I = If;
+            io.A = Af;
+            io.W = W;
+            io.H = H;
+            const float *src = k == 1 ? Fprev : state(outs[(k - 2) & 1]);
+            io.Fp = src;
+            io.wp = k == 1 ? wp : w;
+            io.hp = k == 1 ? hp : h;
+            io.Bp = src + 3 * static_cast<size_t>(io.wp) * io.hp;
+            float *dst = state(outs[(k - 1) & 1]);
+            io.Fo = dst;
+            io.Bo = dst + 3 * static_cast<size_t>(w) * h;
+            io.w = w;
+            io.h = h;
+            io.omega = p.omega;
+            io.eps = p.eps_r;
+            const int err = tile ? launch_fine_tile(io, FGE_F32, s)
+                                 : launch_fine_fused(io, p.strip_rows, FGE_F32, s);
+            if (err) ret = FGE_EHIP;
+            measure(k, dst, w, h, w, h);
+        };
+        measure(0, Fprev, wp, hp, w, h);
+        pass(1);
+        double e_prev = wait(0);
+        int k = 1;
+        for (;;) {
+            if (k < max_passes) pass(k + 1);   // in flight while pass k is judged
+            const double e = wait(k);
+            if (ret != FGE_OK || std::fabs(e_prev - e) <= tol * e_prev || k >= max_passes) break;
+            e_prev = e;
+            ++k;
+        }
+        if (passes_out) passes_out[j] = k;
+        prev = outs[(k - 1) & 1];
+        wp = w;
+        hp = h;
+    }
+    if (ret == FGE_OK) {
+        const float *Fs = reinterpret_cast<float *>(ws + L.st[prev]);
+        hipLaunchKernelGGL(cv_copy_kernel<T>, dim3(blocks_for(3 * N)), dim3(kCvThreads), 0, s, Fs,
+                           Fs + 3 * N, static_cast<T *>(F), static_cast<T *>(B), N, nullptr);
+        if (hipGetLastError() != hipSuccess) ret = FGE_EHIP;
+    }
+    if (hipStreamSynchronize(s) != hipSuccess && ret == FGE_OK) ret = FGE_EHIP;
+    for (hipEvent_t e : ev)
+        if (e) (void)hipEventDestroy(e);
+    (void)hipHostFree(host);
+    return ret;
+}
+
 }  // namespace
 
 size_t levels_workspace_bytes(int W, int H, const fge_params &p, int resize) {
@@ -463,9 +619,60 @@ fge_status estimate_converge(const void *I, const void *A, int W, int H, const f
                            workspace, workspace_bytes, stream);
 }
 
+size_t converge_passes_workspace_bytes(int W, int H, const fge_params &p) {
+    if (W < 1 || H < 1 || W > kMaxSide || H > kMaxSide) return 0;
+    return cp_layout(W, H, p.storage).total;
+}
+
+fge_status estimate_converge_passes(const void *I, const void *A, int W, int H,
+                                    const fge_params &p, double tol, int max_passes, void *F,
+                                    void *B, int32_t *passes_out, void *workspace,
+                                    size_t workspace_bytes, void *stream) {
+    if (!params_valid(p)) return FGE_EINVAL;
+    if (p.order != FGE_REDBLACK) return FGE_EUNSUPPORTED;   // the fused kernels are red-black
+    if (W < 1 || H < 1 || W > kMaxSide || H > kMaxSide) return FGE_EINVAL;
+    if (!I || !A || !F || !B) return FGE_EINVAL;
+    if (!(tol >= 0.0) || !std::isfinite(tol) || max_passes < 1 || max_passes > kCvMaxSweeps)
+        return FGE_EINVAL;
+    if (outputs_alias(I, A, F, B, W, H, p.storage == FGE_F16 ? 2 : 4, workspace, workspace_bytes))
+        return FGE_EINVAL;
+    const size_t need = converge_passes_workspace_bytes(W, H, p);
+    if (!workspace || workspace_bytes < need || (reinterpret_cast<uintptr_t>(workspace) & 255))
+        return FGE_EWORKSPACE;
+    char *ws = static_cast<char *>(workspace);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (p.storage == FGE_F16)
+        return cp_run<_Float16>(I, A, W, H, p, tol, max_passes, F, B, passes_out, ws, s);
+    return cp_run<float>(I, A, W, H, p, tol, max_passes, F, B, passes_out, ws, s);
+}
+
 }  // namespace fge
 
 extern "C" {
+
+size_t fge_converge_passes_workspace_bytes(int32_t H, int32_t W, const fge_params *p) {
+    fge_params tmp;
+    if (!p) {
+        fge_default_params(&tmp);
+        p = &tmp;
+    }
+    return fge::converge_passes_workspace_bytes(W, H, *p);
+}
+
+fge_status fge_estimate_foreground_converge_passes(const void *I, const void *alpha, int32_t H,
+                                                   int32_t W, const fge_params *p, double tol,
+                                                   int32_t max_passes, void *F, void *B,
+                                                   int32_t *passes_out, void *workspace,
+                                                   size_t workspace_bytes, void *stream) {
+    fge_params tmp;
+    if (!p) {
+        fge_default_params(&tmp);
+        p = &tmp;
+    }
+    return fge::estimate_converge_passes(I, alpha, W, H, *p, tol, max_passes, F, B, passes_out,
+                                         workspace, workspace_bytes, stream);
+}
+
 
 size_t fge_converge_workspace_bytes(int32_t H, int32_t W, const fge_params *p) {
     fge_params tmp;

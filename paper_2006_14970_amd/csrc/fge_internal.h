@@ -245,6 +245,12 @@ int energy_blocks(int w, int h);
 int launch_energy(const void *I, const void *A, int W, int H, const void *F, const void *B, int w,
                   int h, float omega, float eps, int storage, int state_storage, const int *stop,
                   double *part, double *out, void *stream);
+// The same with F and B of size fw x fh read through the nearest map onto the w x h level (the
+// energy of a level's start state: the previous level's result as the resize leaves it).
+int launch_energy_mapped(const void *I, const void *A, int W, int H, const void *F, const void *B,
+                         int fw, int fh, int w, int h, float omega, float eps, int storage,
+                         int state_storage, const int *stop, double *part, double *out,
+                         void *stream);
 
 // Level loop with the convergence stop or the Jacobi order (fge_converge.hip); tol < 0 runs the
 // fixed counts.
@@ -252,6 +258,9 @@ size_t converge_workspace_bytes(int W, int H, const fge_params &p);
 fge_status estimate_converge(const void *I, const void *A, int W, int H, const fge_params &p,
                              double tol, int max_sweeps, void *F, void *B, int32_t *sweeps_out,
                              void *workspace, size_t workspace_bytes, void *stream);
+
+// The convergence form in passes of two sweeps on the fused kernels (fge_converge.hip).
+size_t converge_passes_workspace_bytes(int W, int H, const fge_params &p);
 
 // Batched launches: descriptor tables, work lists and counters are device pointers.  Every
 // batched tile or streaming launch uses kQueueCounters counters (one work queue per XCD).

@@ -29,30 +29,38 @@ __device__ __forceinline__ double ld(const T *p, size_t i) {
 
 // Partial sums of one block: [0] data term, [1] smoothness term, [2] sum of |residual| over
 // fractional pixels (0 < a < 1), [3] number of fractional pixels, [4] max |residual| there.
-// F and B are w x h; I and alpha are W x H and are read through the nearest map of a level
-// (source index (x W / w, y H / h); the identity when the sizes agree).  A non-null `stop` that
-// holds a non-zero value turns the launch into a no-op.
+// The energy is that of a w x h level.  I and alpha are W x H and F and B are fw x fh; both are
+// read through the nearest map onto the level (source index (x W / w, y H / h), likewise with fw,
+// fh; the identity when the sizes agree), so the state of the previous level can be evaluated as
+// it stands after the resize.  Threads walk the level in row segments of kRedThreads pixels (one
+// division per segment).  A non-null `stop` that holds a non-zero value turns the launch into a
+// no-op.
 template <typename T, typename TF>
 __global__ __launch_bounds__(kRedThreads) void energy_partial_kernel(
-    const T *I, const T *A, int W, int H, const TF *F, const TF *B, int w, int h, float omega,
-    float eps, const int *stop, double *part) {
+    const T *I, const T *A, int W, int H, const TF *F, const TF *B, int fw, int fh, int w, int h,
+    float omega, float eps, const int *stop, double *part) {
     if (stop && *stop) return;
-    const size_t n = static_cast<size_t>(w) * h, nI = static_cast<size_t>(W) * H;
-    const bool same = W == w && H == h;
+    const size_t nf = static_cast<size_t>(fw) * fh, nI = static_cast<size_t>(W) * H;
+    const bool same = W == w && H == h, fsame = fw == w && fh == h;
     auto src = [&](int xx, int yy) {
         return same ? static_cast<size_t>(yy) * w + xx
                     : static_cast<size_t>(yy * H / h) * W + xx * W / w;
     };
+    auto fsrc = [&](int xx, int yy) {
+        return fsame ? static_cast<size_t>(yy) * w + xx
+                     : static_cast<size_t>(yy * fh / h) * fw + xx * fw / w;
+    };
     double data = 0.0, smooth = 0.0, rsum = 0.0, rcnt = 0.0, rmax = 0.0;
-    const size_t stride = static_cast<size_t>(gridDim.x) * kRedThreads;
-    for (size_t p = static_cast<size_t>(blockIdx.x) * kRedThreads + threadIdx.x; p < n; p += stride) {
-        const int y = static_cast<int>(p / w), x = static_cast<int>(p - static_cast<size_t>(y) * w);
-        const size_t ps = src(x, y);
+    const int segs = (w + kRedThreads - 1) / kRedThreads, units = h * segs;
+    for (int u = blockIdx.x; u < units; u += gridDim.x) {
+        const int y = u / segs, x = (u - y * segs) * kRedThreads + static_cast<int>(threadIdx.x);
+        if (x >= w) continue;
+        const size_t ps = src(x, y), pf = fsrc(x, y);
         const double a = ld(A, ps);
         const bool frac = a > 0.0 && a < 1.0;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            const size_t q = c * n + p;
+            const size_t q = c * nf + pf;
             const double r = a * ld(F, q) + (1.0 - a) * ld(B, q) - ld(I, c * nI + ps);
             data += r * r;
             if (frac) {
@@ -63,22 +71,24 @@ __global__ __launch_bounds__(kRedThreads) void energy_partial_kernel(
         if (frac) rcnt += 1.0;
         if (x + 1 < w) {
             const double s = static_cast<double>(eps) + static_cast<double>(omega) * fabs(a - ld(A, src(x + 1, y)));
+            const size_t pr = fsrc(x + 1, y);
             double d = 0.0;
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                const size_t q = c * n + p;
-                const double df = ld(F, q) - ld(F, q + 1), db = ld(B, q) - ld(B, q + 1);
+                const double df = ld(F, c * nf + pf) - ld(F, c * nf + pr);
+                const double db = ld(B, c * nf + pf) - ld(B, c * nf + pr);
                 d += df * df + db * db;
             }
             smooth += s * d;
         }
         if (y + 1 < h) {
             const double s = static_cast<double>(eps) + static_cast<double>(omega) * fabs(a - ld(A, src(x, y + 1)));
+            const size_t pd = fsrc(x, y + 1);
             double d = 0.0;
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                const size_t q = c * n + p;
-                const double df = ld(F, q) - ld(F, q + w), db = ld(B, q) - ld(B, q + w);
+                const double df = ld(F, c * nf + pf) - ld(F, c * nf + pd);
+                const double db = ld(B, c * nf + pf) - ld(B, c * nf + pd);
                 d += df * df + db * db;
             }
             smooth += s * d;
@@ -343,28 +353,36 @@ int energy_blocks(int w, int h) {
 
 template <typename T, typename TF>
 void launch_energy_t(const void *I, const void *A, int W, int H, const void *F, const void *B,
-                     int w, int h, float omega, float eps, const int *stop, double *part, int nb,
-                     hipStream_t s) {
+                     int fw, int fh, int w, int h, float omega, float eps, const int *stop,
+                     double *part, int nb, hipStream_t s) {
     hipLaunchKernelGGL((energy_partial_kernel<T, TF>), dim3(nb), dim3(kRedThreads), 0, s,
                        static_cast<const T *>(I), static_cast<const T *>(A), W, H,
-                       static_cast<const TF *>(F), static_cast<const TF *>(B), w, h, omega, eps,
-                       stop, part);
+                       static_cast<const TF *>(F), static_cast<const TF *>(B), fw, fh, w, h, omega,
+                       eps, stop, part);
 }
 
 int launch_energy(const void *I, const void *A, int W, int H, const void *F, const void *B, int w,
                   int h, float omega, float eps, int storage, int state_storage, const int *stop,
                   double *part, double *out, void *stream) {
+    return launch_energy_mapped(I, A, W, H, F, B, w, h, w, h, omega, eps, storage, state_storage,
+                                stop, part, out, stream);
+}
+
+int launch_energy_mapped(const void *I, const void *A, int W, int H, const void *F, const void *B,
+                         int fw, int fh, int w, int h, float omega, float eps, int storage,
+                         int state_storage, const int *stop, double *part, double *out,
+                         void *stream) {
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int nb = energy_blocks(w, h);
     const bool i16 = storage == FGE_F16, f16 = state_storage == FGE_F16;
     if (i16 && f16)
-        launch_energy_t<_Float16, _Float16>(I, A, W, H, F, B, w, h, omega, eps, stop, part, nb, s);
+        launch_energy_t<_Float16, _Float16>(I, A, W, H, F, B, fw, fh, w, h, omega, eps, stop, part, nb, s);
     else if (i16)
-        launch_energy_t<_Float16, float>(I, A, W, H, F, B, w, h, omega, eps, stop, part, nb, s);
+        launch_energy_t<_Float16, float>(I, A, W, H, F, B, fw, fh, w, h, omega, eps, stop, part, nb, s);
     else if (f16)
-        launch_energy_t<float, _Float16>(I, A, W, H, F, B, w, h, omega, eps, stop, part, nb, s);
+        launch_energy_t<float, _Float16>(I, A, W, H, F, B, fw, fh, w, h, omega, eps, stop, part, nb, s);
     else
-        launch_energy_t<float, float>(I, A, W, H, F, B, w, h, omega, eps, stop, part, nb, s);
+        launch_energy_t<float, float>(I, A, W, H, F, B, fw, fh, w, h, omega, eps, stop, part, nb, s);
     int err = static_cast<int>(hipGetLastError());
     if (err) return err;
     hipLaunchKernelGGL(energy_final_kernel, dim3(1), dim3(kRedThreads), 0, s, part, nb, stop, out);

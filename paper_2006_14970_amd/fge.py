@@ -227,6 +227,11 @@ def _lib():
     lib.fge_estimate_foreground_converge.argtypes = [vp, vp, i32, i32, pp, ctypes.c_double, i32,
                                                      vp, vp, vp, vp, sz, vp]
     lib.fge_estimate_foreground_converge.restype = ctypes.c_int
+    lib.fge_converge_passes_workspace_bytes.argtypes = [i32, i32, pp]
+    lib.fge_converge_passes_workspace_bytes.restype = sz
+    lib.fge_estimate_foreground_converge_passes.argtypes = [vp, vp, i32, i32, pp, ctypes.c_double,
+                                                            i32, vp, vp, ip, vp, sz, vp]
+    lib.fge_estimate_foreground_converge_passes.restype = ctypes.c_int
     op = ctypes.POINTER(LevelOptions)
     lib.fge_levels_workspace_bytes.argtypes = [i32, i32, pp, op]
     lib.fge_levels_workspace_bytes.restype = sz
@@ -937,6 +942,36 @@ def estimate_foreground_converge(I, alpha, params: Params | None = None, tol: fl
         F.data_ptr(), B.data_ptr(), sweeps.data_ptr(), ws.data_ptr(), ws.numel(),
         _stream_ptr(stream)), "fge_estimate_foreground_converge")
     return F, B, sweeps[:n]
+
+
+@_on_stream
+def estimate_foreground_converge_passes(I, alpha, params: Params | None = None, tol: float = 1e-4,
+                                        max_passes: int = 100, F=None, B=None, stream=None):
+    """The "while not converged" level loop on the fused kernels, tested after every pass of two
+    sweeps (fge_estimate_foreground_converge_passes).  Returns (F, B, passes), passes a list of the
+    per-level pass counts.  Blocks until done."""
+    import torch
+    p = params if params is not None else default_params()
+    dt = storage_dtype(p)
+    _, H, W = I.shape
+    for name, t in (("I", I), ("alpha", alpha)):
+        if not t.is_cuda or t.dtype != dt or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous CUDA tensor of dtype {dt}")
+    if tuple(alpha.shape) != (H, W):
+        raise ValueError("alpha must be (H, W) matching I")
+    if F is None:
+        F = torch.empty((3, H, W), dtype=dt, device=I.device)
+    if B is None:
+        B = torch.empty((3, H, W), dtype=dt, device=I.device)
+    n = num_levels(H, W)
+    passes = (ctypes.c_int32 * max(1, n))()
+    need = _lib().fge_converge_passes_workspace_bytes(H, W, ctypes.byref(p))
+    ws = torch.empty(max(1, need), dtype=torch.uint8, device=I.device)
+    _check(_lib().fge_estimate_foreground_converge_passes(
+        I.data_ptr(), alpha.data_ptr(), H, W, ctypes.byref(p), float(tol), int(max_passes),
+        F.data_ptr(), B.data_ptr(), passes, ws.data_ptr(), ws.numel(), _stream_ptr(stream)),
+        "fge_estimate_foreground_converge_passes")
+    return F, B, list(passes)[:n]
 
 
 @_on_stream

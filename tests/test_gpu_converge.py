@@ -2,10 +2,12 @@
 
 Jacobi with the fixed counts is compared element by element with the oracle's Jacobi order.  In
 the convergence form the sweep count of a level is a decision taken on an energy computed from
-float32 state on the device and from float64 state in the oracle, so near the threshold the two
-can differ by one sweep: the test replays the device's counts in the oracle (a per-level schedule)
-and compares the results element by element, and checks the counts against the oracle's own
-decisions to within one sweep per level.
+float32 state on the device and from float64 state in the oracle.  The counts must equal the
+oracle's own decisions, except at a level where the oracle's relative energy change at the
+deciding test lies within BAND (relative) of the tolerance, where the two arithmetics may fall on
+either side; the results are then compared with the oracle replaying the device's counts (a
+per-level schedule), else with the oracle's own converged result.  The same holds for the form
+tested after every pass of two sweeps on the fused kernels (oracle: the test every m = 2 sweeps).
 """
 import numpy as np
 import pytest
@@ -16,6 +18,30 @@ from paper_2006_14970_amd import synth
 pytestmark = pytest.mark.gpu
 
 TOL = {"f32": 1e-4, "f16": 2e-3}
+# Half-width of the band around tol (relative) inside which a decision may differ: the device's
+# float32 state and float64 sums give energies within ~1e-7 relative of the oracle's, so a relative
+# change of ~1e-4 is known to ~1e-3 of itself; 5% is a wide margin.
+BAND = 0.05
+
+
+def check_counts(dev, ora, rel, tol, replay=None):
+    """Equal counts per level, or a difference decided within BAND of tol.  `rel[l, k]` is the
+    oracle's relative change at its (k+1)-th test of level l.  A level whose energy decays
+    geometrically towards an exact fit (|dE| / E never falls below tol; the arithmetic's own
+    fixed point ends it) may stop at different counts in float32 and float64: `replay(l, k)`, the
+    oracle's level-l state after k tests, then shows that the two counts leave the same state (to
+    1e-7).  Returns whether all counts were equal."""
+    for lv, (d, o) in enumerate(zip(dev, ora)):
+        if d == o:
+            continue
+        k = min(d, o)                      # the first test where one side stopped
+        if abs(rel[lv, k - 1] - tol) > BAND * tol:
+            assert replay is not None, (lv, d, o, rel[lv, k - 1])
+            F1, B1 = replay(lv, d)
+            F2, B2 = replay(lv, o)
+            assert max(maxabs(F1, F2), maxabs(B1, B2)) <= 1e-7, (lv, d, o, rel[lv, k - 1])
+        return False                       # later levels start from a different state
+    return True
 
 
 @pytest.fixture(scope="module")
@@ -69,15 +95,68 @@ def test_converge_matches_oracle(gpu, order, storage):
     torch.cuda.synchronize()
     sw = sw.cpu().tolist()
     I64, a64 = inputs64(I, a)
-    Fo, Bo, swo = oracle.ml_converge(I64, a64, tol, 300, order=order)
+    Fo, Bo, swo, rel = oracle.ml_converge_every(I64, a64, 1, tol, 300, order=order, rel_cap=300)
     print(f"{order} {storage}: device sweeps {sw}, oracle sweeps {swo}")
     assert all(1 <= k <= 300 for k in sw)
-    assert all(abs(x - y) <= 1 for x, y in zip(sw, swo))
-    Fr, Br = oracle.ml_schedule(I64, a64, sw, order=order)
+    if check_counts(sw, swo, rel, tol):
+        Fr, Br = Fo, Bo
+    else:
+        Fr, Br = oracle.ml_schedule(I64, a64, sw, order=order)
     err = max(maxabs(F.double().cpu().numpy(), Fr), maxabs(B.double().cpu().numpy(), Br))
     assert err <= TOL[storage], err
-    if sw == swo:
-        assert max(maxabs(F.double().cpu().numpy(), Fo), maxabs(B.double().cpu().numpy(), Bo)) <= TOL[storage]
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+@pytest.mark.parametrize("wh,kind", [((300, 220), "strands"), ((1024, 768), "strands"),
+                                     ((64, 64), "smooth"), ((97, 3), "smooth"), ((1, 1), "smooth"),
+                                     ((129, 257), "smooth")])
+def test_converge_passes_matches_oracle(gpu, storage, wh, kind):
+    """The fused-pass form (tile kernel up to 2^18 px, streaming kernel above: 1024 x 768's last
+    level) against the oracle's loop tested every two sweeps."""
+    torch, fge = gpu
+    W, H = wh
+    p = fge.default_params(storage=fge.F16 if storage == "f16" else fge.F32)
+    s = (synth.strands(W, H, seed=43 + W, n_strands=max(1, W * H // 4000)) if kind == "strands"
+         else synth.smooth(W, H, seed=44 + W))
+    I, a = to_dev(torch, fge, p, s)
+    tol = 1e-4
+    F, B, ps = fge.estimate_foreground_converge_passes(I, a, p, tol=tol, max_passes=150)
+    I64, a64 = inputs64(I, a)
+    Fo, Bo, ch, rel = oracle.ml_converge_every(I64, a64, 2, tol, 150, rel_cap=150)
+    print(f"{W}x{H} {storage}: device passes {ps}, oracle passes {ch}")
+    assert all(1 <= k <= 150 for k in ps)
+
+    def replay(lv, k):   # the oracle's state of level lv after k passes, as the output carries it
+        sched = [2 * c for c in ch[:lv]] + [2 * k] + [0] * (len(ch) - lv - 1)
+        return oracle.ml_schedule(I64, a64, sched)
+
+    if check_counts(ps, ch, rel, tol, replay):
+        Fr, Br = Fo, Bo
+    else:
+        Fr, Br = oracle.ml_schedule(I64, a64, [2 * k for k in ps])
+    err = max(maxabs(F.double().cpu().numpy(), Fr), maxabs(B.double().cpu().numpy(), Br))
+    print(f"  max-abs vs oracle {err:.2e}")
+    assert err <= TOL[storage], err
+
+
+def test_converge_passes_limits(gpu):
+    torch, fge = gpu
+    p = fge.default_params()
+    s = synth.smooth(200, 150, seed=5)
+    I, a = to_dev(torch, fge, p, s)
+    n = fge.num_levels(150, 200)
+    F, B, ps = fge.estimate_foreground_converge_passes(I, a, p, tol=1.0, max_passes=50)
+    assert ps == [1] * n
+    Fr, Br = oracle.ml_schedule(*inputs64(I, a), [2] * n)
+    assert max(maxabs(F.double().cpu().numpy(), Fr), maxabs(B.double().cpu().numpy(), Br)) <= 1e-4
+    _, _, ps = fge.estimate_foreground_converge_passes(I, a, p, tol=0.0, max_passes=3)
+    assert ps == [3] * n
+    with pytest.raises(fge.FgeError):
+        fge.estimate_foreground_converge_passes(I, a, fge.default_params(order=fge.JACOBI))
+    # repeatable: bit-identical results and counts
+    r1 = fge.estimate_foreground_converge_passes(I, a, p, tol=1e-5, max_passes=100)
+    r2 = fge.estimate_foreground_converge_passes(I, a, p, tol=1e-5, max_passes=100)
+    assert r1[2] == r2[2] and torch.equal(r1[0], r2[0]) and torch.equal(r1[1], r2[1])
 
 
 def test_converge_limits_and_fixed_form(gpu):
