@@ -212,9 +212,29 @@ def run_variants(torch, fge, sample):
                      "sweeps_per_level": sw.cpu().tolist() if tol >= 0 else None,
                      "quality": {"SAD": float(q[0]), "MSE": float(q[1]), "GRAD": float(q[2])}}
         log(f"  {name}: {ms:.1f} ms, SAD {q[0]:.1f} (fused fixed counts {qf[0]:.1f})")
+    # the convergence form on the fused kernels, tested after every pass of two sweeps
+    p = fge.default_params(storage=fge.F16)
+    fge.estimate_foreground_converge_passes(I, a, p, tol=1e-4, max_passes=100)
+    torch.cuda.synchronize()
+    reps = 3
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        F, B, ps = fge.estimate_foreground_converge_passes(I, a, p, tol=1e-4, max_passes=100)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / reps * 1e3
+    q = fge.quality(F, G, a).cpu().numpy()
+    out["converge_passes_redblack"] = {
+        "ms": ms, "value": W_IMG * H_IMG / 1e6 / (ms * 1e-3),
+        "sweeps_per_level": [2 * k for k in ps],
+        "quality": {"SAD": float(q[0]), "MSE": float(q[1]), "GRAD": float(q[2])},
+        "vs_per_level_kernels": out["converge_redblack"]["ms"] / ms}
+    log(f"  converge_passes_redblack: {ms:.1f} ms ({out['converge_redblack']['ms'] / ms:.1f}x the "
+        f"per-level form), sweeps {[2 * k for k in ps]}, SAD {q[0]:.1f}")
     return {"workload": "4096x3072 strands image, float16 storage, per-level kernels: convergence "
                         "form (level energy change <= 1e-4 relative, <= 200 sweeps per level) and "
-                        "the smooth resize variant", "unit": "MP/s", **out}
+                        "the smooth resize variant; converge_passes_redblack: the convergence form "
+                        "on the fused kernels, tested after every pass of two sweeps (<= 100 "
+                        "passes per level)", "unit": "MP/s", **out}
 
 
 CF_BYTES_PER_PX_F32 = 488   # per pixel and PCG iteration, float32 matte: see run_closed_form

@@ -427,15 +427,22 @@ fge_status cv_run(const Plan &pl, const fge_params &p, const void *Iv, const voi
 // Every level runs passes of two red-black sweeps on the fused kernels (the LDS tile kernel for
 // levels up to tile_max_px, the streaming kernel above; one memory round trip per pass), the
 // first pass resizing from the previous level.  After each pass the level's energy is reduced on
-// the device and copied to the host, which stops the level when a pass changes it by at most tol
-// times its value before the pass (the energy before the first pass: the previous level's result
-// as the resize leaves it), or after max_passes passes.  The host keeps one pass in flight beyond
-// the one it decides on: that pass writes the other state buffer, so the accepted state is never
-// overwritten.  The state stays float32 from level to level (inputs in float16 storage are
-// converted once) and is converted to the storage type when the last level is done.
+// the device and written to pinned host memory, and the host stops the level when a pass changes
+// it by at most tol times its value before the pass (the energy before the first pass: the
+// previous level's result as the resize leaves it), or after max_passes passes.  The host keeps
+// passes in flight beyond the one it judges -- up to kCpDepthSmall for levels of at most
+// kCpSmallPx pixels, whose passes are shorter than a host round trip, one for larger levels --
+// each writing the next buffer of a ring that never wraps onto the accepted state.  The state
+// stays float32 from level to level (inputs in float16 storage are converted once) and is
+// converted to the storage type when the last level is done.
+
+constexpr int kCpDepthSmall = 7;                 // passes in flight on small levels
+constexpr long kCpSmallPx = 1L << 16;
+constexpr int kCpSmallBufs = kCpDepthSmall + 2;  // the accepted state and kCpDepthSmall + 1 outputs
+constexpr int kCpSlots = 16;                     // energy slots in pinned memory (> any depth)
 
 struct CpLayout {
-    size_t st[3] = {0, 0, 0}, in = 0, zero = 0, edev = 0, part = 0, total = 0;
+    size_t big[3] = {0, 0, 0}, small[kCpSmallBufs] = {}, in = 0, zero = 0, part = 0, total = 0;
 };
 
 CpLayout cp_layout(int W, int H, int storage) {
@@ -443,14 +450,17 @@ CpLayout cp_layout(int W, int H, int storage) {
     const size_t n = static_cast<size_t>(W) * H;
     size_t off = 0;
     for (int k = 0; k < 3; ++k) {
-        L.st[k] = off;
+        L.big[k] = off;
         off += a256(6 * n * sizeof(float));
+    }
+    const size_t ns = std::min<size_t>(n, kCpSmallPx);
+    for (int k = 0; k < kCpSmallBufs; ++k) {
+        L.small[k] = off;
+        off += a256(6 * ns * sizeof(float));
     }
     L.in = off;
     off += storage == FGE_F16 ? a256(4 * n * sizeof(float)) : 0;
     L.zero = off;   // the 1 x 1 zero start (6 floats)
-    off += 256;
-    L.edev = off;   // two slots of fge_energy's 6 outputs
     off += 256;
     L.part = off;
     off += a256(static_cast<size_t>(energy_blocks(W, H)) * 5 * sizeof(double));
@@ -486,57 +496,63 @@ fge_status cp_run(const void *Iv, const void *Av, int W, int H, const fge_params
     float *zero = reinterpret_cast<float *>(ws + L.zero);
     hipLaunchKernelGGL(cp_zero_kernel, dim3(1), dim3(64), 0, s, zero);
     if (hipGetLastError() != hipSuccess) return FGE_EHIP;
-    double *edev = reinterpret_cast<double *>(ws + L.edev);
     double *part = reinterpret_cast<double *>(ws + L.part);
     const long tile_max = p.tile_max_px == 0 ? kTileMaxPxDefault : (p.tile_max_px < 0 ? 0 : p.tile_max_px);
 
-    double *host = nullptr;   // pinned: the energies of the last two measurements
-    if (hipHostMalloc(reinterpret_cast<void **>(&host), 2 * sizeof(double), hipHostMallocDefault) != hipSuccess)
+    // pinned, mapped: the energy kernels write fge_energy's 6 outputs of measurement m into slot
+    // m % kCpSlots; an event after each tells the host the slot is complete
+    double *host = nullptr, *hdev = nullptr;
+    if (hipHostMalloc(reinterpret_cast<void **>(&host), kCpSlots * 6 * sizeof(double),
+                      hipHostMallocMapped) != hipSuccess)
         return FGE_ENOMEM;
-    hipEvent_t ev[2] = {nullptr, nullptr};
     fge_status ret = FGE_OK;
-    if (hipEventCreateWithFlags(&ev[0], hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&ev[1], hipEventDisableTiming) != hipSuccess)
-        ret = FGE_EHIP;
+    hipEvent_t ev[kCpSlots] = {};
+    if (hipHostGetDevicePointer(reinterpret_cast<void **>(&hdev), host, 0) != hipSuccess) ret = FGE_EHIP;
+    for (int k = 0; k < kCpSlots && ret == FGE_OK; ++k)
+        if (hipEventCreateWithFlags(&ev[k], hipEventDisableTiming) != hipSuccess) ret = FGE_EHIP;
 
-    // measurement m (the energy before pass 1, then after pass m) into slot m % 2
     auto measure = [&](int m, const float *Fs, int fw, int fh, int w, int h) {
-        const int sl = m & 1;
+        const int sl = m % kCpSlots;
         if (launch_energy_mapped(If, Af, W, H, Fs, Fs + 3 * static_cast<size_t>(fw) * fh, fw, fh, w,
-                                 h, p.omega, p.eps_r, FGE_F32, FGE_F32, nullptr, part, edev + 6 * sl,
+                                 h, p.omega, p.eps_r, FGE_F32, FGE_F32, nullptr, part, hdev + 6 * sl,
                                  s) ||
-            hipMemcpyAsync(host + sl, edev + 6 * sl, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
             hipEventRecord(ev[sl], s) != hipSuccess)
             ret = FGE_EHIP;
     };
     auto wait = [&](int m) {
-        if (ret == FGE_OK && hipEventSynchronize(ev[m & 1]) != hipSuccess) ret = FGE_EHIP;
-        return host[m & 1];
+        if (ret == FGE_OK && hipEventSynchronize(ev[m % kCpSlots]) != hipSuccess) ret = FGE_EHIP;
+        return ret == FGE_OK ? reinterpret_cast<volatile double *>(host)[6 * (m % kCpSlots)] : 0.0;
     };
 
+    // buffers: ids 0..2 the full-size ring, 3.. the small ring
+    auto buf = [&](int id) {
+        return reinterpret_cast<float *>(ws + (id < 3 ? L.big[id] : L.small[id - 3]));
+    };
     const int n = num_levels(W, H);
-    int prev = -1, wp = 1, hp = 1;   // the accepted state: buffer index (-1: the zero start), size
+    int prev = -1, wp = 1, hp = 1;   // the accepted state: buffer id (-1: the zero start), size
     for (int j = 0; j < n && ret == FGE_OK; ++j) {
         const int w = level_size(W, j + 1, n), h = level_size(H, j + 1, n);
-        int outs[2], m = 0;
-        for (int k = 0; k < 3; ++k)
-            if (k != prev && m < 2) outs[m++] = k;
-        auto state = [&](int k) { return reinterpret_cast<float *>(ws + L.st[k]); };
-        const float *Fprev = prev < 0 ? zero : state(prev);
-        const bool tile = static_cast<long>(w) * h <= tile_max;
-        // pass k (1-based): from the accepted previous level or from pass k - 1, into outs[(k - 1) % 2]
+        const long px = static_cast<long>(w) * h;
+        const bool small = px <= kCpSmallPx;
+        int outs[kCpSmallBufs], R = 0;
+        for (int id = small ? 3 : 0; id < (small ? 3 + kCpSmallBufs : 3); ++id)
+            if (id != prev && R < kCpSmallBufs - 1 + (small ? 0 : 1)) outs[R++] = id;
+        const int depth = R - 1;   // passes in flight beyond the one judged
+        const float *Fprev = prev < 0 ? zero : buf(prev);
+        const bool tile = px <= tile_max;
+        // pass k (1-based): from the accepted previous level or from pass k - 1, into outs[(k - 1) % R]
         auto pass = [&](int k) {
             LevelIO io{};
             io.I = If;
             io.A = Af;
             io.W = W;
             io.H = H;
-            const float *src = k == 1 ? Fprev : state(outs[(k - 2) & 1]);
+            const float *src = k == 1 ? Fprev : buf(outs[(k - 2) % R]);
             io.Fp = src;
             io.wp = k == 1 ? wp : w;
             io.hp = k == 1 ? hp : h;
             io.Bp = src + 3 * static_cast<size_t>(io.wp) * io.hp;
-            float *dst = state(outs[(k - 1) & 1]);
+            float *dst = buf(outs[(k - 1) % R]);
             io.Fo = dst;
             io.Bo = dst + 3 * static_cast<size_t>(w) * h;
             io.w = w;
@@ -549,23 +565,27 @@ fge_status cp_run(const void *Iv, const void *Av, int W, int H, const fge_params
             measure(k, dst, w, h, w, h);
         };
         measure(0, Fprev, wp, hp, w, h);
-        pass(1);
+        int hi = 0;   // passes enqueued
+        auto fill = [&](int upto) {
+            while (ret == FGE_OK && hi < std::min(upto, max_passes)) pass(++hi);
+        };
+        fill(1 + depth);
         double e_prev = wait(0);
         int k = 1;
         for (;;) {
-            if (k < max_passes) pass(k + 1);   // in flight while pass k is judged
+            fill(k + depth);
             const double e = wait(k);
             if (ret != FGE_OK || std::fabs(e_prev - e) <= tol * e_prev || k >= max_passes) break;
             e_prev = e;
             ++k;
         }
         if (passes_out) passes_out[j] = k;
-        prev = outs[(k - 1) & 1];
+        prev = outs[(k - 1) % R];
         wp = w;
         hp = h;
     }
     if (ret == FGE_OK) {
-        const float *Fs = reinterpret_cast<float *>(ws + L.st[prev]);
+        const float *Fs = buf(prev);
         hipLaunchKernelGGL(cv_copy_kernel<T>, dim3(blocks_for(3 * N)), dim3(kCvThreads), 0, s, Fs,
                            Fs + 3 * N, static_cast<T *>(F), static_cast<T *>(B), N, nullptr);
         if (hipGetLastError() != hipSuccess) ret = FGE_EHIP;
