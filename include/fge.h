@@ -167,10 +167,12 @@ fge_status fge_estimate_foreground_noalloc(const void *I, const void *alpha, int
  * quadratic on the level's F, B against its nearest-resized image and matte) by at most tol times
  * its value before the pass -- before the first pass: the previous level's result as the resize
  * leaves it -- or after max_passes passes (1..100000).  Each level thus runs an even number of
- * sweeps; the CPU oracle's fgo_ml_converge_every with m = 2 is the same loop.  The energies are
- * reduced on the device and read by the host, which keeps one pass in flight beyond the one it
- * judges (that pass writes the other state buffer, so the accepted state is never overwritten):
- * the call BLOCKS until the result is complete.  passes_out (HOST int array of >= n_levels
+ * sweeps; the CPU oracle's fgo_ml_converge_every with m = 2 is the same loop.  The leading
+ * levels that fit the coarse block (w*h <= p->coarse_max_px, or up to 4096 px when it is 0; none
+ * when it is -1) run in one workgroup that reduces each energy in float64 and takes the decision
+ * itself.  For the other levels the energies are reduced on the device and read by the host,
+ * which keeps passes in flight beyond the one it judges (each writes another state buffer, so
+ * the accepted state is never overwritten): the call BLOCKS until the result is complete.  passes_out (HOST int array of >= n_levels
  * entries, or NULL) receives the passes each level ran.  The state stays float32 between passes
  * and levels (float16 inputs are converted once) and F, B are written in p->storage at the end.
  * Red-black order only (FGE_EUNSUPPORTED for Jacobi).  Workspace:

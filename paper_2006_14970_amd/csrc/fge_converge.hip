@@ -432,7 +432,10 @@ fge_status cv_run(const Plan &pl, const fge_params &p, const void *Iv, const voi
 // previous level's result as the resize leaves it), or after max_passes passes.  The host keeps
 // passes in flight beyond the one it judges -- up to kCpDepthSmall for levels of at most
 // kCpSmallPx pixels, whose passes are shorter than a host round trip, one for larger levels --
-// each writing the next buffer of a ring that never wraps onto the accepted state.  The state
+// each writing the next buffer of a ring that never wraps onto the accepted state.  The leading
+// levels that fit the coarse block's LDS (at most coarse_max_px pixels, all that fit when it is
+// 0, none when it is -1) run in one launch of the coarse block, which takes the same decisions
+// on the device (energy reduced in float64 in the workgroup) with no host round trip.  The state
 // stays float32 from level to level (inputs in float16 storage are converted once) and is
 // converted to the storage type when the last level is done.
 
@@ -501,8 +504,10 @@ fge_status cp_run(const void *Iv, const void *Av, int W, int H, const fge_params
 
     // pinned, mapped: the energy kernels write fge_energy's 6 outputs of measurement m into slot
     // m % kCpSlots; an event after each tells the host the slot is complete
+    // (after the slots: the pass counts of the coarse block's levels)
     double *host = nullptr, *hdev = nullptr;
-    if (hipHostMalloc(reinterpret_cast<void **>(&host), kCpSlots * 6 * sizeof(double),
+    const size_t slot_bytes = kCpSlots * 6 * sizeof(double);
+    if (hipHostMalloc(reinterpret_cast<void **>(&host), slot_bytes + kMaxLevels * sizeof(int),
                       hipHostMallocMapped) != hipSuccess)
         return FGE_ENOMEM;
     fge_status ret = FGE_OK;
@@ -530,7 +535,41 @@ fge_status cp_run(const void *Iv, const void *Av, int W, int H, const fge_params
     };
     const int n = num_levels(W, H);
     int prev = -1, wp = 1, hp = 1;   // the accepted state: buffer id (-1: the zero start), size
-    for (int j = 0; j < n && ret == FGE_OK; ++j) {
+
+    // the coarse block: the longest prefix of levels that fit its LDS and the limit
+    const int climit = p.coarse_max_px < 0 ? 0 : (p.coarse_max_px == 0 ? kCoarseMaxPx : p.coarse_max_px);
+    int nc = 0;
+    while (nc < n) {
+        const int w = level_size(W, nc + 1, n), h = level_size(H, nc + 1, n);
+        const long px = static_cast<long>(w) * h;
+        if (px > climit || px > kCoarseMaxPx || static_cast<long>((w + 1) / 2) * h > kCoarseMaxPairs) break;
+        ++nc;
+    }
+    int *hcounts = reinterpret_cast<int *>(reinterpret_cast<char *>(host) + slot_bytes);
+    if (nc > 0 && ret == FGE_OK) {
+        CoarseArgs c{};
+        for (int l = 0; l < nc; ++l) {
+            c.src.I[l] = If;
+            c.src.A[l] = Af;
+            c.src.W[l] = W;
+            c.src.H[l] = H;
+            c.lw[l] = level_size(W, l + 1, n);
+            c.lh[l] = level_size(H, l + 1, n);
+            c.lit[l] = 2;
+        }
+        c.nc = nc;
+        float *dst = buf(3);
+        c.Fo = dst;
+        c.Bo = dst + 3 * static_cast<size_t>(c.lw[nc - 1]) * c.lh[nc - 1];
+        c.omega = p.omega;
+        c.eps = p.eps_r;
+        int *dcounts = reinterpret_cast<int *>(reinterpret_cast<char *>(hdev) + slot_bytes);
+        if (launch_coarse_converge(c, tol, max_passes, dcounts, s)) ret = FGE_EHIP;
+        prev = 3;
+        wp = c.lw[nc - 1];
+        hp = c.lh[nc - 1];
+    }
+    for (int j = nc; j < n && ret == FGE_OK; ++j) {
         const int w = level_size(W, j + 1, n), h = level_size(H, j + 1, n);
         const long px = static_cast<long>(w) * h;
         const bool small = px <= kCpSmallPx;
@@ -591,6 +630,8 @@ fge_status cp_run(const void *Iv, const void *Av, int W, int H, const fge_params
         if (hipGetLastError() != hipSuccess) ret = FGE_EHIP;
     }
     if (hipStreamSynchronize(s) != hipSuccess && ret == FGE_OK) ret = FGE_EHIP;
+    if (ret == FGE_OK && passes_out)
+        for (int l = 0; l < nc; ++l) passes_out[l] = reinterpret_cast<volatile int *>(hcounts)[l];
     for (hipEvent_t e : ev)
         if (e) (void)hipEventDestroy(e);
     (void)hipHostFree(host);

@@ -269,6 +269,11 @@ int launch_zero(int *d, int n, void *stream);
 int launch_gather_batch(const GatherArgs *descs, const long long *first, int n, long long total,
                         int storage, void *stream);
 int launch_coarse_batch(const CoarseArgs *descs, int n, int storage, void *stream);
+// Coarse levels [0, a.nc) in the convergence form, one workgroup, float32 inputs and state: a
+// level runs passes of two sweeps until a pass changes its energy by at most tol times the value
+// before it, or max_passes passes; the passes of level l go to counts[l] (device-visible memory).
+int launch_coarse_converge(const CoarseArgs &a, double tol, int max_passes, int *counts,
+                           void *stream);
 int launch_fine_batch(const FineArgs *descs, const WorkItem *items, int nitems, int *counter,
                       int storage, void *stream);
 int launch_tile_batch(const TileArgs *descs, const WorkItem *items, int nitems, int *counter,

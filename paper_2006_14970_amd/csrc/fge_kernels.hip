@@ -164,8 +164,20 @@ struct CoarseLds {
     float4 B[kCoarseMaxPx];
 };
 
-template <typename T>
-__device__ __forceinline__ void coarse_body(const CoarseArgs &args, CoarseLds &lds) {
+// The convergence form on the coarse block (CONV): a level runs passes of two sweeps until a pass
+// changes the level's energy by at most tol times its value before the pass, or max_passes passes
+// have run; the passes a level ran go to counts[l].  red: 2 * (kCoarseThreads / 64) doubles of
+// LDS for the energy's per-wave sums.
+struct CoarseConv {
+    double tol;
+    int max_passes;
+    int *counts;
+    double *red;
+};
+
+template <typename T, bool CONV = false>
+__device__ __forceinline__ void coarse_body(const CoarseArgs &args, CoarseLds &lds,
+                                            const CoarseConv &cv = CoarseConv{}) {
     float4 *sFA = lds.FA;
     float4 *sB = lds.B;
 
@@ -320,32 +332,109 @@ __device__ __forceinline__ void coarse_body(const CoarseArgs &args, CoarseLds &l
                             sB[cpix[k][c]] = make_float4(bo[0], bo[1], bo[2], 0.0f);
                         }
         };
-        if (npairs <= 64) {
-            // The whole level is slot 0 of wave 0.  A wave's LDS operations execute in order, so
-            // its half-sweeps need no workgroup barrier, only an ordering point for the compiler;
-            // the other waves wait at the barrier that ends the level.
-            if (uniform(tid >> 6) == 0) {
-                for (int it = 0; it < iters; ++it) {
+        // n_it sweeps of the level; every thread leaves through a workgroup barrier.
+        auto sweeps = [&](int n_it) {
+            if (npairs <= 64) {
+                // The whole level is slot 0 of wave 0.  A wave's LDS operations execute in order,
+                // so its half-sweeps need no workgroup barrier, only an ordering point for the
+                // compiler; the other waves wait at the barrier that ends the level.
+                if (uniform(tid >> 6) == 0) {
+                    for (int it = 0; it < n_it; ++it) {
+#pragma unroll
+                        for (int c = 0; c < 2; ++c) {
+                            update(0, c);
+                            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+                            __builtin_amdgcn_wave_barrier();
+                            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+                        }
+                    }
+                }
+                lds_sync();
+            } else {
+                for (int it = 0; it < n_it; ++it) {
 #pragma unroll
                     for (int c = 0; c < 2; ++c) {
-                        update(0, c);
-                        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
-                        __builtin_amdgcn_wave_barrier();
-                        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+#pragma unroll
+                        for (int k = 0; k < kCoarsePairsPerThread; ++k)
+                            if (live(k)) update(k, c);
+                        lds_sync();
                     }
                 }
             }
-            lds_sync();
+        };
+        if constexpr (!CONV) {
+            sweeps(iters);
         } else {
-            for (int it = 0; it < iters; ++it) {
+            // The level's energy (the data term of every pixel plus, for each pixel, its right
+            // and lower edge, so every edge once), each term in float64 from the stored values:
+            // per thread, then per wave (butterfly sums, equal in every lane), then over the
+            // waves in a fixed order by every thread, so the stop decision is the same
+            // everywhere.  Called by all threads after a barrier; the barrier inside separates
+            // the per-wave stores from the reads, and the next call's stores come after the
+            // sweeps' closing barrier.
+            auto energy = [&]() {
+                double data = 0.0, smooth = 0.0;
 #pragma unroll
-                for (int c = 0; c < 2; ++c) {
+                for (int k = 0; k < kCoarsePairsPerThread; ++k) {
+                    if (!live(k)) continue;
 #pragma unroll
-                    for (int k = 0; k < kCoarsePairsPerThread; ++k)
-                        if (live(k)) update(k, c);
-                    lds_sync();
+                    for (int s = 0; s < 2; ++s) {
+                        if (!(s == 0 ? pr[k].valid0 : pr[k].valid1)) continue;
+                        const int i = pr[k].p0 + s, x = pr[k].x0 + s, y = pr[k].y;
+                        const float4 f = sFA[i], g = sB[i];
+                        const double a = av[k][s], b = 1.0 - a;
+                        const double fv[3] = {f.x, f.y, f.z}, bv[3] = {g.x, g.y, g.z};
+#pragma unroll
+                        for (int ch = 0; ch < 3; ++ch) {
+                            const double r = a * fv[ch] + b * bv[ch] - static_cast<double>(iv[k][s][ch]);
+                            data += r * r;
+                        }
+#pragma unroll
+                        for (int e = 0; e < 2; ++e) {
+                            if (e == 0 ? x + 1 >= w : y + 1 >= h) continue;
+                            const int j = e == 0 ? i + 1 : i + w;
+                            const float4 fj = sFA[j], gj = sB[j];
+                            const double wgt = static_cast<double>(eps) +
+                                               static_cast<double>(omega) * fabs(a - static_cast<double>(fj.w));
+                            const double df[3] = {fv[0] - fj.x, fv[1] - fj.y, fv[2] - fj.z};
+                            const double db[3] = {bv[0] - gj.x, bv[1] - gj.y, bv[2] - gj.z};
+                            double d = 0.0;
+#pragma unroll
+                            for (int ch = 0; ch < 3; ++ch) d += df[ch] * df[ch] + db[ch] * db[ch];
+                            smooth += wgt * d;
+                        }
+                    }
                 }
+#pragma unroll
+                for (int off = 32; off > 0; off >>= 1) {
+                    data += __shfl_xor(data, off);
+                    smooth += __shfl_xor(smooth, off);
+                }
+                constexpr int kWaves = kCoarseThreads / 64;
+                if ((tid & 63) == 0) {
+                    cv.red[tid >> 6] = data;
+                    cv.red[kWaves + (tid >> 6)] = smooth;
+                }
+                lds_sync();
+                double D = 0.0, Sm = 0.0;
+#pragma unroll
+                for (int q = 0; q < kWaves; ++q) {
+                    D += cv.red[q];
+                    Sm += cv.red[kWaves + q];
+                }
+                return D + Sm;
+            };
+            double e_prev = energy();
+            int k = 0;
+            for (;;) {
+                sweeps(2);
+                const double e = energy();
+                ++k;
+                const bool stop = fabs(e_prev - e) <= cv.tol * e_prev || k >= cv.max_passes;
+                if (uniform(stop ? 1 : 0)) break;
+                e_prev = e;
             }
+            if (tid == 0) cv.counts[l] = k;
         }
         if (l + 1 < args.nc) {
 #pragma unroll
@@ -377,6 +466,14 @@ __global__ __launch_bounds__(kCoarseThreads) void coarse_kernel(CoarseArgs args)
 }
 
 // Batch: workgroup b runs the coarse block of image b.
+// The coarse levels in the convergence form (float32 state and inputs).
+__global__ __launch_bounds__(kCoarseThreads) void coarse_conv_kernel(CoarseArgs args, double tol,
+                                                                     int max_passes, int *counts) {
+    __shared__ CoarseLds lds;
+    __shared__ double red[2 * (kCoarseThreads / 64)];
+    coarse_body<float, true>(args, lds, CoarseConv{tol, max_passes, counts, red});
+}
+
 template <typename T>
 __global__ __launch_bounds__(kCoarseThreads) void coarse_batch_kernel(const CoarseArgs *descs) {
     __shared__ CoarseLds lds;
@@ -1847,6 +1944,13 @@ int launch_coarse(const Plan &plan, const LevelSrc &src, void *Fo, void *Bo, flo
     make_coarse_args(plan, src, Fo, Bo, omega, eps, &a);
     FGE_DISPATCH(storage, coarse_kernel, dim3(1), dim3(kCoarseThreads), 0,
                  static_cast<hipStream_t>(stream), a);
+    return static_cast<int>(hipGetLastError());
+}
+
+int launch_coarse_converge(const CoarseArgs &a, double tol, int max_passes, int *counts,
+                           void *stream) {
+    hipLaunchKernelGGL(coarse_conv_kernel, dim3(1), dim3(kCoarseThreads), 0,
+                       static_cast<hipStream_t>(stream), a, tol, max_passes, counts);
     return static_cast<int>(hipGetLastError());
 }
 

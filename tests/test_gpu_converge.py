@@ -139,6 +139,37 @@ def test_converge_passes_matches_oracle(gpu, storage, wh, kind):
     assert err <= TOL[storage], err
 
 
+@pytest.mark.parametrize("coarse_max_px", [-1, 1024, 0])
+def test_converge_passes_coarse_block(gpu, coarse_max_px):
+    """The leading levels on the coarse block (decided on the device), on part of them, or on
+    none (every level host-driven): each against the oracle's loop under the same count rule, at
+    a size whose first six levels fit the block (300 x 220)."""
+    torch, fge = gpu
+    W, H = 300, 220
+    p = fge.default_params(coarse_max_px=coarse_max_px)
+    s = synth.strands(W, H, seed=71, n_strands=20)
+    I, a = to_dev(torch, fge, p, s)
+    tol = 1e-4
+    F, B, ps = fge.estimate_foreground_converge_passes(I, a, p, tol=tol, max_passes=150)
+    I64, a64 = inputs64(I, a)
+    Fo, Bo, ch, rel = oracle.ml_converge_every(I64, a64, 2, tol, 150, rel_cap=150)
+    print(f"coarse_max_px {coarse_max_px}: device passes {ps}, oracle passes {ch}")
+
+    def replay(lv, k):
+        sched = [2 * c for c in ch[:lv]] + [2 * k] + [0] * (len(ch) - lv - 1)
+        return oracle.ml_schedule(I64, a64, sched)
+
+    if check_counts(ps, ch, rel, tol, replay):
+        Fr, Br = Fo, Bo
+    else:
+        Fr, Br = oracle.ml_schedule(I64, a64, [2 * k for k in ps])
+    err = max(maxabs(F.double().cpu().numpy(), Fr), maxabs(B.double().cpu().numpy(), Br))
+    assert err <= 1e-4, err
+    # a pass cap the coarse block must honour too
+    _, _, ps3 = fge.estimate_foreground_converge_passes(I, a, p, tol=0.0, max_passes=3)
+    assert ps3 == [3] * len(ch)
+
+
 def test_converge_passes_limits(gpu):
     torch, fge = gpu
     p = fge.default_params()
