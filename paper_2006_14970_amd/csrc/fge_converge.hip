@@ -426,33 +426,40 @@ fge_status cv_run(const Plan &pl, const fge_params &p, const void *Iv, const voi
 //
 // Every level runs passes of two red-black sweeps on the fused kernels (the LDS tile kernel for
 // levels up to tile_max_px, the streaming kernel above; one memory round trip per pass), the
-// first pass resizing from the previous level.  After each pass the level's energy is reduced on
-// the device and written to pinned host memory, and the host stops the level when a pass changes
-// it by at most tol times its value before the pass (the energy before the first pass: the
-// previous level's result as the resize leaves it), or after max_passes passes.  The host keeps
-// passes in flight beyond the one it judges -- up to kCpDepthSmall for levels of at most
-// kCpSmallPx pixels, whose passes are shorter than a host round trip, one for larger levels --
-// each writing the next buffer of a ring that never wraps onto the accepted state.  The leading
+// first pass resizing from the previous level.  Each pass also reduces the energy of the state it
+// starts from (pass k: the energy after pass k - 1; pass 1: the previous level's result as the
+// resize leaves it) and writes it to pinned host memory, so the energy after pass k arrives with
+// pass k + 1; the host stops the level when a pass changes the energy by at most tol times its
+// value before the pass, or after max_passes passes.  The host keeps passes in flight beyond the
+// one it judges -- up to kCpSmallBufs - 2 on levels of at most kCpSmallPx pixels, whose passes
+// are shorter than a host round trip, two or three on larger levels -- each writing the next
+// buffer of a ring that never wraps onto the accepted state (pass k + 1 and the ones after it
+// are speculative: the level's result is the accepted pass's buffer).  The leading
 // levels that fit the coarse block's LDS (at most coarse_max_px pixels, all that fit when it is
 // 0, none when it is -1) run in one launch of the coarse block, which takes the same decisions
 // on the device (energy reduced in float64 in the workgroup) with no host round trip.  The state
 // stays float32 from level to level (inputs in float16 storage are converted once) and is
 // converted to the storage type when the last level is done.
 
-constexpr int kCpDepthSmall = 7;                 // passes in flight on small levels
 constexpr long kCpSmallPx = 1L << 16;
-constexpr int kCpSmallBufs = kCpDepthSmall + 2;  // the accepted state and kCpDepthSmall + 1 outputs
-constexpr int kCpSlots = 16;                     // energy slots in pinned memory (> any depth)
+constexpr int kCpSmallBufs = 9;   // small levels: the accepted state and a ring of 8 outputs
+constexpr int kCpBigBufs = 4;     // full-size buffers: the accepted state and a ring of 3
+constexpr int kCpSlots = 16;      // energy slots in pinned memory (> passes in flight)
 
 struct CpLayout {
-    size_t big[3] = {0, 0, 0}, small[kCpSmallBufs] = {}, in = 0, zero = 0, part = 0, total = 0;
+    size_t big[kCpBigBufs] = {}, small[kCpSmallBufs] = {}, in = 0, zero = 0, part = 0, total = 0;
+    int nparts = 0;               // partial sums of the largest pass
 };
 
-CpLayout cp_layout(int W, int H, int storage) {
+long cp_tile_max(const fge_params &p) {
+    return p.tile_max_px == 0 ? kTileMaxPxDefault : (p.tile_max_px < 0 ? 0 : p.tile_max_px);
+}
+
+CpLayout cp_layout(int W, int H, const fge_params &p) {
     CpLayout L;
     const size_t n = static_cast<size_t>(W) * H;
     size_t off = 0;
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 0; k < kCpBigBufs; ++k) {
         L.big[k] = off;
         off += a256(6 * n * sizeof(float));
     }
@@ -462,11 +469,21 @@ CpLayout cp_layout(int W, int H, int storage) {
         off += a256(6 * ns * sizeof(float));
     }
     L.in = off;
-    off += storage == FGE_F16 ? a256(4 * n * sizeof(float)) : 0;
+    off += p.storage == FGE_F16 ? a256(4 * n * sizeof(float)) : 0;
     L.zero = off;   // the 1 x 1 zero start (6 floats)
     off += 256;
+    const int nl = num_levels(W, H);
+    for (int j = 0; j < nl; ++j) {
+        LevelIO io{};
+        io.W = W;
+        io.H = H;
+        io.w = io.wp = level_size(W, j + 1, nl);
+        io.h = io.hp = level_size(H, j + 1, nl);
+        const bool tile = static_cast<long>(io.w) * io.h <= cp_tile_max(p);
+        L.nparts = std::max(L.nparts, pass_energy_parts(io, p.strip_rows, tile));
+    }
     L.part = off;
-    off += a256(static_cast<size_t>(energy_blocks(W, H)) * 5 * sizeof(double));
+    off += a256(static_cast<size_t>(L.nparts) * 5 * sizeof(double));
     L.total = off;
     return L;
 }
@@ -486,7 +503,7 @@ __global__ void cp_zero_kernel(float *z) {
 template <typename T>
 fge_status cp_run(const void *Iv, const void *Av, int W, int H, const fge_params &p, double tol,
                   int max_passes, void *F, void *B, int32_t *passes_out, char *ws, hipStream_t s) {
-    const CpLayout L = cp_layout(W, H, p.storage);
+    const CpLayout L = cp_layout(W, H, p);
     const size_t N = static_cast<size_t>(W) * H;
     const float *If = static_cast<const float *>(Iv), *Af = static_cast<const float *>(Av);
     if (p.storage == FGE_F16) {
@@ -500,10 +517,10 @@ fge_status cp_run(const void *Iv, const void *Av, int W, int H, const fge_params
     hipLaunchKernelGGL(cp_zero_kernel, dim3(1), dim3(64), 0, s, zero);
     if (hipGetLastError() != hipSuccess) return FGE_EHIP;
     double *part = reinterpret_cast<double *>(ws + L.part);
-    const long tile_max = p.tile_max_px == 0 ? kTileMaxPxDefault : (p.tile_max_px < 0 ? 0 : p.tile_max_px);
+    const long tile_max = cp_tile_max(p);
 
-    // pinned, mapped: the energy kernels write fge_energy's 6 outputs of measurement m into slot
-    // m % kCpSlots; an event after each tells the host the slot is complete
+    // pinned, mapped: the energy of the state after pass m (written with pass m + 1) goes to slot
+    // m % kCpSlots as fge_energy's 6 outputs; an event after each tells the host it is complete
     // (after the slots: the pass counts of the coarse block's levels)
     double *host = nullptr, *hdev = nullptr;
     const size_t slot_bytes = kCpSlots * 6 * sizeof(double);
@@ -516,22 +533,14 @@ fge_status cp_run(const void *Iv, const void *Av, int W, int H, const fge_params
     for (int k = 0; k < kCpSlots && ret == FGE_OK; ++k)
         if (hipEventCreateWithFlags(&ev[k], hipEventDisableTiming) != hipSuccess) ret = FGE_EHIP;
 
-    auto measure = [&](int m, const float *Fs, int fw, int fh, int w, int h) {
-        const int sl = m % kCpSlots;
-        if (launch_energy_mapped(If, Af, W, H, Fs, Fs + 3 * static_cast<size_t>(fw) * fh, fw, fh, w,
-                                 h, p.omega, p.eps_r, FGE_F32, FGE_F32, nullptr, part, hdev + 6 * sl,
-                                 s) ||
-            hipEventRecord(ev[sl], s) != hipSuccess)
-            ret = FGE_EHIP;
-    };
     auto wait = [&](int m) {
         if (ret == FGE_OK && hipEventSynchronize(ev[m % kCpSlots]) != hipSuccess) ret = FGE_EHIP;
         return ret == FGE_OK ? reinterpret_cast<volatile double *>(host)[6 * (m % kCpSlots)] : 0.0;
     };
 
-    // buffers: ids 0..2 the full-size ring, 3.. the small ring
+    // buffers: ids 0 .. kCpBigBufs - 1 the full-size ring, then the small ring
     auto buf = [&](int id) {
-        return reinterpret_cast<float *>(ws + (id < 3 ? L.big[id] : L.small[id - 3]));
+        return reinterpret_cast<float *>(ws + (id < kCpBigBufs ? L.big[id] : L.small[id - kCpBigBufs]));
     };
     const int n = num_levels(W, H);
     int prev = -1, wp = 1, hp = 1;   // the accepted state: buffer id (-1: the zero start), size
@@ -558,14 +567,14 @@ fge_status cp_run(const void *Iv, const void *Av, int W, int H, const fge_params
             c.lit[l] = 2;
         }
         c.nc = nc;
-        float *dst = buf(3);
+        float *dst = buf(kCpBigBufs);
         c.Fo = dst;
         c.Bo = dst + 3 * static_cast<size_t>(c.lw[nc - 1]) * c.lh[nc - 1];
         c.omega = p.omega;
         c.eps = p.eps_r;
         int *dcounts = reinterpret_cast<int *>(reinterpret_cast<char *>(hdev) + slot_bytes);
         if (launch_coarse_converge(c, tol, max_passes, dcounts, s)) ret = FGE_EHIP;
-        prev = 3;
+        prev = kCpBigBufs;
         wp = c.lw[nc - 1];
         hp = c.lh[nc - 1];
     }
@@ -573,13 +582,17 @@ fge_status cp_run(const void *Iv, const void *Av, int W, int H, const fge_params
         const int w = level_size(W, j + 1, n), h = level_size(H, j + 1, n);
         const long px = static_cast<long>(w) * h;
         const bool small = px <= kCpSmallPx;
+        const int lo = small ? kCpBigBufs : 0, hi_id = small ? kCpBigBufs + kCpSmallBufs : kCpBigBufs;
         int outs[kCpSmallBufs], R = 0;
-        for (int id = small ? 3 : 0; id < (small ? 3 + kCpSmallBufs : 3); ++id)
-            if (id != prev && R < kCpSmallBufs - 1 + (small ? 0 : 1)) outs[R++] = id;
-        const int depth = R - 1;   // passes in flight beyond the one judged
+        for (int id = lo; id < hi_id; ++id)
+            if (id != prev && R < kCpSmallBufs - 1) outs[R++] = id;
+        // Judging pass k needs pass k + 1 (its energy); passes up to k + R - 1 may be in flight,
+        // none of which writes pass k's buffer outs[(k - 1) % R].
         const float *Fprev = prev < 0 ? zero : buf(prev);
         const bool tile = px <= tile_max;
-        // pass k (1-based): from the accepted previous level or from pass k - 1, into outs[(k - 1) % R]
+        int parts = 0;
+        // pass k (1-based): from the accepted previous level or from pass k - 1, into
+        // outs[(k - 1) % R]; with it, the energy of its start state into slot k - 1
         auto pass = [&](int k) {
             LevelIO io{};
             io.I = If;
@@ -598,23 +611,25 @@ fge_status cp_run(const void *Iv, const void *Av, int W, int H, const fge_params
             io.h = h;
             io.omega = p.omega;
             io.eps = p.eps_r;
-            const int err = tile ? launch_fine_tile(io, FGE_F32, s)
-                                 : launch_fine_fused(io, p.strip_rows, FGE_F32, s);
-            if (err) ret = FGE_EHIP;
-            measure(k, dst, w, h, w, h);
+            if (parts == 0) parts = pass_energy_parts(io, p.strip_rows, tile);
+            const int sl = (k - 1) % kCpSlots;
+            if (launch_pass_energy(io, p.strip_rows, tile, part, s) ||
+                launch_energy_final(part, parts, hdev + 6 * sl, s) ||
+                hipEventRecord(ev[sl], s) != hipSuccess)
+                ret = FGE_EHIP;
         };
-        measure(0, Fprev, wp, hp, w, h);
         int hi = 0;   // passes enqueued
         auto fill = [&](int upto) {
             while (ret == FGE_OK && hi < std::min(upto, max_passes)) pass(++hi);
         };
-        fill(1 + depth);
+        fill(R);
         double e_prev = wait(0);
         int k = 1;
         for (;;) {
-            fill(k + depth);
+            if (ret != FGE_OK || k >= max_passes) break;
+            fill(k + R - 1);
             const double e = wait(k);
-            if (ret != FGE_OK || std::fabs(e_prev - e) <= tol * e_prev || k >= max_passes) break;
+            if (ret != FGE_OK || std::fabs(e_prev - e) <= tol * e_prev) break;
             e_prev = e;
             ++k;
         }
@@ -682,7 +697,7 @@ fge_status estimate_converge(const void *I, const void *A, int W, int H, const f
 
 size_t converge_passes_workspace_bytes(int W, int H, const fge_params &p) {
     if (W < 1 || H < 1 || W > kMaxSide || H > kMaxSide) return 0;
-    return cp_layout(W, H, p.storage).total;
+    return cp_layout(W, H, p).total;
 }
 
 fge_status estimate_converge_passes(const void *I, const void *A, int W, int H,

@@ -140,6 +140,12 @@ int launch_coarse(const Plan &plan, const LevelSrc &src, void *Fo, void *Bo, flo
                   float eps, int storage, void *stream);
 int launch_fine_fused(const LevelIO &io, int strip_rows, int storage, void *stream);
 int launch_fine_tile(const LevelIO &io, int storage, void *stream);
+// A pass of the convergence form (float32 state; the tile kernel when `tile`, else the streaming
+// kernel) that also reduces the energy of the state it starts from -- the previous pass's result,
+// or the previous level as the resize leaves it -- into pass_energy_parts() partial sums at epart
+// (5 doubles each, fge_energy's layout; energy_final_kernel totals them).
+int pass_energy_parts(const LevelIO &io, int strip_rows, bool tile);
+int launch_pass_energy(const LevelIO &io, int strip_rows, bool tile, double *epart, void *stream);
 int launch_naive_level(const LevelIO &io, int iters, int storage, void *stream);
 
 
@@ -251,6 +257,9 @@ int launch_energy_mapped(const void *I, const void *A, int W, int H, const void 
                          int fw, int fh, int w, int h, float omega, float eps, int storage,
                          int state_storage, const int *stop, double *part, double *out,
                          void *stream);
+// Totals nb partial sums of fge_energy's layout (5 doubles each) into out[0..5], as fge_energy
+// reports them (out[0] the energy).
+int launch_energy_final(const double *part, int nb, double *out, void *stream);
 
 // Level loop with the convergence stop or the Jacobi order (fge_converge.hip); tol < 0 runs the
 // fixed counts.

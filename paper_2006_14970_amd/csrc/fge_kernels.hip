@@ -588,10 +588,18 @@ __device__ __forceinline__ void tile_fetch(const T *I, const T *A, int W, int H,
 // absorbs the stale neighbours (one ring per half-sweep).  Previous-level values taken from LDS
 // are rounded to the storage type first, as they would have been on their way through memory,
 // so the result does not depend on the path.
-template <typename T, bool PREV_LDS>
+//
+// EN (the energy kernel): before sweeping, the workgroup also reduces the energy of the state it
+// loaded over its core pixels (data term, right and lower edge of each, so every edge of the
+// level once; each pixel's terms in float32, summed in float64) and thread 0 writes it to
+// epart[5 * unit] (then zeros; the layout of fge_energy's partial sums).  ered: kTileThreads / 64
+// doubles of LDS.
+template <typename T, bool PREV_LDS, bool EN = false>
 __device__ __forceinline__ void tile_level(const TileInput &in, int w, int h, const TilePrev &pv,
                                            const TileRegion &R, float4 *sFA, float4 *sB,
-                                           float omega, float eps, T *Fo, T *Bo) {
+                                           float omega, float eps, T *Fo, T *Bo,
+                                           double *epart = nullptr, int unit = 0,
+                                           double *ered = nullptr) {
     const T *Fp = static_cast<const T *>(pv.Fp);
     const T *Bp = static_cast<const T *>(pv.Bp);
     const size_t planeP = static_cast<size_t>(pv.wp) * pv.hp;
@@ -645,6 +653,55 @@ __device__ __forceinline__ void tile_level(const TileInput &in, int w, int h, co
                 sB[li] = lb[k][s];
             }
     lds_sync();
+
+    if constexpr (EN) {
+        double acc = 0.0;
+#pragma unroll
+        for (int k = 0; k < kTilePairsPerThread; ++k)
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                const int x = qx[k] + s, y = qy[k], gx = rx0 + x, gy = ry0 + y;
+                if (!(s ? qv1[k] : qv0[k]) || gx < R.cx0 || gx >= R.cx1 || gy < R.cy0 || gy >= R.cy1)
+                    continue;
+                const float4 f = lf[k][s], g = lb[k][s];
+                const float a = f.w, b = 1.0f - a;
+                const float fv[3] = {f.x, f.y, f.z}, bv[3] = {g.x, g.y, g.z};
+                float e = 0.0f;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const float res = fmaf(a, fv[c], fmaf(b, bv[c], -in.iv[k][s][c]));
+                    e = fmaf(res, res, e);
+                }
+#pragma unroll
+                for (int dir = 0; dir < 2; ++dir) {
+                    if (dir == 0 ? gx + 1 >= w : gy + 1 >= h) continue;
+                    const int nx = x + (dir == 0), ny = y + (dir == 1);
+                    const int j = tile_slot(nx, ny, (rx0 + ry0 + nx + ny) & 1, pw);
+                    const float4 fj = sFA[j], gj = sB[j];
+                    const float fjv[3] = {fj.x, fj.y, fj.z}, bjv[3] = {gj.x, gj.y, gj.z};
+                    float d = 0.0f;
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        const float df = fv[c] - fjv[c], db = bv[c] - bjv[c];
+                        d = fmaf(df, df, fmaf(db, db, d));
+                    }
+                    e = fmaf(fmaf(omega, fabsf(a - fj.w), eps), d, e);
+                }
+                acc += static_cast<double>(e);
+            }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+        if ((tid & 63) == 0) ered[tid >> 6] = acc;
+        lds_sync();   // also: every neighbour read above is done before the sweeps write
+        if (tid == 0) {
+            double sum = 0.0;
+#pragma unroll
+            for (int q = 0; q < kTileThreads / 64; ++q) sum += ered[q];
+            double *o = epart + 5 * static_cast<size_t>(unit);
+            o[0] = sum;
+            o[1] = o[2] = o[3] = o[4] = 0.0;
+        }
+    }
 
     // Weights of the pixel updated in half-sweep c of each pair (colour-ordered, as in the
     // coarse kernel): slot (rx0 + ry0 + y + c) & 1 of the pair.
@@ -760,8 +817,9 @@ __device__ __forceinline__ void tile_level(const TileInput &in, int w, int h, co
 }
 
 // One fine level, output tile `tile`: the level's F and B come from the stored previous level.
-template <typename T>
-__device__ __forceinline__ void tile_body(const TileArgs &args, int tile, TileLds &lds) {
+template <typename T, bool EN = false>
+__device__ __forceinline__ void tile_body(const TileArgs &args, int tile, TileLds &lds,
+                                          double *epart = nullptr, double *ered = nullptr) {
     const int w = args.w, h = args.h;
     const int tx = tile % args.tiles_x, ty = tile / args.tiles_x;
     const int cx0 = tx * kTileCore, cy0 = ty * kTileCore;
@@ -774,14 +832,22 @@ __device__ __forceinline__ void tile_body(const TileArgs &args, int tile, TileLd
     TileInput in;
     tile_fetch<T>(static_cast<const T *>(args.I), static_cast<const T *>(args.A), args.W, args.H,
                   w, h, R, in);
-    tile_level<T, false>(in, w, h, pv, R, lds.FA, lds.B, args.omega, args.eps,
-                         static_cast<T *>(args.Fo), static_cast<T *>(args.Bo));
+    tile_level<T, false, EN>(in, w, h, pv, R, lds.FA, lds.B, args.omega, args.eps,
+                             static_cast<T *>(args.Fo), static_cast<T *>(args.Bo), epart, tile, ered);
 }
 
 template <typename T>
 __global__ __launch_bounds__(kTileThreads) void tile_kernel(TileArgs args) {
     __shared__ TileLds lds;
     tile_body<T>(args, blockIdx.x, lds);
+}
+
+// The convergence form's passes (float32 state): a tile pass that also reduces the energy of
+// the state it starts from, one partial per tile.
+__global__ __launch_bounds__(kTileThreads) void tile_energy_kernel(TileArgs args, double *epart) {
+    __shared__ TileLds lds;
+    __shared__ double ered[kTileThreads / 64];
+    tile_body<float, true>(args, blockIdx.x, lds, epart, ered);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -1063,6 +1129,7 @@ struct FineWin {
     float fv[kWin][2][3];
     float bv[kWin][2][3];
     float wl[kWin][2], wr[kWin][2], wu[kWin][2], wd[kWin][2], ka[kWin][2], kb[kWin][2];
+    double energy;   // the energy kernels only: this lane's share of the input state's energy
 };
 
 // floor(tc * num / den) for a row index tc that advances one at a time (uniform, no division).
@@ -1292,6 +1359,44 @@ __device__ __forceinline__ void fine_update(FineWin &v, const FineGeo &g) {
     }
 }
 
+// The energy of the state a pass starts from, accumulated while it streams (the energy kernels):
+// at step t, after row t is taken and before row t - 1's first half-sweep, rows t - 1 and t still
+// hold that state.  Row r = t - 1 (slot R, row r + 1 in slot D) adds, for each core pixel of the
+// lane, its data term and its right and lower edges (so every edge of the level once), each
+// pixel's terms summed in float32 and added to the lane's float64 total.
+template <int R, int D, bool EDGE>
+__device__ __forceinline__ void fine_energy(FineWin &v, const FineGeo &g, int r) {
+    if (r < g.y0 || r >= g.y1) return;   // core rows (wave-uniform)
+    const float omega = g.omega, eps = g.eps;
+    const bool down = r + 1 < g.h;
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        const float a = v.al[R][s], b = 1.0f - a;
+        float e = 0.0f;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const float res = fmaf(a, v.fv[R][s][c], fmaf(b, v.bv[R][s][c], -v.iv[R][s][c]));
+            e = fmaf(res, res, e);
+        }
+        // right neighbour: column b of the lane, or column a of the next lane
+        const float ar = s == 0 ? v.al[R][1] : from_right_z(v.al[R][0]);
+        float dr = 0.0f, dd = 0.0f;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const float fr = s == 0 ? v.fv[R][1][c] : from_right_z(v.fv[R][0][c]);
+            const float br = s == 0 ? v.bv[R][1][c] : from_right_z(v.bv[R][0][c]);
+            const float df = v.fv[R][s][c] - fr, db = v.bv[R][s][c] - br;
+            dr = fmaf(df, df, fmaf(db, db, dr));
+            const float dfd = v.fv[R][s][c] - v.fv[D][s][c], dbd = v.bv[R][s][c] - v.bv[D][s][c];
+            dd = fmaf(dfd, dfd, fmaf(dbd, dbd, dd));
+        }
+        const bool right = s == 0 ? !g.right_a : !g.right_b;
+        if (right) e = fmaf(fmaf(omega, fabsf(a - ar), eps), dr, e);
+        if (down) e = fmaf(fmaf(omega, fabsf(a - v.al[D][s]), eps), dd, e);
+        if (s == 0 ? g.store_a : g.store_b) v.energy += static_cast<double>(e);
+    }
+}
+
 template <typename T>
 __device__ __forceinline__ void bstore_pair(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff,
                                             float v0, float v1) {
@@ -1352,7 +1457,7 @@ __device__ __forceinline__ void fine_store_row(const FineWin &v, const FineGeo &
 // test: the wait counters must assume the worst where the paths join, which makes a later step
 // wait for the prefetch of its own rows.
 constexpr int kStCheck = 0, kStNone = 1, kStCore = 2;
-template <int TT, bool EDGE, bool BORDER, int PAIR, typename T, int ST>
+template <int TT, bool EDGE, bool BORDER, int PAIR, typename T, int ST, bool EN>
 __device__ __forceinline__ void fine_step(FineWin &v, const FineGeo &g, RowMap &mi, RowMap &mp,
                                           int t) {
     constexpr int S = (TT + 1) & 1;       // column of the pair updated in this step
@@ -1365,6 +1470,7 @@ __device__ __forceinline__ void fine_step(FineWin &v, const FineGeo &g, RowMap &
         fine_load_row<(TT + kPD) % kWin, PAIR, T>(v, g, mi.q, mp.q);
     }
     fine_consume<TT % kWin, T>(v);
+    if constexpr (EN) fine_energy<(TT + kWin - 1) % kWin, TT % kWin, EDGE>(v, g, t - 1);
     fine_constants<(TT + kWin - 1) % kWin, (TT + kWin - 2) % kWin, TT % kWin, EDGE, BORDER>(v, g, t - 1);
     fine_update<(TT + kWin - 1) % kWin, (TT + kWin - 2) % kWin, TT % kWin, S, EDGE>(v, g);
     fine_update<(TT + kWin - 2) % kWin, (TT + kWin - 3) % kWin, (TT + kWin - 1) % kWin, S, EDGE>(v, g);
@@ -1376,21 +1482,22 @@ __device__ __forceinline__ void fine_step(FineWin &v, const FineGeo &g, RowMap &
     __builtin_amdgcn_sched_barrier(0);
 }
 
-template <bool EDGE, bool BORDER, int PAIR, typename T, int ST = kStCheck>
+template <bool EDGE, bool BORDER, int PAIR, typename T, int ST, bool EN>
 __device__ __forceinline__ void fine_block(FineWin &v, const FineGeo &g, RowMap &mi, RowMap &mp,
                                            int t) {
-    fine_step<0, EDGE, BORDER, PAIR, T, ST>(v, g, mi, mp, t);
-    fine_step<1, EDGE, BORDER, PAIR, T, ST>(v, g, mi, mp, t + 1);
-    fine_step<2, EDGE, BORDER, PAIR, T, ST>(v, g, mi, mp, t + 2);
-    fine_step<3, EDGE, BORDER, PAIR, T, ST>(v, g, mi, mp, t + 3);
-    fine_step<4, EDGE, BORDER, PAIR, T, ST>(v, g, mi, mp, t + 4);
-    fine_step<5, EDGE, BORDER, PAIR, T, ST>(v, g, mi, mp, t + 5);
-    fine_step<6, EDGE, BORDER, PAIR, T, ST>(v, g, mi, mp, t + 6);
-    fine_step<7, EDGE, BORDER, PAIR, T, ST>(v, g, mi, mp, t + 7);
+    fine_step<0, EDGE, BORDER, PAIR, T, ST, EN>(v, g, mi, mp, t);
+    fine_step<1, EDGE, BORDER, PAIR, T, ST, EN>(v, g, mi, mp, t + 1);
+    fine_step<2, EDGE, BORDER, PAIR, T, ST, EN>(v, g, mi, mp, t + 2);
+    fine_step<3, EDGE, BORDER, PAIR, T, ST, EN>(v, g, mi, mp, t + 3);
+    fine_step<4, EDGE, BORDER, PAIR, T, ST, EN>(v, g, mi, mp, t + 4);
+    fine_step<5, EDGE, BORDER, PAIR, T, ST, EN>(v, g, mi, mp, t + 5);
+    fine_step<6, EDGE, BORDER, PAIR, T, ST, EN>(v, g, mi, mp, t + 6);
+    fine_step<7, EDGE, BORDER, PAIR, T, ST, EN>(v, g, mi, mp, t + 7);
 }
 
-template <typename T, bool EDGE, int PAIR>
-__device__ __forceinline__ void fine_strip(const FineArgs &args, int sx, int sy, int lane) {
+// Returns the lane's share of the input state's energy (EN), else 0.
+template <typename T, bool EDGE, int PAIR, bool EN>
+__device__ __forceinline__ double fine_strip(const FineArgs &args, int sx, int sy, int lane) {
     FineGeo g;
     const size_t planeI = static_cast<size_t>(args.W) * args.H * sizeof(T);
     const size_t planeP = static_cast<size_t>(args.wp) * args.hp * sizeof(T);
@@ -1459,6 +1566,7 @@ __device__ __forceinline__ void fine_strip(const FineArgs &args, int sx, int sy,
     g.tlast = g.y1 - 1 + kNHS;
 
     FineWin v;
+    v.energy = 0.0;
 #pragma unroll
     for (int r = 0; r < kWin; ++r)
 #pragma unroll
@@ -1503,27 +1611,28 @@ __device__ __forceinline__ void fine_strip(const FineArgs &args, int sx, int sy,
     const int nsteps = g.tlast - g.t0 + 1;
     if (t > 0 && g.y0 - t == kHalo && (nsteps & (kWin - 1)) == 0 && nsteps >= 3 * kWin &&
         t + nsteps <= h + 1) {
-        fine_block<EDGE, false, PAIR, T, kStNone>(v, g, mi, mp, t);
+        fine_block<EDGE, false, PAIR, T, kStNone, EN>(v, g, mi, mp, t);
         for (t += kWin; t + kWin <= g.tlast; t += kWin)
-            fine_block<EDGE, false, PAIR, T, kStCore>(v, g, mi, mp, t);
-        fine_block<EDGE, false, PAIR, T, kStCore>(v, g, mi, mp, t);
-        return;
+            fine_block<EDGE, false, PAIR, T, kStCore, EN>(v, g, mi, mp, t);
+        fine_block<EDGE, false, PAIR, T, kStCore, EN>(v, g, mi, mp, t);
+        return v.energy;
     }
     if (t <= 0 || t + kWin > h + 1)
-        fine_block<EDGE, true, PAIR, T, kStNone>(v, g, mi, mp, t);
+        fine_block<EDGE, true, PAIR, T, kStNone, EN>(v, g, mi, mp, t);
     else
-        fine_block<EDGE, false, PAIR, T, kStNone>(v, g, mi, mp, t);
+        fine_block<EDGE, false, PAIR, T, kStNone, EN>(v, g, mi, mp, t);
     t += kWin;
     for (; t <= g.tlast && t + kWin <= h + 1 && t - 4 < g.y0; t += kWin)
-        fine_block<EDGE, false, PAIR, T>(v, g, mi, mp, t);
+        fine_block<EDGE, false, PAIR, T, kStCheck, EN>(v, g, mi, mp, t);
     for (; t <= g.tlast && t + kWin <= h + 1 && t + 3 < g.y1; t += kWin)
-        fine_block<EDGE, false, PAIR, T, kStCore>(v, g, mi, mp, t);
-    for (; t <= g.tlast && t + kWin <= h + 1; t += kWin) fine_block<EDGE, false, PAIR, T>(v, g, mi, mp, t);
-    for (; t <= g.tlast; t += kWin) fine_block<EDGE, true, PAIR, T>(v, g, mi, mp, t);
+        fine_block<EDGE, false, PAIR, T, kStCore, EN>(v, g, mi, mp, t);
+    for (; t <= g.tlast && t + kWin <= h + 1; t += kWin) fine_block<EDGE, false, PAIR, T, kStCheck, EN>(v, g, mi, mp, t);
+    for (; t <= g.tlast; t += kWin) fine_block<EDGE, true, PAIR, T, kStCheck, EN>(v, g, mi, mp, t);
+    return v.energy;
 }
 
-template <typename T>
-__device__ __forceinline__ void fine_body(const FineArgs &args, int wave, int lane) {
+template <typename T, bool EN = false>
+__device__ __forceinline__ double fine_body(const FineArgs &args, int wave, int lane) {
     const int sx = wave % args.nx, sy = wave / args.nx;
     // Paired access needs the identity input map in x; sharing the previous level's column needs
     // the previous level exactly half as wide.  Interior strips start on even columns and keep
@@ -1539,17 +1648,17 @@ __device__ __forceinline__ void fine_body(const FineArgs &args, int wave, int la
     if (args.w <= kStripCols || sx == 0 || sx == args.nx - 1) {
         const bool edge_ok = sx == 0 || (args.w & 1) == 0;
         if (edge_ok && pair_full)
-            fine_strip<T, true, kPairFull>(args, sx, sy, lane);
+            return fine_strip<T, true, kPairFull, EN>(args, sx, sy, lane);
         else if (edge_ok && pair_in)
-            fine_strip<T, true, kPairIn>(args, sx, sy, lane);
+            return fine_strip<T, true, kPairIn, EN>(args, sx, sy, lane);
         else
-            fine_strip<T, true, kPairNone>(args, sx, sy, lane);
+            return fine_strip<T, true, kPairNone, EN>(args, sx, sy, lane);
     } else if (pair_full) {
-        fine_strip<T, false, kPairFull>(args, sx, sy, lane);
+        return fine_strip<T, false, kPairFull, EN>(args, sx, sy, lane);
     } else if (pair_in) {
-        fine_strip<T, false, kPairIn>(args, sx, sy, lane);
+        return fine_strip<T, false, kPairIn, EN>(args, sx, sy, lane);
     } else {
-        fine_strip<T, false, kPairNone>(args, sx, sy, lane);
+        return fine_strip<T, false, kPairNone, EN>(args, sx, sy, lane);
     }
 }
 
@@ -1569,6 +1678,24 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, 2) void fine_kernel(FineArgs a
     const int wave = uniform(pos * kWavesPerBlock + (threadIdx.x >> 6));
     if (wave >= units) return;
     fine_body<T>(args, wave, threadIdx.x & 63);
+}
+
+// The convergence form's passes (float32 state): the streaming pass that also reduces the energy
+// of the state it starts from, one partial per strip (epart[5 * strip], fge_energy's layout).
+__global__ __launch_bounds__(64 * kWavesPerBlock, 2) void fine_energy_kernel(FineArgs args,
+                                                                             double *epart) {
+    const int units = args.nx * args.ny;
+    const int pos = (blockIdx.x % kXcds) * fine_block_chunk(units) + blockIdx.x / kXcds;
+    const int wave = uniform(pos * kWavesPerBlock + (threadIdx.x >> 6));
+    if (wave >= units) return;
+    double e = fine_body<float, true>(args, wave, threadIdx.x & 63);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) e += __shfl_xor(e, off);
+    if ((threadIdx.x & 63) == 0) {
+        double *o = epart + 5 * static_cast<size_t>(wave);
+        o[0] = e;
+        o[1] = o[2] = o[3] = o[4] = 0.0;
+    }
 }
 
 // ------------------------------------------------------------------------------------------
@@ -2026,6 +2153,33 @@ int launch_fine_tile(const LevelIO &io, int storage, void *stream) {
     make_tile_args(io, &a);
     FGE_DISPATCH(storage, tile_kernel, dim3(tile_units(a)), dim3(kTileThreads), 0,
                  static_cast<hipStream_t>(stream), a);
+    return static_cast<int>(hipGetLastError());
+}
+
+int pass_energy_parts(const LevelIO &io, int strip_rows, bool tile) {
+    if (tile) {
+        TileArgs a;
+        make_tile_args(io, &a);
+        return tile_units(a);
+    }
+    FineArgs a;
+    make_fine_args(io, strip_rows, &a);
+    return fine_units(a);
+}
+
+int launch_pass_energy(const LevelIO &io, int strip_rows, bool tile, double *epart,
+                       void *stream) {
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (tile) {
+        TileArgs a;
+        make_tile_args(io, &a);
+        hipLaunchKernelGGL(tile_energy_kernel, dim3(tile_units(a)), dim3(kTileThreads), 0, s, a, epart);
+    } else {
+        FineArgs a;
+        make_fine_args(io, strip_rows, &a);
+        const int blocks = kXcds * fine_block_chunk(fine_units(a));
+        hipLaunchKernelGGL(fine_energy_kernel, dim3(blocks), dim3(64 * kWavesPerBlock), 0, s, a, epart);
+    }
     return static_cast<int>(hipGetLastError());
 }
 

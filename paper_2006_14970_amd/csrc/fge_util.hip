@@ -389,6 +389,12 @@ int launch_energy_mapped(const void *I, const void *A, int W, int H, const void 
     return static_cast<int>(hipGetLastError());
 }
 
+int launch_energy_final(const double *part, int nb, double *out, void *stream) {
+    hipLaunchKernelGGL(energy_final_kernel, dim3(1), dim3(kRedThreads), 0,
+                       static_cast<hipStream_t>(stream), part, nb, nullptr, out);
+    return static_cast<int>(hipGetLastError());
+}
+
 }  // namespace fge
 
 extern "C" {
