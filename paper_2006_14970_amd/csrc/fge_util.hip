@@ -11,6 +11,7 @@
 // blocks' partial sums by one workgroup in a fixed order, so the result is deterministic.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 
@@ -225,6 +226,90 @@ __global__ __launch_bounds__(kRedThreads) void quality_partial_kernel(const T *F
     if (threadIdx.x < 4) part[static_cast<size_t>(blockIdx.x) * 4 + threadIdx.x] = red[threadIdx.x][0];
 }
 
+// The same measures, tiled (radius up to kQMaxR): a workgroup takes a kQTx x kQTy tile, loads
+// D = F - G of the tile plus an r-pixel mirrored ring into LDS one channel at a time, filters the
+// rows (derivative and smoothing filter in x), then the columns (smoothing and derivative in y),
+// so a pixel costs 4 (2r + 1) multiply-adds per channel instead of 2 (2r + 1)^2 loads and
+// multiply-adds.  Same taps, same float64, another summation order.  One partial (4 sums) per
+// tile, reduced in a fixed order.
+constexpr int kQTx = 64, kQTy = 16, kQThreads = 256, kQMaxR = 8;
+constexpr int kQRw = kQTx + 2 * kQMaxR, kQRh = kQTy + 2 * kQMaxR;
+constexpr int kQPx = kQTx * kQTy / kQThreads;   // output pixels per thread
+
+template <typename T>
+__global__ __launch_bounds__(kQThreads) void quality_tile_kernel(const T *F, const T *G, const T *A,
+                                                                 int w, int h, GradFilter K,
+                                                                 double *part) {
+    __shared__ double sd[kQRh * kQRw];    // D over the region (row stride RW)
+    __shared__ double sx[kQRh * kQTx];    // rows filtered with the derivative
+    __shared__ double ss[kQRh * kQTx];    // rows filtered with the smoothing filter
+    __shared__ double red[4][kQThreads];
+    const int r = K.r, RW = kQTx + 2 * r, RH = kQTy + 2 * r;
+    const int tx0 = blockIdx.x * kQTx, ty0 = blockIdx.y * kQTy;
+    const int tid = threadIdx.x;
+    const size_t n = static_cast<size_t>(w) * h;
+    double s1[kQPx] = {}, s2[kQPx] = {}, g2[kQPx] = {};
+    for (int c = 0; c < 3; ++c) {
+        const T *Fc = F + c * n, *Gc = G + c * n;
+        __syncthreads();   // the previous channel's reads of sd, sx, ss are done
+        for (int i = tid; i < RW * RH; i += kQThreads) {
+            const int ry = i / RW, rx = i - ry * RW;
+            const size_t q = static_cast<size_t>(mirror(ty0 - r + ry, h)) * w + mirror(tx0 - r + rx, w);
+            sd[i] = ld(Fc, q) - ld(Gc, q);
+        }
+        __syncthreads();
+        for (int i = tid; i < kQTx * RH; i += kQThreads) {
+            const int ry = i / kQTx, ox = i - ry * kQTx;
+            const double *row = sd + ry * RW + ox;
+            double d = 0.0, p = 0.0;
+            for (int j = 0; j <= 2 * r; ++j) {
+                d += K.der[j] * row[j];
+                p += K.phi[j] * row[j];
+            }
+            sx[i] = d;
+            ss[i] = p;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kQPx; ++k) {
+            const int q = tid + k * kQThreads, oy = q / kQTx, ox = q - oy * kQTx;
+            double gx = 0.0, gy = 0.0;
+            for (int j = 0; j <= 2 * r; ++j) {
+                gx += K.phi[j] * sx[(oy + j) * kQTx + ox];
+                gy += K.der[j] * ss[(oy + j) * kQTx + ox];
+            }
+            g2[k] += gx * gx + gy * gy;
+            const double d = sd[(oy + r) * RW + ox + r];
+            s1[k] += fabs(d);
+            s2[k] += d * d;
+        }
+    }
+    double sad = 0.0, mse = 0.0, grad = 0.0, cnt = 0.0;
+#pragma unroll
+    for (int k = 0; k < kQPx; ++k) {
+        const int q = tid + k * kQThreads, x = tx0 + q % kQTx, y = ty0 + q / kQTx;
+        if (x >= w || y >= h) continue;
+        const double a = ld(A, static_cast<size_t>(y) * w + x);
+        if (!(a > 0.0 && a < 1.0)) continue;
+        sad += a * s1[k];
+        mse += a * s2[k];
+        grad += a * g2[k];
+        cnt += 1.0;
+    }
+    red[0][tid] = sad;
+    red[1][tid] = mse;
+    red[2][tid] = grad;
+    red[3][tid] = cnt;
+    __syncthreads();
+    for (int half = kQThreads / 2; half > 0; half >>= 1) {
+        if (tid < half)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) red[k][tid] += red[k][tid + half];
+        __syncthreads();
+    }
+    if (tid < 4) part[(static_cast<size_t>(blockIdx.y) * gridDim.x + blockIdx.x) * 4 + tid] = red[tid][0];
+}
+
 __global__ __launch_bounds__(kRedThreads) void quality_final_kernel(const double *part, int nb,
                                                                     double *out) {
     __shared__ double red[4][kRedThreads];
@@ -426,7 +511,9 @@ fge_status fge_energy(const void *I, const void *alpha, const void *F, const voi
 
 size_t fge_quality_workspace_bytes(int32_t H, int32_t W) {
     if (W < 1 || H < 1 || W > fge::kMaxSide || H > fge::kMaxSide) return 0;
-    return (static_cast<size_t>(fge::energy_blocks(W, H)) * 4 * sizeof(double) + 255) & ~static_cast<size_t>(255);
+    const size_t tiles = static_cast<size_t>((W + fge::kQTx - 1) / fge::kQTx) * ((H + fge::kQTy - 1) / fge::kQTy);
+    const size_t nb = std::max(tiles, static_cast<size_t>(fge::energy_blocks(W, H)));
+    return (nb * 4 * sizeof(double) + 255) & ~static_cast<size_t>(255);
 }
 
 fge_status fge_quality(const void *F, const void *G, const void *alpha, int32_t H, int32_t W,
@@ -450,6 +537,21 @@ fge_status fge_quality(const void *F, const void *G, const void *alpha, int32_t 
     }
     hipStream_t s = static_cast<hipStream_t>(stream);
     double *part = static_cast<double *>(workspace);
+    if (r <= fge::kQMaxR) {
+        const dim3 grid((W + fge::kQTx - 1) / fge::kQTx, (H + fge::kQTy - 1) / fge::kQTy);
+        if (dtype == FGE_F16)
+            hipLaunchKernelGGL(fge::quality_tile_kernel<_Float16>, grid, dim3(fge::kQThreads), 0, s,
+                               static_cast<const _Float16 *>(F), static_cast<const _Float16 *>(G),
+                               static_cast<const _Float16 *>(alpha), W, H, K, part);
+        else
+            hipLaunchKernelGGL(fge::quality_tile_kernel<float>, grid, dim3(fge::kQThreads), 0, s,
+                               static_cast<const float *>(F), static_cast<const float *>(G),
+                               static_cast<const float *>(alpha), W, H, K, part);
+        if (hipGetLastError() != hipSuccess) return FGE_EHIP;
+        hipLaunchKernelGGL(fge::quality_final_kernel, dim3(1), dim3(fge::kRedThreads), 0, s, part,
+                           static_cast<int>(grid.x * grid.y), out);
+        return hipGetLastError() == hipSuccess ? FGE_OK : FGE_EHIP;
+    }
     const int nb = fge::energy_blocks(W, H);
     if (dtype == FGE_F16)
         hipLaunchKernelGGL(fge::quality_partial_kernel<_Float16>, dim3(nb), dim3(fge::kRedThreads),
