@@ -434,7 +434,9 @@ fge_status cv_run(const Plan &pl, const fge_params &p, const void *Iv, const voi
 // one it judges -- up to kCpSmallBufs - 2 on levels of at most kCpSmallPx pixels, whose passes
 // are shorter than a host round trip, two or three on larger levels -- each writing the next
 // buffer of a ring that never wraps onto the accepted state (pass k + 1 and the ones after it
-// are speculative: the level's result is the accepted pass's buffer).  The leading
+// are speculative: the level's result is the accepted pass's buffer).  The device applies the
+// same rule to the same values as it totals each energy, so the speculative passes after the
+// stop return at once.  The leading
 // levels that fit the coarse block's LDS (at most coarse_max_px pixels, all that fit when it is
 // 0, none when it is -1) run in one launch of the coarse block, which takes the same decisions
 // on the device (energy reduced in float64 in the workgroup) with no host round trip.  The state
@@ -447,7 +449,8 @@ constexpr int kCpBigBufs = 4;     // full-size buffers: the accepted state and a
 constexpr int kCpSlots = 16;      // energy slots in pinned memory (> passes in flight)
 
 struct CpLayout {
-    size_t big[kCpBigBufs] = {}, small[kCpSmallBufs] = {}, in = 0, zero = 0, part = 0, total = 0;
+    size_t big[kCpBigBufs] = {}, small[kCpSmallBufs] = {}, in = 0, zero = 0, ctl = 0, part = 0,
+           total = 0;
     int nparts = 0;               // partial sums of the largest pass
 };
 
@@ -471,6 +474,8 @@ CpLayout cp_layout(int W, int H, const fge_params &p) {
     L.in = off;
     off += p.storage == FGE_F16 ? a256(4 * n * sizeof(float)) : 0;
     L.zero = off;   // the 1 x 1 zero start (6 floats)
+    off += 256;
+    L.ctl = off;    // the device's copy of the stop rule (PassCtl)
     off += 256;
     const int nl = num_levels(W, H);
     for (int j = 0; j < nl; ++j) {
@@ -517,6 +522,7 @@ fge_status cp_run(const void *Iv, const void *Av, int W, int H, const fge_params
     hipLaunchKernelGGL(cp_zero_kernel, dim3(1), dim3(64), 0, s, zero);
     if (hipGetLastError() != hipSuccess) return FGE_EHIP;
     double *part = reinterpret_cast<double *>(ws + L.part);
+    PassCtl *ctl = reinterpret_cast<PassCtl *>(ws + L.ctl);
     const long tile_max = cp_tile_max(p);
 
     // pinned, mapped: the energy of the state after pass m (written with pass m + 1) goes to slot
@@ -613,8 +619,10 @@ fge_status cp_run(const void *Iv, const void *Av, int W, int H, const fge_params
             io.eps = p.eps_r;
             if (parts == 0) parts = pass_energy_parts(io, p.strip_rows, tile);
             const int sl = (k - 1) % kCpSlots;
-            if (launch_pass_energy(io, p.strip_rows, tile, part, s) ||
-                launch_energy_final(part, parts, hdev + 6 * sl, s) ||
+            // the device applies the stop rule too: passes after the one that reports the stop
+            // (pass k + 1 reports the energy after pass k) return at once
+            if (launch_pass_energy(io, p.strip_rows, tile, part, k == 1 ? nullptr : &ctl->stop, s) ||
+                launch_pass_final(part, parts, hdev + 6 * sl, ctl, k, tol, s) ||
                 hipEventRecord(ev[sl], s) != hipSuccess)
                 ret = FGE_EHIP;
         };

@@ -144,8 +144,10 @@ int launch_fine_tile(const LevelIO &io, int storage, void *stream);
 // kernel) that also reduces the energy of the state it starts from -- the previous pass's result,
 // or the previous level as the resize leaves it -- into pass_energy_parts() partial sums at epart
 // (5 doubles each, fge_energy's layout; energy_final_kernel totals them).
+// A non-null `skip` holding a non-zero value turns the pass into a no-op (see PassCtl).
 int pass_energy_parts(const LevelIO &io, int strip_rows, bool tile);
-int launch_pass_energy(const LevelIO &io, int strip_rows, bool tile, double *epart, void *stream);
+int launch_pass_energy(const LevelIO &io, int strip_rows, bool tile, double *epart,
+                       const int *skip, void *stream);
 int launch_naive_level(const LevelIO &io, int iters, int storage, void *stream);
 
 
@@ -260,6 +262,17 @@ int launch_energy_mapped(const void *I, const void *A, int W, int H, const void 
 // Totals nb partial sums of fge_energy's layout (5 doubles each) into out[0..5], as fge_energy
 // reports them (out[0] the energy).
 int launch_energy_final(const double *part, int nb, double *out, void *stream);
+// The convergence form's stop rule on the device, beside the host's: pass m's total (the energy
+// after pass m - 1) also updates ctl -- m == 1 starts the level (e_prev = that energy, stop = 0);
+// m > 1 sets stop when |e_prev - e| <= tol e_prev, else e_prev = e.  Once stop is set the later
+// passes and totals of the level do nothing (the host, judging the same values, stops there too).
+struct PassCtl {
+    double e_prev;
+    int stop;
+    int pad;
+};
+int launch_pass_final(const double *part, int nb, double *out, PassCtl *ctl, int m, double tol,
+                      void *stream);
 
 // Level loop with the convergence stop or the Jacobi order (fge_converge.hip); tol < 0 runs the
 // fixed counts.

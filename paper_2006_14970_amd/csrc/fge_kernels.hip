@@ -843,8 +843,11 @@ __global__ __launch_bounds__(kTileThreads) void tile_kernel(TileArgs args) {
 }
 
 // The convergence form's passes (float32 state): a tile pass that also reduces the energy of
-// the state it starts from, one partial per tile.
-__global__ __launch_bounds__(kTileThreads) void tile_energy_kernel(TileArgs args, double *epart) {
+// the state it starts from, one partial per tile.  A non-null `skip` holding a non-zero value
+// (the level has stopped) makes the launch a no-op.
+__global__ __launch_bounds__(kTileThreads) void tile_energy_kernel(TileArgs args, double *epart,
+                                                                  const int *skip) {
+    if (skip && *skip) return;
     __shared__ TileLds lds;
     __shared__ double ered[kTileThreads / 64];
     tile_body<float, true>(args, blockIdx.x, lds, epart, ered);
@@ -1683,7 +1686,9 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, 2) void fine_kernel(FineArgs a
 // The convergence form's passes (float32 state): the streaming pass that also reduces the energy
 // of the state it starts from, one partial per strip (epart[5 * strip], fge_energy's layout).
 __global__ __launch_bounds__(64 * kWavesPerBlock, 2) void fine_energy_kernel(FineArgs args,
-                                                                             double *epart) {
+                                                                             double *epart,
+                                                                             const int *skip) {
+    if (skip && *skip) return;   // the level has stopped
     const int units = args.nx * args.ny;
     const int pos = (blockIdx.x % kXcds) * fine_block_chunk(units) + blockIdx.x / kXcds;
     const int wave = uniform(pos * kWavesPerBlock + (threadIdx.x >> 6));
@@ -2168,17 +2173,19 @@ int pass_energy_parts(const LevelIO &io, int strip_rows, bool tile) {
 }
 
 int launch_pass_energy(const LevelIO &io, int strip_rows, bool tile, double *epart,
-                       void *stream) {
+                       const int *skip, void *stream) {
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (tile) {
         TileArgs a;
         make_tile_args(io, &a);
-        hipLaunchKernelGGL(tile_energy_kernel, dim3(tile_units(a)), dim3(kTileThreads), 0, s, a, epart);
+        hipLaunchKernelGGL(tile_energy_kernel, dim3(tile_units(a)), dim3(kTileThreads), 0, s, a, epart,
+                           skip);
     } else {
         FineArgs a;
         make_fine_args(io, strip_rows, &a);
         const int blocks = kXcds * fine_block_chunk(fine_units(a));
-        hipLaunchKernelGGL(fine_energy_kernel, dim3(blocks), dim3(64 * kWavesPerBlock), 0, s, a, epart);
+        hipLaunchKernelGGL(fine_energy_kernel, dim3(blocks), dim3(64 * kWavesPerBlock), 0, s, a,
+                           epart, skip);
     }
     return static_cast<int>(hipGetLastError());
 }

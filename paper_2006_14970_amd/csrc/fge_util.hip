@@ -146,6 +146,44 @@ __global__ __launch_bounds__(kRedThreads) void energy_final_kernel(const double 
     }
 }
 
+// energy_final_kernel's total plus the convergence form's stop rule (PassCtl).
+__global__ __launch_bounds__(kRedThreads) void pass_final_kernel(const double *part, int nb,
+                                                                 double *out, PassCtl *ctl, int m,
+                                                                 double tol) {
+    if (m > 1 && ctl->stop) return;
+    __shared__ double red[2][kRedThreads];
+    double acc[2] = {0.0, 0.0};
+    for (int b = threadIdx.x; b < nb; b += kRedThreads) {
+        acc[0] += part[static_cast<size_t>(b) * 5];
+        acc[1] += part[static_cast<size_t>(b) * 5 + 1];
+    }
+    red[0][threadIdx.x] = acc[0];
+    red[1][threadIdx.x] = acc[1];
+    __syncthreads();
+    for (int half = kRedThreads / 2; half > 0; half >>= 1) {
+        if (threadIdx.x < half) {
+            red[0][threadIdx.x] += red[0][threadIdx.x + half];
+            red[1][threadIdx.x] += red[1][threadIdx.x + half];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double e = red[0][0] + red[1][0];
+        out[0] = e;
+        out[1] = red[0][0];
+        out[2] = red[1][0];
+        out[3] = out[4] = out[5] = 0.0;
+        if (m == 1) {
+            ctl->e_prev = e;
+            ctl->stop = 0;
+        } else if (fabs(ctl->e_prev - e) <= tol * ctl->e_prev) {
+            ctl->stop = 1;
+        } else {
+            ctl->e_prev = e;
+        }
+    }
+}
+
 // ---- quality measures and compositing -------------------------------------------------------
 //
 // The paper's error measures of a foreground estimate F against a reference G (Section IV,
@@ -477,6 +515,13 @@ int launch_energy_mapped(const void *I, const void *A, int W, int H, const void 
 int launch_energy_final(const double *part, int nb, double *out, void *stream) {
     hipLaunchKernelGGL(energy_final_kernel, dim3(1), dim3(kRedThreads), 0,
                        static_cast<hipStream_t>(stream), part, nb, nullptr, out);
+    return static_cast<int>(hipGetLastError());
+}
+
+int launch_pass_final(const double *part, int nb, double *out, PassCtl *ctl, int m, double tol,
+                      void *stream) {
+    hipLaunchKernelGGL(pass_final_kernel, dim3(1), dim3(kRedThreads), 0,
+                       static_cast<hipStream_t>(stream), part, nb, out, ctl, m, tol);
     return static_cast<int>(hipGetLastError());
 }
 
