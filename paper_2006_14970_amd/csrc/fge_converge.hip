@@ -430,13 +430,13 @@ fge_status cv_run(const Plan &pl, const fge_params &p, const void *Iv, const voi
 // starts from (pass k: the energy after pass k - 1; pass 1: the previous level's result as the
 // resize leaves it) and writes it to pinned host memory, so the energy after pass k arrives with
 // pass k + 1; the host stops the level when a pass changes the energy by at most tol times its
-// value before the pass, or after max_passes passes.  The host keeps passes in flight beyond the
-// one it judges -- up to kCpSmallBufs - 2 on levels of at most kCpSmallPx pixels, whose passes
-// are shorter than a host round trip, two or three on larger levels -- each writing the next
-// buffer of a ring that never wraps onto the accepted state (pass k + 1 and the ones after it
-// are speculative: the level's result is the accepted pass's buffer).  The device applies the
-// same rule to the same values as it totals each energy, so the speculative passes after the
-// stop return at once.  The leading
+// value before the pass, or after max_passes passes.  The device applies the same rule to the
+// same values as it totals each energy, so once a level stops at pass k (reported by pass
+// k + 1's total) every later pass of the level returns at once and writes nothing; the passes
+// write a ring of output buffers in turn, and with two or more of them pass k + 1 never writes
+// pass k's.  So the host can keep passes in flight beyond the one it judges at no risk to the
+// accepted state -- kCpDepthSmall on levels of at most kCpSmallPx pixels, whose passes are
+// shorter than a host round trip, kCpDepthBig on larger ones.  The leading
 // levels that fit the coarse block's LDS (at most coarse_max_px pixels, all that fit when it is
 // 0, none when it is -1) run in one launch of the coarse block, which takes the same decisions
 // on the device (energy reduced in float64 in the workgroup) with no host round trip.  The state
@@ -444,8 +444,10 @@ fge_status cv_run(const Plan &pl, const fge_params &p, const void *Iv, const voi
 // converted to the storage type when the last level is done.
 
 constexpr long kCpSmallPx = 1L << 16;
-constexpr int kCpSmallBufs = 9;   // small levels: the accepted state and a ring of 8 outputs
-constexpr int kCpBigBufs = 4;     // full-size buffers: the accepted state and a ring of 3
+constexpr int kCpSmallBufs = 3;   // small levels: the accepted state and a ring of 2 outputs
+constexpr int kCpBigBufs = 3;     // full-size: likewise
+constexpr int kCpDepthSmall = 7;  // passes in flight beyond the one judged
+constexpr int kCpDepthBig = 3;
 constexpr int kCpSlots = 16;      // energy slots in pinned memory (> passes in flight)
 
 struct CpLayout {
@@ -592,8 +594,9 @@ fge_status cp_run(const void *Iv, const void *Av, int W, int H, const fge_params
         int outs[kCpSmallBufs], R = 0;
         for (int id = lo; id < hi_id; ++id)
             if (id != prev && R < kCpSmallBufs - 1) outs[R++] = id;
-        // Judging pass k needs pass k + 1 (its energy); passes up to k + R - 1 may be in flight,
-        // none of which writes pass k's buffer outs[(k - 1) % R].
+        // Judging pass k needs pass k + 1 (its energy); passes up to k + 1 + depth are in
+        // flight (see above: after a stop at k, the passes from k + 2 on write nothing).
+        const int depth = small ? kCpDepthSmall : kCpDepthBig;
         const float *Fprev = prev < 0 ? zero : buf(prev);
         const bool tile = px <= tile_max;
         int parts = 0;
@@ -630,12 +633,12 @@ fge_status cp_run(const void *Iv, const void *Av, int W, int H, const fge_params
         auto fill = [&](int upto) {
             while (ret == FGE_OK && hi < std::min(upto, max_passes)) pass(++hi);
         };
-        fill(R);
+        fill(2 + depth);
         double e_prev = wait(0);
         int k = 1;
         for (;;) {
             if (ret != FGE_OK || k >= max_passes) break;
-            fill(k + R - 1);
+            fill(k + 1 + depth);
             const double e = wait(k);
             if (ret != FGE_OK || std::fabs(e_prev - e) <= tol * e_prev) break;
             e_prev = e;
