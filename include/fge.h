@@ -177,7 +177,8 @@ fge_status fge_estimate_foreground_noalloc(const void *I, const void *alpha, int
  * and levels (float16 inputs are converted once) and F, B are written in p->storage at the end.
  * Red-black order only (FGE_EUNSUPPORTED for Jacobi).  Workspace:
  * fge_converge_passes_workspace_bytes (three float32 states at full size, about 72 B/px, plus
- * 16 B/px of float32 inputs in float16 storage). */
+ * 16 B/px of float32 inputs in float16 storage, plus the float32 inputs of the largest level
+ * below full size, about 4 B/px). */
 size_t fge_converge_passes_workspace_bytes(int32_t H, int32_t W, const fge_params *p);
 fge_status fge_estimate_foreground_converge_passes(const void *I, const void *alpha, int32_t H,
                                                    int32_t W, const fge_params *p, double tol,

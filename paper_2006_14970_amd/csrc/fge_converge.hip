@@ -451,8 +451,8 @@ constexpr int kCpDepthBig = 3;
 constexpr int kCpSlots = 16;      // energy slots in pinned memory (> passes in flight)
 
 struct CpLayout {
-    size_t big[kCpBigBufs] = {}, small[kCpSmallBufs] = {}, in = 0, zero = 0, ctl = 0, part = 0,
-           total = 0;
+    size_t big[kCpBigBufs] = {}, small[kCpSmallBufs] = {}, in = 0, lin = 0, zero = 0, ctl = 0,
+           part = 0, total = 0;
     int nparts = 0;               // partial sums of the largest pass
 };
 
@@ -475,6 +475,13 @@ CpLayout cp_layout(int W, int H, const fge_params &p) {
     }
     L.in = off;
     off += p.storage == FGE_F16 ? a256(4 * n * sizeof(float)) : 0;
+    // a level's inputs resized once (I, alpha planes), for the levels below full resolution
+    const int nl0 = num_levels(W, H);
+    size_t lin_px = 0;
+    for (int j = 0; j + 1 < nl0; ++j)
+        lin_px = std::max(lin_px, static_cast<size_t>(level_size(W, j + 1, nl0)) * level_size(H, j + 1, nl0));
+    L.lin = off;
+    off += a256(4 * lin_px * sizeof(float));
     L.zero = off;   // the 1 x 1 zero start (6 floats)
     off += 256;
     L.ctl = off;    // the device's copy of the stop rule (PassCtl)
@@ -501,6 +508,23 @@ __global__ __launch_bounds__(kCvThreads) void cp_to_f32_kernel(const T *I, const
     for (size_t p = static_cast<size_t>(blockIdx.x) * kCvThreads + threadIdx.x; p < 4 * n;
          p += static_cast<size_t>(gridDim.x) * kCvThreads)
         out[p] = static_cast<float>(p < 3 * n ? I[p] : A[p - 3 * n]);
+}
+
+// I and alpha of a w x h level from the full-resolution float32 inputs by the nearest map (the
+// passes' own map, integer division), into 4 compact planes: every pass of the level then reads
+// its inputs with the identity map.
+__global__ __launch_bounds__(kCvThreads) void cp_compact_kernel(const float *I, const float *A, int W,
+                                                               int H, int w, int h, float *out) {
+    const size_t n = static_cast<size_t>(w) * h, N = static_cast<size_t>(W) * H;
+    for (size_t p = static_cast<size_t>(blockIdx.x) * kCvThreads + threadIdx.x; p < n;
+         p += static_cast<size_t>(gridDim.x) * kCvThreads) {
+        const int y = static_cast<int>(p / w), x = static_cast<int>(p - static_cast<size_t>(y) * w);
+        const size_t q = static_cast<size_t>(static_cast<long long>(y) * H / h) * W +
+                         static_cast<size_t>(static_cast<long long>(x) * W / w);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) out[c * n + p] = I[c * N + q];
+        out[3 * n + p] = A[q];
+    }
 }
 
 __global__ void cp_zero_kernel(float *z) {
@@ -600,14 +624,27 @@ fge_status cp_run(const void *Iv, const void *Av, int W, int H, const fge_params
         const float *Fprev = prev < 0 ? zero : buf(prev);
         const bool tile = px <= tile_max;
         int parts = 0;
+        // inputs: full resolution for the finest level, else the level's compact copy
+        const float *Il = If, *Al = Af;
+        int Wl = W, Hl = H;
+        if (w != W || h != H) {
+            float *lin = reinterpret_cast<float *>(ws + L.lin);
+            hipLaunchKernelGGL(cp_compact_kernel, dim3(blocks_for(static_cast<size_t>(w) * h)),
+                               dim3(kCvThreads), 0, s, If, Af, W, H, w, h, lin);
+            if (hipGetLastError() != hipSuccess) ret = FGE_EHIP;
+            Il = lin;
+            Al = lin + 3 * static_cast<size_t>(w) * h;
+            Wl = w;
+            Hl = h;
+        }
         // pass k (1-based): from the accepted previous level or from pass k - 1, into
         // outs[(k - 1) % R]; with it, the energy of its start state into slot k - 1
         auto pass = [&](int k) {
             LevelIO io{};
-            io.I = If;
-            io.A = Af;
-            io.W = W;
-            io.H = H;
+            io.I = Il;
+            io.A = Al;
+            io.W = Wl;
+            io.H = Hl;
             const float *src = k == 1 ? Fprev : buf(outs[(k - 2) % R]);
             io.Fp = src;
             io.wp = k == 1 ? wp : w;
