@@ -1162,8 +1162,11 @@ struct RowMap {
 //              lane's two columns are adjacent in I and alpha (one load per plane) and in F and
 //              B (one store per plane); the previous level is read per pixel;
 //   kPairFull  as kPairIn, and the previous level is exactly half as wide: both columns read
-//              the same previous-level column (one load per plane).
-constexpr int kPairNone = 0, kPairIn = 1, kPairFull = 2;
+//              the same previous-level column (one load per plane);
+//   kPairSame  as kPairIn, and the previous state has the level's own size (the passes of the
+//              convergence form after the first): a lane's two columns are adjacent there too
+//              (one load per plane).
+constexpr int kPairNone = 0, kPairIn = 1, kPairFull = 2, kPairSame = 3;
 
 // Gather one row into slot R: I and alpha from input row qi (nearest), F and B from
 // previous-level row qp.  float32 lands in the float window directly; binary16 lands as raw
@@ -1199,6 +1202,16 @@ __device__ __forceinline__ void fine_load_row(FineWin &v, const FineGeo &g, int 
                 const uint32_t cp = sp + c * g.pP;
                 v.fv[R][0][c] = v.fv[R][1][c] = loadf(g.P, g.spa, cp);
                 v.bv[R][0][c] = v.bv[R][1][c] = loadf(g.P, g.spa, cp + 3 * g.pP);
+            }
+        } else if constexpr (PAIR == kPairSame) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const uint32_t cp = sp + c * g.pP;
+                const f32x2 fv = loadf2(g.P, g.spa, cp), bv = loadf2(g.P, g.spa, cp + 3 * g.pP);
+                v.fv[R][0][c] = fv.x;
+                v.fv[R][1][c] = fv.y;
+                v.bv[R][0][c] = bv.x;
+                v.bv[R][1][c] = bv.y;
             }
         } else {
 #pragma unroll
@@ -1237,6 +1250,16 @@ __device__ __forceinline__ void fine_load_row(FineWin &v, const FineGeo &g, int 
                 const uint32_t cp = sp + c * g.pP;
                 v.rf[R][0][c] = v.rf[R][1][c] = bload<T>(g.P, g.spa, cp);
                 v.rb[R][0][c] = v.rb[R][1][c] = bload<T>(g.P, g.spa, cp + 3 * g.pP);
+            }
+        } else if constexpr (PAIR == kPairSame) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const uint32_t cp = sp + c * g.pP;
+                const uint32_t fv = bload<float>(g.P, g.spa, cp), bv = bload<float>(g.P, g.spa, cp + 3 * g.pP);
+                v.rf[R][0][c] = fv;
+                v.rf[R][1][c] = fv >> 16;
+                v.rb[R][0][c] = bv;
+                v.rb[R][1][c] = bv >> 16;
             }
         } else {
 #pragma unroll
@@ -1648,14 +1671,19 @@ __device__ __forceinline__ double fine_body(const FineArgs &args, int wave, int 
     // strip (w <= 128) has lanes past the last column and stays unpaired.
     const bool pair_in = args.w == args.W && args.w > kStripCols;
     const bool pair_full = pair_in && 2 * args.wp == args.w;
+    const bool pair_same = pair_in && args.wp == args.w;   // instantiated for the energy kernel
     if (args.w <= kStripCols || sx == 0 || sx == args.nx - 1) {
         const bool edge_ok = sx == 0 || (args.w & 1) == 0;
+        if constexpr (EN)
+            if (edge_ok && pair_same) return fine_strip<T, true, kPairSame, EN>(args, sx, sy, lane);
         if (edge_ok && pair_full)
             return fine_strip<T, true, kPairFull, EN>(args, sx, sy, lane);
         else if (edge_ok && pair_in)
             return fine_strip<T, true, kPairIn, EN>(args, sx, sy, lane);
         else
             return fine_strip<T, true, kPairNone, EN>(args, sx, sy, lane);
+    } else if (EN && pair_same) {
+        return fine_strip<T, false, EN ? kPairSame : kPairIn, EN>(args, sx, sy, lane);
     } else if (pair_full) {
         return fine_strip<T, false, kPairFull, EN>(args, sx, sy, lane);
     } else if (pair_in) {
