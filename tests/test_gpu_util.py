@@ -97,6 +97,27 @@ def test_quality_matches_oracle(gpu, wh, storage):
         assert abs(got - want) <= 1e-10 * max(1e-30, abs(want)), (got, want)
 
 
+@pytest.mark.parametrize("sigma", [0.5, 1.9, 2.2, 3.5])
+def test_quality_filter_radius(gpu, sigma):
+    """Filter radii int(4 sigma + 0.5) of 2 and 8 (the tiled kernel's smallest and largest) and 9
+    and 14 (the direct sum), on a size with ragged tiles (70 x 37) and one smaller than the
+    radius (5 x 4, mirrored borders folding more than once)."""
+    torch, fge = gpu
+    from oracle import metrics
+    for W, H in ((70, 37), (5, 4)):
+        s = synth.strands(W, H, seed=5 * W + H, n_strands=2)
+        rng = np.random.default_rng(W + H)
+        a = torch.from_numpy(np.clip(s.alpha + rng.uniform(-0.05, 0.05, s.alpha.shape), 0, 1)).float().cuda()
+        G = torch.from_numpy(s.F).float().cuda()
+        F = torch.from_numpy(np.clip(s.F + rng.normal(0, 0.05, s.F.shape), 0, 1)).float().cuda()
+        out = fge.quality(F, G, a, sigma=sigma).cpu().numpy()
+        want = metrics.quality(F.double().cpu().numpy(), G.double().cpu().numpy(),
+                               a.double().cpu().numpy(), sigma)
+        assert out[3] == want[3]
+        for got, w in zip(out[:3], want[:3]):
+            assert abs(got - w) <= 1e-10 * max(1e-30, abs(w)), (sigma, W, H, got, w)
+
+
 @pytest.mark.parametrize("storage", ["f32", "f16"])
 def test_composite_bit_exact(gpu, storage):
     torch, fge = gpu
