@@ -555,8 +555,9 @@ def main():
                     help="also run a plain 512 MiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on one GPU only: the method has no multi-GPU path in this build "
-              "(images are independent; see the design notes on sharding).", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path (images are "
+              "independent, and a level would shard by row bands with a 4-row halo exchange).",
+              file=sys.stderr)
         sys.exit(2)
     if args.steps < 1 or args.warmup < 1:
         sys.exit("--steps and --warmup must be >= 1")
