@@ -180,11 +180,12 @@ def run_storage(torch, fge, sample, storage, steps, warmup, oracle_F=None, oracl
 
 
 def run_variants(torch, fge, sample):
-    """The per-level-kernel variants of the level loop on the 4096x3072 image, float16 storage:
-    the convergence form (tol 1e-4, at most 200 sweeps per level) in red-black and Jacobi order,
-    and the smooth resize variant (area / bilinear) with the fixed counts and converged.  Each:
-    time, sweeps per level, and quality against the ground truth; the fused path's quality (nearest
-    resize, fixed counts) is the reference point."""
+    """The variants of the level loop on the 4096x3072 image, float16 storage: the convergence form
+    (tol 1e-4, at most 200 sweeps per level) in red-black and Jacobi order on per-level kernels,
+    and the smooth resize variant (area / bilinear) with the fixed counts (sweeps on the fused
+    kernels) and converged (per-level kernels).  Each: time, sweeps per level, and quality against
+    the ground truth; the fused path's quality (nearest resize, fixed counts) is the reference
+    point."""
     dev = torch.device("cuda:0")
     I = torch.from_numpy(sample.I).half().to(dev).contiguous()
     a = torch.from_numpy(sample.alpha).half().to(dev).contiguous()
@@ -232,9 +233,10 @@ def run_variants(torch, fge, sample):
         f"per-level form), sweeps {[2 * k for k in ps]}, SAD {q[0]:.1f}")
     return {"workload": "4096x3072 strands image, float16 storage, per-level kernels: convergence "
                         "form (level energy change <= 1e-4 relative, <= 200 sweeps per level) and "
-                        "the smooth resize variant; converge_passes_redblack: the convergence form "
-                        "on the fused kernels, tested after every pass of two sweeps (<= 100 "
-                        "passes per level)", "unit": "MP/s", **out}
+                        "the smooth resize variant converged; smooth_fixed_counts: sweeps on the "
+                        "fused kernels; converge_passes_redblack: the convergence form on the "
+                        "fused kernels, tested after every pass of two sweeps (<= 100 passes per "
+                        "level)", "unit": "MP/s", **out}
 
 
 CF_BYTES_PER_PX_F32 = 488   # per pixel and PCG iteration, float32 matte: see run_closed_form

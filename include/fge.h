@@ -216,9 +216,14 @@ typedef struct fge_level_options {
     int32_t reserved0;
 } fge_level_options;
 
-/* The level loop on per-level kernels with these options (order from p->order): the general
- * form of fge_estimate_foreground_converge (which is resize NEAREST).  The smooth variant's level
- * inputs are float32 copies (area sums in float64).  Workspace: fge_levels_workspace_bytes. */
+/* The level loop with these options (order from p->order): the general form of
+ * fge_estimate_foreground_converge (which is resize NEAREST), on per-level kernels.  The smooth
+ * variant's level inputs are float32 copies (area sums in float64).  One exception: the smooth
+ * variant with the red-black order and fixed counts (tol < 0, kernel not FGE_KERNEL_NAIVE) runs a
+ * level's sweeps on the fused kernels, in passes of two sweeps between two float32 state buffers
+ * (plus one per-level sweep for an odd count); the same sweeps in another rounding order.
+ * Workspace: fge_levels_workspace_bytes (that case adds a second float32 state and, for binary16
+ * storage, float32 copies of I and alpha: 16 bytes per pixel). */
 size_t fge_levels_workspace_bytes(int32_t H, int32_t W, const fge_params *p,
                                   const fge_level_options *o);
 fge_status fge_estimate_foreground_levels(const void *I, const void *alpha, int32_t H, int32_t W,

@@ -12,7 +12,8 @@
 //
 // Resize variants: nearest (Algorithm 1 as read everywhere else) or smooth (the image and matte
 // area-averaged from full resolution into float32 level copies, the previous level's F and B
-// resized bilinearly).
+// resized bilinearly).  The smooth variant with the red-black order and fixed counts sweeps on
+// the fused kernels (cv_fused_sweeps).
 //
 // Orders: red-black (two half-sweeps in place, (x + y) even first) or Jacobi (every pixel from
 // the previous sweep's values: sweep into a temporary, copy back).  The per-pixel update is the
@@ -99,61 +100,65 @@ __global__ __launch_bounds__(kCvThreads) void cv_bilinear_kernel(const T *Fp, co
     }
 }
 
-// Area resize (smooth variant), separable: destination pixel x of an axis of nd pixels averages
-// the source over [x ns/nd, (x+1) ns/nd), every source pixel weighted by its overlap.  Pass 1
-// resizes the rows of the 4 input planes (I then alpha, W x H, type T) to w columns; pass 2 the
-// columns of that result to h rows.  Sums in float64, results in float32.
-__device__ __forceinline__ double area_sum_begin(int x, int ns, int nd, int *i0, int *i1, double *x0,
-                                                 double *x1) {
-    *x0 = static_cast<double>(x) * ns / nd;
-    *x1 = static_cast<double>(x + 1) * ns / nd;
+// Area resize (smooth variant), separable: destination pixel u of an axis of nd pixels averages
+// the source over [u ns/nd, (u+1) ns/nd), every source pixel weighted by its overlap.  Pass 1
+// (ROWS) resizes the rows of the 4 input planes (I then alpha, W x H, type T) to w columns; pass 2
+// the columns of that result (float32) to h rows.  Sums in float64, results in float32.  A launch
+// is a grid of (destination pixels of a row, rows, 4 planes); G lanes (a power of two up to 64,
+// about an eighth of the footprint's length) share one destination pixel: lane g takes source
+// pixels i0 + g, i0 + g + G, ..., and the group adds its partial sums in a fixed butterfly.  The
+// footprint's ends are u times the float64 quotient ns / nd (within a few ulps of u ns / nd; an
+// end that lands a rounding off an integer only adds or drops a pixel of weight ~1e-16).
+__device__ __forceinline__ double area_span(int u, double step, int ns, int *i0, int *i1,
+                                            double *x0, double *x1) {
+    *x0 = static_cast<double>(u) * step;
+    *x1 = static_cast<double>(u + 1) * step;
     *i0 = static_cast<int>(floor(*x0));
     *i1 = static_cast<int>(ceil(*x1));
     if (*i1 > ns) *i1 = ns;
     return *x1 - *x0;
 }
 
-template <typename T>
-__global__ __launch_bounds__(kCvThreads) void cv_area_rows_kernel(const T *I, const T *A, int W,
-                                                                  int H, int w, float *out) {
-    const size_t n = static_cast<size_t>(w) * H * 4;
-    for (size_t p = static_cast<size_t>(blockIdx.x) * kCvThreads + threadIdx.x; p < n;
-         p += static_cast<size_t>(gridDim.x) * kCvThreads) {
-        const int c = static_cast<int>(p / (static_cast<size_t>(w) * H));
-        const size_t r = p - static_cast<size_t>(c) * w * H;
-        const int y = static_cast<int>(r / w), x = static_cast<int>(r - static_cast<size_t>(y) * w);
-        const T *row = (c < 3 ? I + static_cast<size_t>(c) * W * H : A) + static_cast<size_t>(y) * W;
-        int i0, i1;
-        double x0, x1;
-        const double len = area_sum_begin(x, W, w, &i0, &i1, &x0, &x1);
-        double acc = 0.0;
-        for (int i = i0; i < i1; ++i) {
-            const double a = i > x0 ? i : x0, b = i + 1 < x1 ? i + 1 : x1;
-            acc += (b - a) * static_cast<float>(row[i]);
-        }
-        out[p] = static_cast<float>(acc / len);
-    }
+// log2 of the lanes per destination pixel for a footprint of ns / nd source pixels.
+int area_group_log2(int ns, int nd) {
+    const int f = (ns + nd - 1) / nd;
+    int lg = 0;
+    while ((8 << lg) < f && lg < 6) ++lg;
+    return lg;
 }
 
-__global__ __launch_bounds__(kCvThreads) void cv_area_cols_kernel(const float *in, int w, int H,
-                                                                  int h, float *out) {
-    const size_t n = static_cast<size_t>(w) * h * 4;
-    for (size_t p = static_cast<size_t>(blockIdx.x) * kCvThreads + threadIdx.x; p < n;
-         p += static_cast<size_t>(gridDim.x) * kCvThreads) {
-        const int c = static_cast<int>(p / (static_cast<size_t>(w) * h));
-        const size_t r = p - static_cast<size_t>(c) * w * h;
-        const int y = static_cast<int>(r / w), x = static_cast<int>(r - static_cast<size_t>(y) * w);
-        const float *col = in + static_cast<size_t>(c) * w * H + x;
-        int j0, j1;
-        double y0, y1;
-        const double len = area_sum_begin(y, H, h, &j0, &j1, &y0, &y1);
-        double acc = 0.0;
-        for (int j = j0; j < j1; ++j) {
-            const double a = j > y0 ? j : y0, b = j + 1 < y1 ? j + 1 : y1;
-            acc += (b - a) * col[static_cast<size_t>(j) * w];
-        }
-        out[p] = static_cast<float>(acc / len);
+// ROWS: I (3 planes) and A, W x H, into 4 planes of w x H.  Columns: I = the rows pass's output
+// (4 planes of w x H, float32), into 4 planes of w x h.  step = ns / nd of the resized axis.
+template <typename T, bool ROWS>
+__global__ __launch_bounds__(kCvThreads) void cv_area_kernel(const T *I, const T *A, int W, int H,
+                                                             int w, int h, int lg, double step,
+                                                             float *out) {
+    const int G = 1 << lg;
+    const int c = blockIdx.z, y = blockIdx.y;
+    const int t = blockIdx.x * kCvThreads + threadIdx.x;
+    const int x = t >> lg, g = t & (G - 1);
+    if (x >= w) return;   // whole groups: G divides the block
+    int i0, i1;
+    double x0, x1;
+    const double len = ROWS ? area_span(x, step, W, &i0, &i1, &x0, &x1)
+                            : area_span(y, step, H, &i0, &i1, &x0, &x1);
+    const T *line;
+    size_t stride;
+    if (ROWS) {
+        line = (c < 3 ? I + static_cast<size_t>(c) * W * H : A) + static_cast<size_t>(y) * W;
+        stride = 1;
+    } else {
+        line = I + static_cast<size_t>(c) * w * H + x;
+        stride = static_cast<size_t>(w);
     }
+    double acc = 0.0;
+    for (int i = i0 + g; i < i1; i += G) {
+        const double a = i > x0 ? i : x0, b = i + 1 < x1 ? i + 1 : x1;
+        acc += (b - a) * static_cast<float>(line[static_cast<size_t>(i) * stride]);
+    }
+    for (int off = G >> 1; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+    const int ho = ROWS ? H : h;
+    if (g == 0) out[(static_cast<size_t>(c) * ho + y) * w + x] = static_cast<float>(acc / len);
 }
 
 // The update of pixel (x, y) of a w x h level from the state (F, B), with I and alpha read from
@@ -275,11 +280,29 @@ __global__ void cv_check_kernel(const double *enow, double *eprev, int *stop, in
     eprev[0] = e;
 }
 
+// Fused passes (two sweeps per memory round trip) run on the LDS tile kernel up to tile_max_px
+// and on the streaming kernel above, except where a level's float32 state (6 planes, one buffer
+// resource) would reach 4 GiB, the reach of the streaming kernel's addressing.
+long cp_tile_max(const fge_params &p) {
+    return p.tile_max_px == 0 ? kTileMaxPxDefault : (p.tile_max_px < 0 ? 0 : p.tile_max_px);
+}
+bool cp_use_tile(long px, const fge_params &p) {
+    return px <= cp_tile_max(p) || 24LL * px >= (1LL << 32);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kCvThreads) void cp_to_f32_kernel(const T *I, const T *A, float *out,
+                                                               size_t n) {
+    for (size_t p = static_cast<size_t>(blockIdx.x) * kCvThreads + threadIdx.x; p < 4 * n;
+         p += static_cast<size_t>(gridDim.x) * kCvThreads)
+        out[p] = static_cast<float>(p < 3 * n ? I[p] : A[p - 3 * n]);
+}
+
 // Workspace: the naive plan's ping-pong level buffers (storage type), the float32 working state
 // and the float32 Jacobi temporary (6 planes at full size each), the energy partial sums, and a
 // small block of scalars.
 struct CvLayout {
-    size_t work = 0, temp = 0, lvin = 0, rows = 0, part = 0, scal = 0, total = 0;
+    size_t work = 0, temp = 0, lvin = 0, rows = 0, in32 = 0, part = 0, scal = 0, total = 0;
 };
 
 size_t a256(size_t v) { return (v + 255) & ~static_cast<size_t>(255); }
@@ -290,8 +313,13 @@ CvLayout cv_layout(const Plan &pl, bool jacobi, bool smooth) {
     const size_t planes6 = a256(6 * static_cast<size_t>(pl.W) * pl.H * sizeof(float));
     L.work = off;
     off += planes6;
+    // the smooth red-black variant sweeps on the fused kernels (cv_fused_sweeps): a second state
+    // buffer, and float32 copies of binary16 full-resolution inputs (4 planes)
+    const bool fused = smooth && !jacobi;
     L.temp = off;
-    off += jacobi ? planes6 : 0;
+    off += jacobi || fused ? planes6 : 0;
+    L.in32 = off;
+    off += fused && pl.elem == 2 ? a256(4 * static_cast<size_t>(pl.W) * pl.H * sizeof(float)) : 0;
     // smooth variant: the area-resized I and alpha of a level below full size (4 float planes)
     // and the row pass of that resize (4 planes of w x H), at the largest such level
     size_t lv_px = 0, rows_px = 0;
@@ -366,6 +394,43 @@ fge_status cv_sweep_level(const fge_params &p, const TI *I, const TI *A, int Wi,
     return FGE_OK;
 }
 
+// The fixed sweep count kmax of a smooth red-black level on the fused kernels: kmax / 2 passes
+// of two sweeps, each from one float32 state buffer of the level's size into the other (so the
+// previous state is read through the identity map), then one sweep on the per-level kernels when
+// kmax is odd.  I and alpha: float32 planes of Wi x Hi (the level's area copy, or full
+// resolution).  *out receives the buffer that holds the result (F, then B three planes on).
+fge_status cv_fused_sweeps(const fge_params &p, const float *I, const float *A, int Wi, int Hi,
+                           float *S0, float *S1, int w, int h, int kmax, float **out, hipStream_t s) {
+    const size_t n = static_cast<size_t>(w) * h;
+    const bool tile = cp_use_tile(static_cast<long>(n), p);
+    float *src = S0, *dst = S1;
+    for (int k = 0; k + 2 <= kmax; k += 2) {
+        LevelIO io{};
+        io.I = I;
+        io.A = A;
+        io.W = Wi;
+        io.H = Hi;
+        io.Fp = src;
+        io.Bp = src + 3 * n;
+        io.wp = w;
+        io.hp = h;
+        io.Fo = dst;
+        io.Bo = dst + 3 * n;
+        io.w = w;
+        io.h = h;
+        io.omega = p.omega;
+        io.eps = p.eps_r;
+        if (tile ? launch_fine_tile(io, FGE_F32, s) : launch_fine_fused(io, p.strip_rows, FGE_F32, s))
+            return FGE_EHIP;
+        std::swap(src, dst);
+    }
+    *out = src;
+    if (kmax & 1)
+        return cv_sweep_level<float>(p, I, A, Wi, Hi, FGE_F32, src, src + 3 * n, dst, dst + 3 * n, w,
+                                     h, false, 0.0, 1, nullptr, nullptr, nullptr, nullptr, nullptr, s);
+    return FGE_OK;
+}
+
 template <typename T>
 fge_status cv_run(const Plan &pl, const fge_params &p, const void *Iv, const void *Av, void *Fv,
                   void *Bv, int resize, double tol, int max_sweeps, int32_t *sweeps_out, char *ws,
@@ -380,6 +445,18 @@ fge_status cv_run(const Plan &pl, const fge_params &p, const void *Iv, const voi
     int *counts = sweeps_out ? sweeps_out : reinterpret_cast<int *>(ws + L.scal + 256);
     const T *I = static_cast<const T *>(Iv);
     const T *A = static_cast<const T *>(Av);
+    // the smooth red-black variant with fixed counts sweeps on the fused kernels
+    const bool fused = smooth && !conv && p.order == FGE_REDBLACK && p.kernel != FGE_KERNEL_NAIVE;
+    const float *I32 = static_cast<const float *>(Iv), *A32 = static_cast<const float *>(Av);
+    if (fused && p.storage == FGE_F16) {
+        const size_t N = static_cast<size_t>(pl.W) * pl.H;
+        float *in = reinterpret_cast<float *>(ws + L.in32);
+        hipLaunchKernelGGL(cp_to_f32_kernel<T>, dim3(blocks_for(4 * N)), dim3(kCvThreads), 0, s, I, A,
+                           in, N);
+        if (hipGetLastError() != hipSuccess) return FGE_EHIP;
+        I32 = in;
+        A32 = in + 3 * N;
+    }
     for (int j = 0; j < pl.n; ++j) {
         const LevelIO io = level_io(pl, ws, j, Iv, Av, Fv, Bv, p.omega, p.eps_r);
         const int w = io.w, h = io.h;
@@ -399,24 +476,34 @@ fge_status cv_run(const Plan &pl, const fge_params &p, const void *Iv, const voi
         if (hipGetLastError() != hipSuccess) return FGE_EHIP;
         const int kmax = conv ? max_sweeps : pl.lv[j].iters;
         fge_status st;
+        float *res = Fo;   // the level's result (F, then B)
         if (smooth && (w != pl.W || h != pl.H)) {
             float *lv = reinterpret_cast<float *>(ws + L.lvin);   // I (3 planes), alpha: w x h
             float *rows = reinterpret_cast<float *>(ws + L.rows);
-            hipLaunchKernelGGL(cv_area_rows_kernel<T>, dim3(blocks_for(4 * static_cast<size_t>(w) * pl.H)),
-                               dim3(kCvThreads), 0, s, I, A, pl.W, pl.H, w, rows);
-            hipLaunchKernelGGL(cv_area_cols_kernel, dim3(blocks_for(4 * n)), dim3(kCvThreads), 0, s,
-                               rows, w, pl.H, h, lv);
+            const int lgr = area_group_log2(pl.W, w), lgc = area_group_log2(pl.H, h);
+            const unsigned bx_r = static_cast<unsigned>(((static_cast<size_t>(w) << lgr) + kCvThreads - 1) / kCvThreads);
+            const unsigned bx_c = static_cast<unsigned>(((static_cast<size_t>(w) << lgc) + kCvThreads - 1) / kCvThreads);
+            hipLaunchKernelGGL((cv_area_kernel<T, true>), dim3(bx_r, pl.H, 4), dim3(kCvThreads), 0, s,
+                               I, A, pl.W, pl.H, w, h, lgr, static_cast<double>(pl.W) / w, rows);
+            hipLaunchKernelGGL((cv_area_kernel<float, false>), dim3(bx_c, h, 4), dim3(kCvThreads), 0,
+                               s, rows, static_cast<const float *>(nullptr), pl.W, pl.H, w, h, lgc,
+                               static_cast<double>(pl.H) / h, lv);
             if (hipGetLastError() != hipSuccess) return FGE_EHIP;
-            st = cv_sweep_level<float>(p, lv, lv + 3 * n, w, h, FGE_F32, Fo, Bo, Ft, Bt, w, h, conv,
-                                       tol, kmax, stop, counts + j, part, enow, eprev, s);
+            if (fused)
+                st = cv_fused_sweeps(p, lv, lv + 3 * n, w, h, Fo, Ft, w, h, kmax, &res, s);
+            else
+                st = cv_sweep_level<float>(p, lv, lv + 3 * n, w, h, FGE_F32, Fo, Bo, Ft, Bt, w, h,
+                                           conv, tol, kmax, stop, counts + j, part, enow, eprev, s);
+        } else if (fused) {
+            st = cv_fused_sweeps(p, I32, A32, pl.W, pl.H, Fo, Ft, w, h, kmax, &res, s);
         } else {
             st = cv_sweep_level<T>(p, I, A, pl.W, pl.H, p.storage, Fo, Bo, Ft, Bt, w, h, conv, tol,
                                    kmax, stop, counts + j, part, enow, eprev, s);
         }
         if (st != FGE_OK) return st;
         // the level's state, in the storage type
-        hipLaunchKernelGGL(cv_copy_kernel<T>, dim3(blocks_for(3 * n)), dim3(kCvThreads), 0, s, Fo,
-                           Bo, static_cast<T *>(io.Fo), static_cast<T *>(io.Bo), n, nullptr);
+        hipLaunchKernelGGL(cv_copy_kernel<T>, dim3(blocks_for(3 * n)), dim3(kCvThreads), 0, s, res,
+                           res + 3 * n, static_cast<T *>(io.Fo), static_cast<T *>(io.Bo), n, nullptr);
         if (hipGetLastError() != hipSuccess) return FGE_EHIP;
     }
     return FGE_OK;
@@ -456,10 +543,6 @@ struct CpLayout {
     int nparts = 0;               // partial sums of the largest pass
 };
 
-long cp_tile_max(const fge_params &p) {
-    return p.tile_max_px == 0 ? kTileMaxPxDefault : (p.tile_max_px < 0 ? 0 : p.tile_max_px);
-}
-
 CpLayout cp_layout(int W, int H, const fge_params &p) {
     CpLayout L;
     const size_t n = static_cast<size_t>(W) * H;
@@ -493,21 +576,13 @@ CpLayout cp_layout(int W, int H, const fge_params &p) {
         io.H = H;
         io.w = io.wp = level_size(W, j + 1, nl);
         io.h = io.hp = level_size(H, j + 1, nl);
-        const bool tile = static_cast<long>(io.w) * io.h <= cp_tile_max(p);
+        const bool tile = cp_use_tile(static_cast<long>(io.w) * io.h, p);
         L.nparts = std::max(L.nparts, pass_energy_parts(io, p.strip_rows, tile));
     }
     L.part = off;
     off += a256(static_cast<size_t>(L.nparts) * 5 * sizeof(double));
     L.total = off;
     return L;
-}
-
-template <typename T>
-__global__ __launch_bounds__(kCvThreads) void cp_to_f32_kernel(const T *I, const T *A, float *out,
-                                                               size_t n) {
-    for (size_t p = static_cast<size_t>(blockIdx.x) * kCvThreads + threadIdx.x; p < 4 * n;
-         p += static_cast<size_t>(gridDim.x) * kCvThreads)
-        out[p] = static_cast<float>(p < 3 * n ? I[p] : A[p - 3 * n]);
 }
 
 // I and alpha of a w x h level from the full-resolution float32 inputs by the nearest map (the
@@ -549,7 +624,6 @@ fge_status cp_run(const void *Iv, const void *Av, int W, int H, const fge_params
     if (hipGetLastError() != hipSuccess) return FGE_EHIP;
     double *part = reinterpret_cast<double *>(ws + L.part);
     PassCtl *ctl = reinterpret_cast<PassCtl *>(ws + L.ctl);
-    const long tile_max = cp_tile_max(p);
 
     // pinned, mapped: the energy of the state after pass m (written with pass m + 1) goes to slot
     // m % kCpSlots as fge_energy's 6 outputs; an event after each tells the host it is complete
@@ -622,7 +696,7 @@ fge_status cp_run(const void *Iv, const void *Av, int W, int H, const fge_params
         // flight (see above: after a stop at k, the passes from k + 2 on write nothing).
         const int depth = small ? kCpDepthSmall : kCpDepthBig;
         const float *Fprev = prev < 0 ? zero : buf(prev);
-        const bool tile = px <= tile_max;
+        const bool tile = cp_use_tile(px, p);
         int parts = 0;
         // inputs: full resolution for the finest level, else the level's compact copy
         const float *Il = If, *Al = Af;

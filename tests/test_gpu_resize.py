@@ -1,5 +1,8 @@
 """GPU tests of the smooth resize variant (area averaging of the image and matte, bilinear
-resize of F and B) against the oracle's form of Algorithm 1 with the same variant."""
+resize of F and B) against the oracle's form of Algorithm 1 with the same variant.  With the
+red-black order and fixed counts a level's sweeps run on the fused kernels (two sweeps per pass,
+the tile kernel or, above 2^18 px, the streaming kernel; an odd count ends with one sweep on the
+per-level kernels); otherwise on the per-level kernels."""
 import numpy as np
 import pytest
 
@@ -73,3 +76,49 @@ def test_nearest_levels_equal_converge_path(gpu):
     r2 = fge.estimate_foreground_converge(I, a, p, tol=1e-4, max_sweeps=50)
     torch.cuda.synchronize()
     assert torch.equal(r1[0], r2[0]) and torch.equal(r1[1], r2[1]) and torch.equal(r1[2], r2[2])
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+@pytest.mark.parametrize("wh,strip_rows", [((300, 200), 0), ((1024, 768), 0), ((1024, 768), 11)])
+def test_smooth_fused_passes_match_per_level_kernels(gpu, storage, wh, strip_rows):
+    """The fused passes against the per-level kernels (kernel NAIVE) on the same input: the same
+    sweeps in another rounding order, so equal to float32 rounding (in binary16 storage, up to
+    one unit in the last place where a level's rounding differs), and both within the tolerance
+    of the oracle."""
+    torch, fge = gpu
+    W, H = wh
+    st = fge.F16 if storage == "f16" else fge.F32
+    p = fge.default_params(storage=st, strip_rows=strip_rows)
+    q = fge.default_params(storage=st, kernel=fge.KERNEL_NAIVE)
+    dt = fge.storage_dtype(p)
+    s = synth.strands(W, H, seed=7 * W + H, n_strands=max(1, W * H // 4000))
+    I = torch.from_numpy(s.I).to(dt).cuda()
+    a = torch.from_numpy(s.alpha).to(dt).cuda()
+    F1, B1, _ = fge.estimate_foreground_levels(I, a, p, resize="smooth")
+    F2, B2, _ = fge.estimate_foreground_levels(I, a, q, resize="smooth")
+    torch.cuda.synchronize()
+    d = max(float((F1.double() - F2.double()).abs().max()), float((B1.double() - B2.double()).abs().max()))
+    print(f"fused vs per-level {storage} {W}x{H} rows {strip_rows}: {d:.2e}")
+    assert d <= (1e-5 if storage == "f32" else 2e-3)
+    Fo, Bo = oracle.ml_resize(I.double().cpu().numpy(), a.double().cpu().numpy(), "smooth")
+    err = max(maxabs(F1.double().cpu().numpy(), Fo), maxabs(B1.double().cpu().numpy(), Bo))
+    assert err <= TOL[storage]
+
+
+@pytest.mark.parametrize("iters", [(3, 3), (10, 1), (4, 5)])
+def test_smooth_fused_passes_any_sweep_count(gpu, iters):
+    """Sweep counts other than 10 / 2: whole passes, then one per-level sweep for an odd count."""
+    torch, fge = gpu
+    W, H = 333, 211
+    p = fge.default_params(iters_small=iters[0], iters_big=iters[1])
+    s = synth.strands(W, H, seed=91, n_strands=20)
+    I = torch.from_numpy(s.I).float().cuda()
+    a = torch.from_numpy(s.alpha).float().cuda()
+    F, B, _ = fge.estimate_foreground_levels(I, a, p, resize="smooth")
+    torch.cuda.synchronize()
+    sweeps = [k for _, _, k in oracle.level_plan(W, H, iters_small=iters[0], iters_big=iters[1])]
+    Fo, Bo = oracle.ml_resize(I.double().cpu().numpy(), a.double().cpu().numpy(), "smooth",
+                              sweeps=sweeps)
+    err = max(maxabs(F.double().cpu().numpy(), Fo), maxabs(B.double().cpu().numpy(), Bo))
+    print(f"smooth fused sweeps {iters}: {err:.2e}")
+    assert err <= TOL["f32"]
