@@ -103,10 +103,10 @@ void fge_default_params(fge_params *p);
 /* Human-readable name of a status code (static string). */
 const char *fge_status_string(int status);
 
-/* Library ABI version (increments when fge_params or a signature changes); this header is 8
+/* Library ABI version (increments when fge_params or a signature changes); this header is 9
  * (4 moved every size argument to height-first order, 5 added fge_estimate_foreground_noalloc,
  * 6 added the closed-form solve fge_closed_form, 7 the server's failure counters, cancellation
- * and simulated executor, 8 the convergence form in fused passes). */
+ * and simulated executor, 8 the convergence form in fused passes, 9 fge_level_options.passes). */
 int32_t fge_version(void);
 
 /* ---- host-only planning (no GPU needed) ---------------------------------------------- */
@@ -212,8 +212,13 @@ typedef struct fge_level_options {
     uint32_t size;         /* sizeof(fge_level_options) */
     int32_t resize;        /* fge_resize */
     double tol;            /* < 0: the fixed sweep counts; >= 0: the convergence form above */
-    int32_t max_sweeps;    /* convergence form: 1..100000 sweeps per level */
-    int32_t reserved0;
+    int32_t max_sweeps;    /* convergence form: 1..100000 sweeps (passes) per level */
+    int32_t passes;        /* 0: the test after every sweep, on per-level kernels; 1: the form of
+                              fge_estimate_foreground_converge_passes (red-black, tol >= 0, the test
+                              after every pass of two sweeps on the fused kernels, max_sweeps caps
+                              the passes and sweeps_out receives them; the call returns when the
+                              result is complete) with this resize variant; with SMOOTH no coarse
+                              block runs (its resize is the nearest map) */
 } fge_level_options;
 
 /* The level loop with these options (order from p->order): the general form of

@@ -538,12 +538,12 @@ constexpr int kCpDepthBig = 3;
 constexpr int kCpSlots = 16;      // energy slots in pinned memory (> passes in flight)
 
 struct CpLayout {
-    size_t big[kCpBigBufs] = {}, small[kCpSmallBufs] = {}, in = 0, lin = 0, zero = 0, ctl = 0,
-           part = 0, total = 0;
+    size_t big[kCpBigBufs] = {}, small[kCpSmallBufs] = {}, in = 0, lin = 0, rows = 0, zero = 0,
+           ctl = 0, part = 0, total = 0;
     int nparts = 0;               // partial sums of the largest pass
 };
 
-CpLayout cp_layout(int W, int H, const fge_params &p) {
+CpLayout cp_layout(int W, int H, const fge_params &p, bool smooth) {
     CpLayout L;
     const size_t n = static_cast<size_t>(W) * H;
     size_t off = 0;
@@ -565,6 +565,12 @@ CpLayout cp_layout(int W, int H, const fge_params &p) {
         lin_px = std::max(lin_px, static_cast<size_t>(level_size(W, j + 1, nl0)) * level_size(H, j + 1, nl0));
     L.lin = off;
     off += a256(4 * lin_px * sizeof(float));
+    // the smooth variant's area resize: its row pass (4 planes of w x H) at the widest level
+    size_t rows_px = 0;
+    for (int j = 0; smooth && j + 1 < nl0; ++j)
+        rows_px = std::max(rows_px, static_cast<size_t>(level_size(W, j + 1, nl0)) * H);
+    L.rows = off;
+    off += a256(4 * rows_px * sizeof(float));
     L.zero = off;   // the 1 x 1 zero start (6 floats)
     off += 256;
     L.ctl = off;    // the device's copy of the stop rule (PassCtl)
@@ -607,9 +613,10 @@ __global__ void cp_zero_kernel(float *z) {
 }
 
 template <typename T>
-fge_status cp_run(const void *Iv, const void *Av, int W, int H, const fge_params &p, double tol,
-                  int max_passes, void *F, void *B, int32_t *passes_out, char *ws, hipStream_t s) {
-    const CpLayout L = cp_layout(W, H, p);
+fge_status cp_run(const void *Iv, const void *Av, int W, int H, const fge_params &p, bool smooth,
+                  double tol, int max_passes, void *F, void *B, int32_t *passes_out, char *ws,
+                  hipStream_t s) {
+    const CpLayout L = cp_layout(W, H, p, smooth);
     const size_t N = static_cast<size_t>(W) * H;
     const float *If = static_cast<const float *>(Iv), *Af = static_cast<const float *>(Av);
     if (p.storage == FGE_F16) {
@@ -652,7 +659,8 @@ fge_status cp_run(const void *Iv, const void *Av, int W, int H, const fge_params
     int prev = -1, wp = 1, hp = 1;   // the accepted state: buffer id (-1: the zero start), size
 
     // the coarse block: the longest prefix of levels that fit its LDS and the limit
-    const int climit = p.coarse_max_px < 0 ? 0 : (p.coarse_max_px == 0 ? kCoarseMaxPx : p.coarse_max_px);
+    const int climit = p.coarse_max_px < 0 || smooth
+                           ? 0 : (p.coarse_max_px == 0 ? kCoarseMaxPx : p.coarse_max_px);
     int nc = 0;
     while (nc < n) {
         const int w = level_size(W, nc + 1, n), h = level_size(H, nc + 1, n);
@@ -703,26 +711,50 @@ fge_status cp_run(const void *Iv, const void *Av, int W, int H, const fge_params
         int Wl = W, Hl = H;
         if (w != W || h != H) {
             float *lin = reinterpret_cast<float *>(ws + L.lin);
-            hipLaunchKernelGGL(cp_compact_kernel, dim3(blocks_for(static_cast<size_t>(w) * h)),
-                               dim3(kCvThreads), 0, s, If, Af, W, H, w, h, lin);
+            if (smooth) {   // the level's area averages
+                float *rows = reinterpret_cast<float *>(ws + L.rows);
+                const int lgr = area_group_log2(W, w), lgc = area_group_log2(H, h);
+                const unsigned bx_r = static_cast<unsigned>(((static_cast<size_t>(w) << lgr) + kCvThreads - 1) / kCvThreads);
+                const unsigned bx_c = static_cast<unsigned>(((static_cast<size_t>(w) << lgc) + kCvThreads - 1) / kCvThreads);
+                hipLaunchKernelGGL((cv_area_kernel<float, true>), dim3(bx_r, H, 4), dim3(kCvThreads),
+                                   0, s, If, Af, W, H, w, h, lgr, static_cast<double>(W) / w, rows);
+                hipLaunchKernelGGL((cv_area_kernel<float, false>), dim3(bx_c, h, 4), dim3(kCvThreads),
+                                   0, s, rows, static_cast<const float *>(nullptr), W, H, w, h, lgc,
+                                   static_cast<double>(H) / h, lin);
+            } else {
+                hipLaunchKernelGGL(cp_compact_kernel, dim3(blocks_for(static_cast<size_t>(w) * h)),
+                                   dim3(kCvThreads), 0, s, If, Af, W, H, w, h, lin);
+            }
             if (hipGetLastError() != hipSuccess) ret = FGE_EHIP;
             Il = lin;
             Al = lin + 3 * static_cast<size_t>(w) * h;
             Wl = w;
             Hl = h;
         }
-        // pass k (1-based): from the accepted previous level or from pass k - 1, into
-        // outs[(k - 1) % R]; with it, the energy of its start state into slot k - 1
+        // The smooth variant's first pass starts from the previous level resized bilinearly to
+        // this level's size, put in outs[1] (pass 2 is the first to write it, after pass 1 has
+        // read it).
+        if (smooth && ret == FGE_OK) {
+            float *st = buf(outs[1]);
+            const size_t n = static_cast<size_t>(w) * h;
+            hipLaunchKernelGGL(cv_bilinear_kernel<float>, dim3(blocks_for(n)), dim3(kCvThreads), 0, s,
+                               Fprev, Fprev + 3 * static_cast<size_t>(wp) * hp, wp, hp, st, st + 3 * n,
+                               w, h);
+            if (hipGetLastError() != hipSuccess) ret = FGE_EHIP;
+        }
+        // pass k (1-based): from the accepted previous level (smooth: its resize) or from pass
+        // k - 1, into outs[(k - 1) % R]; with it, the energy of its start state into slot k - 1
         auto pass = [&](int k) {
             LevelIO io{};
             io.I = Il;
             io.A = Al;
             io.W = Wl;
             io.H = Hl;
-            const float *src = k == 1 ? Fprev : buf(outs[(k - 2) % R]);
+            const bool from_prev = k == 1 && !smooth;
+            const float *src = from_prev ? Fprev : buf(outs[(k - 2 + R) % R]);
             io.Fp = src;
-            io.wp = k == 1 ? wp : w;
-            io.hp = k == 1 ? hp : h;
+            io.wp = from_prev ? wp : w;
+            io.hp = from_prev ? hp : h;
             io.Bp = src + 3 * static_cast<size_t>(io.wp) * io.hp;
             float *dst = buf(outs[(k - 1) % R]);
             io.Fo = dst;
@@ -777,20 +809,39 @@ fge_status cp_run(const void *Iv, const void *Av, int W, int H, const fge_params
 
 }  // namespace
 
-size_t levels_workspace_bytes(int W, int H, const fge_params &p, int resize) {
+size_t levels_workspace_bytes(int W, int H, const fge_params &p, int resize, int passes) {
+    if (passes)
+        return converge_passes_workspace_bytes(W, H, p, resize == FGE_RESIZE_SMOOTH);
     Plan pl;
     if (cv_plan(W, H, p, &pl) != FGE_OK) return 0;
     return cv_layout(pl, p.order == FGE_JACOBI, resize == FGE_RESIZE_SMOOTH).total;
 }
 
 size_t converge_workspace_bytes(int W, int H, const fge_params &p) {
-    return levels_workspace_bytes(W, H, p, FGE_RESIZE_NEAREST);
+    return levels_workspace_bytes(W, H, p, FGE_RESIZE_NEAREST, 0);
 }
 
 fge_status estimate_levels(const void *I, const void *A, int W, int H, const fge_params &p,
-                           int resize, double tol, int max_sweeps, void *F, void *B,
+                           int resize, double tol, int max_sweeps, int passes, void *F, void *B,
                            int32_t *sweeps_out, void *workspace, size_t workspace_bytes,
                            void *stream) {
+    if (passes != 0 && passes != 1) return FGE_EINVAL;
+    if (resize != FGE_RESIZE_NEAREST && resize != FGE_RESIZE_SMOOTH) return FGE_EINVAL;
+    if (passes) {   // the test after every pass of two sweeps, on the fused kernels
+        // (the pass counts come back to the host, which takes the stop decisions; sweeps_out is
+        // device memory here, as in the per-level form)
+        int32_t counts[kMaxLevels] = {};
+        const fge_status st = estimate_converge_passes(I, A, W, H, p, tol, max_sweeps, F, B, counts,
+                                                       workspace, workspace_bytes, stream,
+                                                       resize == FGE_RESIZE_SMOOTH);
+        if (st != FGE_OK || !sweeps_out) return st;
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        if (hipMemcpyAsync(sweeps_out, counts, num_levels(W, H) * sizeof(int32_t),
+                           hipMemcpyHostToDevice, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return FGE_EHIP;
+        return FGE_OK;
+    }
     Plan pl;
     const fge_status st = cv_plan(W, H, p, &pl);
     if (st != FGE_OK) return st;
@@ -813,19 +864,19 @@ fge_status estimate_levels(const void *I, const void *A, int W, int H, const fge
 fge_status estimate_converge(const void *I, const void *A, int W, int H, const fge_params &p,
                              double tol, int max_sweeps, void *F, void *B, int32_t *sweeps_out,
                              void *workspace, size_t workspace_bytes, void *stream) {
-    return estimate_levels(I, A, W, H, p, FGE_RESIZE_NEAREST, tol, max_sweeps, F, B, sweeps_out,
+    return estimate_levels(I, A, W, H, p, FGE_RESIZE_NEAREST, tol, max_sweeps, 0, F, B, sweeps_out,
                            workspace, workspace_bytes, stream);
 }
 
-size_t converge_passes_workspace_bytes(int W, int H, const fge_params &p) {
+size_t converge_passes_workspace_bytes(int W, int H, const fge_params &p, bool smooth) {
     if (W < 1 || H < 1 || W > kMaxSide || H > kMaxSide) return 0;
-    return cp_layout(W, H, p).total;
+    return cp_layout(W, H, p, smooth).total;
 }
 
 fge_status estimate_converge_passes(const void *I, const void *A, int W, int H,
                                     const fge_params &p, double tol, int max_passes, void *F,
                                     void *B, int32_t *passes_out, void *workspace,
-                                    size_t workspace_bytes, void *stream) {
+                                    size_t workspace_bytes, void *stream, bool smooth) {
     if (!params_valid(p)) return FGE_EINVAL;
     if (p.order != FGE_REDBLACK) return FGE_EUNSUPPORTED;   // the fused kernels are red-black
     if (W < 1 || H < 1 || W > kMaxSide || H > kMaxSide) return FGE_EINVAL;
@@ -834,14 +885,14 @@ fge_status estimate_converge_passes(const void *I, const void *A, int W, int H,
         return FGE_EINVAL;
     if (outputs_alias(I, A, F, B, W, H, p.storage == FGE_F16 ? 2 : 4, workspace, workspace_bytes))
         return FGE_EINVAL;
-    const size_t need = converge_passes_workspace_bytes(W, H, p);
+    const size_t need = converge_passes_workspace_bytes(W, H, p, smooth);
     if (!workspace || workspace_bytes < need || (reinterpret_cast<uintptr_t>(workspace) & 255))
         return FGE_EWORKSPACE;
     char *ws = static_cast<char *>(workspace);
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (p.storage == FGE_F16)
-        return cp_run<_Float16>(I, A, W, H, p, tol, max_passes, F, B, passes_out, ws, s);
-    return cp_run<float>(I, A, W, H, p, tol, max_passes, F, B, passes_out, ws, s);
+        return cp_run<_Float16>(I, A, W, H, p, smooth, tol, max_passes, F, B, passes_out, ws, s);
+    return cp_run<float>(I, A, W, H, p, smooth, tol, max_passes, F, B, passes_out, ws, s);
 }
 
 }  // namespace fge
@@ -889,7 +940,7 @@ size_t fge_levels_workspace_bytes(int32_t H, int32_t W, const fge_params *p,
         p = &tmp;
     }
     if (!o || o->size != sizeof(fge_level_options)) return 0;
-    return fge::levels_workspace_bytes(W, H, *p, o->resize);
+    return fge::levels_workspace_bytes(W, H, *p, o->resize, o->passes);
 }
 
 fge_status fge_estimate_foreground_levels(const void *I, const void *alpha, int32_t H, int32_t W,
@@ -902,8 +953,8 @@ fge_status fge_estimate_foreground_levels(const void *I, const void *alpha, int3
         p = &tmp;
     }
     if (!o || o->size != sizeof(fge_level_options)) return FGE_EINVAL;
-    return fge::estimate_levels(I, alpha, W, H, *p, o->resize, o->tol, o->max_sweeps, F, B,
-                                sweeps_out, workspace, workspace_bytes, stream);
+    return fge::estimate_levels(I, alpha, W, H, *p, o->resize, o->tol, o->max_sweeps, o->passes, F,
+                                B, sweeps_out, workspace, workspace_bytes, stream);
 }
 
 fge_status fge_estimate_foreground_converge(const void *I, const void *alpha, int32_t H, int32_t W,

@@ -281,8 +281,14 @@ fge_status estimate_converge(const void *I, const void *A, int W, int H, const f
                              double tol, int max_sweeps, void *F, void *B, int32_t *sweeps_out,
                              void *workspace, size_t workspace_bytes, void *stream);
 
-// The convergence form in passes of two sweeps on the fused kernels (fge_converge.hip).
-size_t converge_passes_workspace_bytes(int W, int H, const fge_params &p);
+// The convergence form in passes of two sweeps on the fused kernels (fge_converge.hip); smooth:
+// with the smooth resize variant (area copies of I and alpha, the previous level's F and B resized
+// bilinearly before the first pass; no coarse block).
+size_t converge_passes_workspace_bytes(int W, int H, const fge_params &p, bool smooth = false);
+fge_status estimate_converge_passes(const void *I, const void *A, int W, int H,
+                                    const fge_params &p, double tol, int max_passes, void *F,
+                                    void *B, int32_t *passes_out, void *workspace,
+                                    size_t workspace_bytes, void *stream, bool smooth = false);
 
 // Batched launches: descriptor tables, work lists and counters are device pointers.  Every
 // batched tile or streaming launch uses kQueueCounters counters (one work queue per XCD).

@@ -54,7 +54,7 @@ class LevelOptions(ctypes.Structure):
         ("resize", ctypes.c_int32),
         ("tol", ctypes.c_double),
         ("max_sweeps", ctypes.c_int32),
-        ("reserved0", ctypes.c_int32),
+        ("passes", ctypes.c_int32),
     ]
 
 
@@ -1011,25 +1011,29 @@ def composite(F, alpha, B, stream=None):
     return C
 
 
-def level_options(resize: str = "smooth", tol: float = -1.0, max_sweeps: int = 100) -> LevelOptions:
+def level_options(resize: str = "smooth", tol: float = -1.0, max_sweeps: int = 100,
+                  passes: bool = False) -> LevelOptions:
     o = LevelOptions()
     o.size = ctypes.sizeof(LevelOptions)
     o.resize = {"nearest": RESIZE_NEAREST, "smooth": RESIZE_SMOOTH}[resize]
     o.tol = float(tol)
     o.max_sweeps = int(max_sweeps)
+    o.passes = 1 if passes else 0
     return o
 
 
 @_on_stream
 def estimate_foreground_levels(I, alpha, params: Params | None = None, resize: str = "smooth",
                                tol: float = -1.0, max_sweeps: int = 100, F=None, B=None,
-                               stream=None):
-    """The level loop on per-level kernels with a resize variant and, for tol >= 0, the
-    convergence stop (fge_estimate_foreground_levels).  Returns (F, B, sweeps per level; the
-    counts are written in the convergence form only).  Does not synchronise."""
+                               stream=None, passes: bool = False):
+    """The level loop with a resize variant and, for tol >= 0, the convergence stop
+    (fge_estimate_foreground_levels): tested after every sweep on per-level kernels, or with
+    passes=True after every pass of two sweeps on the fused kernels (max_sweeps then caps the
+    passes, and the call completes before it returns).  Returns (F, B, sweeps -- or passes -- per
+    level; the counts are written in the convergence form only).  Does not synchronise otherwise."""
     import torch
     p = params if params is not None else default_params()
-    o = level_options(resize, tol, max_sweeps)
+    o = level_options(resize, tol, max_sweeps, passes)
     dt = storage_dtype(p)
     _, H, W = I.shape
     for name, t in (("I", I), ("alpha", alpha)):

@@ -44,7 +44,7 @@ def test_params_layout_and_defaults(fge):
     assert abs(p.omega - 0.1) < 1e-7 and abs(p.eps_r - 5e-3) < 1e-9
     assert (p.small_size, p.iters_small, p.iters_big) == (32, 10, 2)
     assert (p.storage, p.order, p.kernel, p.strip_rows, p.coarse_max_px, p.tile_max_px) == (0,) * 6
-    assert fge.load().fge_version() == 8
+    assert fge.load().fge_version() == 9
 
 
 def test_plan_matches_golden(fge):

@@ -122,3 +122,53 @@ def test_smooth_fused_passes_any_sweep_count(gpu, iters):
     err = max(maxabs(F.double().cpu().numpy(), Fo), maxabs(B.double().cpu().numpy(), Bo))
     print(f"smooth fused sweeps {iters}: {err:.2e}")
     assert err <= TOL["f32"]
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+@pytest.mark.parametrize("wh", [(320, 240), (1024, 768), (1, 1), (97, 3)])
+def test_smooth_converge_passes_replay_in_oracle(gpu, storage, wh):
+    """The convergence form tested after every pass of two sweeps, on the fused kernels, with the
+    smooth resize (passes=True): the result equals the oracle's smooth form run with the device's
+    pass counts (two sweeps each), at 1024 x 768 with the streaming kernel on the last level."""
+    torch, fge = gpu
+    W, H = wh
+    p = fge.default_params(storage=fge.F16 if storage == "f16" else fge.F32)
+    dt = fge.storage_dtype(p)
+    s = synth.strands(W, H, seed=11 * W + H, n_strands=max(1, W * H // 4000))
+    I = torch.from_numpy(s.I).to(dt).cuda()
+    a = torch.from_numpy(s.alpha).to(dt).cuda()
+    F, B, ps = fge.estimate_foreground_levels(I, a, p, resize="smooth", tol=1e-4, max_sweeps=150,
+                                              passes=True)
+    ps = ps.cpu().tolist()
+    assert len(ps) == fge.num_levels(H, W) and all(1 <= k <= 150 for k in ps)
+    Fo, Bo = oracle.ml_resize(I.double().cpu().numpy(), a.double().cpu().numpy(), "smooth",
+                              sweeps=[2 * k for k in ps])
+    err = max(maxabs(F.double().cpu().numpy(), Fo), maxabs(B.double().cpu().numpy(), Bo))
+    print(f"smooth converge passes {storage} {W}x{H}: passes {ps}, {err:.2e}")
+    assert err <= TOL[storage]
+
+
+def test_passes_option_limits_and_nearest(gpu):
+    """passes=True: tol 1 stops every level after its first pass, tol 0 runs max_sweeps passes;
+    with the nearest resize it is fge_estimate_foreground_converge_passes (same counts, same
+    bits); the Jacobi order is refused."""
+    torch, fge = gpu
+    p = fge.default_params()
+    s = synth.smooth(200, 150, seed=12)
+    I = torch.from_numpy(s.I).float().cuda()
+    a = torch.from_numpy(s.alpha).float().cuda()
+    n = fge.num_levels(150, 200)
+    _, _, ps = fge.estimate_foreground_levels(I, a, p, resize="smooth", tol=1.0, max_sweeps=40,
+                                              passes=True)
+    assert ps.cpu().tolist() == [1] * n
+    _, _, ps = fge.estimate_foreground_levels(I, a, p, resize="smooth", tol=0.0, max_sweeps=3,
+                                              passes=True)
+    assert ps.cpu().tolist() == [3] * n
+    F1, B1, c1 = fge.estimate_foreground_levels(I, a, p, resize="nearest", tol=1e-4, max_sweeps=60,
+                                                passes=True)
+    F2, B2, c2 = fge.estimate_foreground_converge_passes(I, a, p, tol=1e-4, max_passes=60)
+    torch.cuda.synchronize()
+    assert c1.cpu().tolist() == list(c2) and torch.equal(F1, F2) and torch.equal(B1, B2)
+    with pytest.raises(fge.FgeError):
+        fge.estimate_foreground_levels(I, a, fge.default_params(order=fge.JACOBI), resize="smooth",
+                                       tol=1e-4, passes=True)
