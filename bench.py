@@ -231,6 +231,23 @@ def run_variants(torch, fge, sample):
         "vs_per_level_kernels": out["converge_redblack"]["ms"] / ms}
     log(f"  converge_passes_redblack: {ms:.1f} ms ({out['converge_redblack']['ms'] / ms:.1f}x the "
         f"per-level form), sweeps {[2 * k for k in ps]}, SAD {q[0]:.1f}")
+    # the Jacobi order in the same passes (every level on the tile kernel)
+    pj = fge.default_params(storage=fge.F16, order=fge.JACOBI)
+    fge.estimate_foreground_converge_passes(I, a, pj, tol=1e-4, max_passes=100)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        F, B, ps = fge.estimate_foreground_converge_passes(I, a, pj, tol=1e-4, max_passes=100)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / reps * 1e3
+    q = fge.quality(F, G, a).cpu().numpy()
+    out["converge_passes_jacobi"] = {
+        "ms": ms, "value": W_IMG * H_IMG / 1e6 / (ms * 1e-3),
+        "sweeps_per_level": [2 * k for k in ps],
+        "quality": {"SAD": float(q[0]), "MSE": float(q[1]), "GRAD": float(q[2])},
+        "vs_per_level_kernels": out["converge_jacobi"]["ms"] / ms}
+    log(f"  converge_passes_jacobi: {ms:.1f} ms ({out['converge_jacobi']['ms'] / ms:.1f}x the "
+        f"per-level form), sweeps {[2 * k for k in ps]}, SAD {q[0]:.1f}")
     # the smooth variant's convergence form in the same passes
     fge.estimate_foreground_levels(I, a, p, resize="smooth", tol=1e-4, max_sweeps=100, passes=True)
     torch.cuda.synchronize()
@@ -252,9 +269,9 @@ def run_variants(torch, fge, sample):
     return {"workload": "4096x3072 strands image, float16 storage, per-level kernels: convergence "
                         "form (level energy change <= 1e-4 relative, <= 200 sweeps per level) and "
                         "the smooth resize variant converged; smooth_fixed_counts: sweeps on the "
-                        "fused kernels; converge_passes_redblack, smooth_converge_passes: the "
-                        "convergence form on the fused kernels, tested after every pass of two "
-                        "sweeps (<= 100 passes per level), nearest and smooth resize",
+                        "fused kernels; converge_passes_redblack, converge_passes_jacobi, "
+                        "smooth_converge_passes: the convergence form on the fused kernels, "
+                        "tested after every pass of two sweeps (<= 100 passes per level)",
             "unit": "MP/s", **out}
 
 

@@ -161,8 +161,8 @@ fge_status fge_estimate_foreground_noalloc(const void *I, const void *alpha, int
                                            const fge_params *p, void *F, void *B, void *stream);
 
 /* Algorithm 1's "while not converged" form on the fused kernels, the test taken after every pass
- * of two sweeps: every level runs passes of two red-black sweeps (one memory round trip each: the
- * LDS tile kernel for levels up to p->tile_max_px, the streaming kernel above; the first pass
+ * of two sweeps: every level runs passes of two sweeps in p->order (one memory round trip each:
+ * the LDS tile kernel for levels up to p->tile_max_px, the streaming kernel above; the first pass
  * resizes from the previous level), and stops when a pass changes the level's energy (fge_energy's
  * quadratic on the level's F, B against its nearest-resized image and matte) by at most tol times
  * its value before the pass -- before the first pass: the previous level's result as the resize
@@ -175,7 +175,8 @@ fge_status fge_estimate_foreground_noalloc(const void *I, const void *alpha, int
  * the accepted state is never overwritten): the call BLOCKS until the result is complete.  passes_out (HOST int array of >= n_levels
  * entries, or NULL) receives the passes each level ran.  The state stays float32 between passes
  * and levels (float16 inputs are converted once) and F, B are written in p->storage at the end.
- * Red-black order only (FGE_EUNSUPPORTED for Jacobi).  Workspace:
+ * In the Jacobi order every level runs on the tile kernel (each sweep from the state before it,
+ * in LDS) and none in the coarse block, which is red-black.  Workspace:
  * fge_converge_passes_workspace_bytes (three float32 states at full size, about 72 B/px, plus
  * 16 B/px of float32 inputs in float16 storage, plus the float32 inputs of the largest level
  * below full size, about 4 B/px). */
@@ -214,7 +215,7 @@ typedef struct fge_level_options {
     double tol;            /* < 0: the fixed sweep counts; >= 0: the convergence form above */
     int32_t max_sweeps;    /* convergence form: 1..100000 sweeps (passes) per level */
     int32_t passes;        /* 0: the test after every sweep, on per-level kernels; 1: the form of
-                              fge_estimate_foreground_converge_passes (red-black, tol >= 0, the test
+                              fge_estimate_foreground_converge_passes (tol >= 0, the test
                               after every pass of two sweeps on the fused kernels, max_sweeps caps
                               the passes and sweeps_out receives them; the call returns when the
                               result is complete) with this resize variant; with SMOOTH no coarse

@@ -582,7 +582,7 @@ CpLayout cp_layout(int W, int H, const fge_params &p, bool smooth) {
         io.H = H;
         io.w = io.wp = level_size(W, j + 1, nl);
         io.h = io.hp = level_size(H, j + 1, nl);
-        const bool tile = cp_use_tile(static_cast<long>(io.w) * io.h, p);
+        const bool tile = p.order == FGE_JACOBI || cp_use_tile(static_cast<long>(io.w) * io.h, p);
         L.nparts = std::max(L.nparts, pass_energy_parts(io, p.strip_rows, tile));
     }
     L.part = off;
@@ -659,7 +659,9 @@ fge_status cp_run(const void *Iv, const void *Av, int W, int H, const fge_params
     int prev = -1, wp = 1, hp = 1;   // the accepted state: buffer id (-1: the zero start), size
 
     // the coarse block: the longest prefix of levels that fit its LDS and the limit
-    const int climit = p.coarse_max_px < 0 || smooth
+    // the coarse block: red-black, nearest resize
+    const bool jac = p.order == FGE_JACOBI;
+    const int climit = p.coarse_max_px < 0 || smooth || jac
                            ? 0 : (p.coarse_max_px == 0 ? kCoarseMaxPx : p.coarse_max_px);
     int nc = 0;
     while (nc < n) {
@@ -704,7 +706,7 @@ fge_status cp_run(const void *Iv, const void *Av, int W, int H, const fge_params
         // flight (see above: after a stop at k, the passes from k + 2 on write nothing).
         const int depth = small ? kCpDepthSmall : kCpDepthBig;
         const float *Fprev = prev < 0 ? zero : buf(prev);
-        const bool tile = cp_use_tile(px, p);
+        const bool tile = jac || cp_use_tile(px, p);   // the Jacobi order: tile kernel only
         int parts = 0;
         // inputs: full resolution for the finest level, else the level's compact copy
         const float *Il = If, *Al = Af;
@@ -767,7 +769,8 @@ fge_status cp_run(const void *Iv, const void *Av, int W, int H, const fge_params
             const int sl = (k - 1) % kCpSlots;
             // the device applies the stop rule too: passes after the one that reports the stop
             // (pass k + 1 reports the energy after pass k) return at once
-            if (launch_pass_energy(io, p.strip_rows, tile, part, k == 1 ? nullptr : &ctl->stop, s) ||
+            if (launch_pass_energy(io, p.strip_rows, tile, part, k == 1 ? nullptr : &ctl->stop, s,
+                                   jac) ||
                 launch_pass_final(part, parts, hdev + 6 * sl, ctl, k, tol, s) ||
                 hipEventRecord(ev[sl], s) != hipSuccess)
                 ret = FGE_EHIP;
@@ -878,7 +881,6 @@ fge_status estimate_converge_passes(const void *I, const void *A, int W, int H,
                                     void *B, int32_t *passes_out, void *workspace,
                                     size_t workspace_bytes, void *stream, bool smooth) {
     if (!params_valid(p)) return FGE_EINVAL;
-    if (p.order != FGE_REDBLACK) return FGE_EUNSUPPORTED;   // the fused kernels are red-black
     if (W < 1 || H < 1 || W > kMaxSide || H > kMaxSide) return FGE_EINVAL;
     if (!I || !A || !F || !B) return FGE_EINVAL;
     if (!(tol >= 0.0) || !std::isfinite(tol) || max_passes < 1 || max_passes > kCvMaxSweeps)

@@ -146,8 +146,9 @@ int launch_fine_tile(const LevelIO &io, int storage, void *stream);
 // (5 doubles each, fge_energy's layout; energy_final_kernel totals them).
 // A non-null `skip` holding a non-zero value turns the pass into a no-op (see PassCtl).
 int pass_energy_parts(const LevelIO &io, int strip_rows, bool tile);
+// jacobi: the pass's two sweeps in the Jacobi order (always on the tile kernel).
 int launch_pass_energy(const LevelIO &io, int strip_rows, bool tile, double *epart,
-                       const int *skip, void *stream);
+                       const int *skip, void *stream, bool jacobi = false);
 int launch_naive_level(const LevelIO &io, int iters, int storage, void *stream);
 
 

@@ -594,7 +594,7 @@ __device__ __forceinline__ void tile_fetch(const T *I, const T *A, int W, int H,
 // level once; each pixel's terms in float32, summed in float64) and thread 0 writes it to
 // epart[5 * unit] (then zeros; the layout of fge_energy's partial sums).  ered: kTileThreads / 64
 // doubles of LDS.
-template <typename T, bool PREV_LDS, bool EN = false>
+template <typename T, bool PREV_LDS, bool EN = false, bool JAC = false>
 __device__ __forceinline__ void tile_level(const TileInput &in, int w, int h, const TilePrev &pv,
                                            const TileRegion &R, float4 *sFA, float4 *sB,
                                            float omega, float eps, T *Fo, T *Bo,
@@ -756,43 +756,64 @@ __device__ __forceinline__ void tile_level(const TileInput &in, int w, int h, co
         }
     }
 
+    // The update of the colour-c pixel of each owned pair from the neighbours in LDS.
+    // Unconditional reads and arithmetic (indices are clamped into the region), guarded stores:
+    // the reads of all owned pairs are in flight together.
+    auto solve = [&](int c, float (&fo)[kTilePairsPerThread][3], float (&bo)[kTilePairsPerThread][3]) {
+#pragma unroll
+        for (int k = 0; k < kTilePairsPerThread; ++k) {
+            float fb[3] = {0.f, 0.f, 0.f}, bb[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const float wj = cw[k][c][j];
+                const float4 f = sFA[cnb[k][c][j]];
+                const float4 g = sB[cnb[k][c][j]];
+                fb[0] = fmaf(wj, f.x, fb[0]);
+                fb[1] = fmaf(wj, f.y, fb[1]);
+                fb[2] = fmaf(wj, f.z, fb[2]);
+                bb[0] = fmaf(wj, g.x, bb[0]);
+                bb[1] = fmaf(wj, g.y, bb[1]);
+                bb[2] = fmaf(wj, g.z, bb[2]);
+            }
+            const float a = ca[k][c], b = 1.0f - a;
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) {
+                const float r = ci[k][c][ch] - a * fb[ch] - b * bb[ch];
+                fo[k][ch] = clamp01(fmaf(cka[k][c], r, fb[ch]));
+                bo[k][ch] = clamp01(fmaf(ckb[k][c], r, bb[ch]));
+            }
+        }
+    };
+    auto put = [&](int c, const float (&fo)[kTilePairsPerThread][3],
+                   const float (&bo)[kTilePairsPerThread][3]) {
+#pragma unroll
+        for (int k = 0; k < kTilePairsPerThread; ++k)
+            if (cok[k][c]) {
+                sFA[cpix[k][c]] = make_float4(fo[k][0], fo[k][1], fo[k][2], ca[k][c]);
+                sB[cpix[k][c]] = make_float4(bo[k][0], bo[k][1], bo[k][2], 0.0f);
+            }
+    };
 #pragma unroll
     for (int it = 0; it < 2; ++it) {
-#pragma unroll
-        for (int c = 0; c < 2; ++c) {
-            // Unconditional reads and arithmetic (indices are clamped into the region), guarded
-            // stores: the reads of all owned pairs are in flight together.
-            float fo[kTilePairsPerThread][3], bo[kTilePairsPerThread][3];
-#pragma unroll
-            for (int k = 0; k < kTilePairsPerThread; ++k) {
-                float fb[3] = {0.f, 0.f, 0.f}, bb[3] = {0.f, 0.f, 0.f};
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const float wj = cw[k][c][j];
-                    const float4 f = sFA[cnb[k][c][j]];
-                    const float4 g = sB[cnb[k][c][j]];
-                    fb[0] = fmaf(wj, f.x, fb[0]);
-                    fb[1] = fmaf(wj, f.y, fb[1]);
-                    fb[2] = fmaf(wj, f.z, fb[2]);
-                    bb[0] = fmaf(wj, g.x, bb[0]);
-                    bb[1] = fmaf(wj, g.y, bb[1]);
-                    bb[2] = fmaf(wj, g.z, bb[2]);
-                }
-                const float a = ca[k][c], b = 1.0f - a;
-#pragma unroll
-                for (int ch = 0; ch < 3; ++ch) {
-                    const float r = ci[k][c][ch] - a * fb[ch] - b * bb[ch];
-                    fo[k][ch] = clamp01(fmaf(cka[k][c], r, fb[ch]));
-                    bo[k][ch] = clamp01(fmaf(ckb[k][c], r, bb[ch]));
-                }
-            }
-#pragma unroll
-            for (int k = 0; k < kTilePairsPerThread; ++k)
-                if (cok[k][c]) {
-                    sFA[cpix[k][c]] = make_float4(fo[k][0], fo[k][1], fo[k][2], ca[k][c]);
-                    sB[cpix[k][c]] = make_float4(bo[k][0], bo[k][1], bo[k][2], 0.0f);
-                }
+        if constexpr (JAC) {
+            // Jacobi: both colours from the state before the sweep, written after every read
+            // of the sweep (each sweep invalidates one ring of the region; two are needed).
+            float fo0[kTilePairsPerThread][3], bo0[kTilePairsPerThread][3];
+            float fo1[kTilePairsPerThread][3], bo1[kTilePairsPerThread][3];
+            solve(0, fo0, bo0);
+            solve(1, fo1, bo1);
             lds_sync();
+            put(0, fo0, bo0);
+            put(1, fo1, bo1);
+            lds_sync();
+        } else {
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                float fo[kTilePairsPerThread][3], bo[kTilePairsPerThread][3];
+                solve(c, fo, bo);
+                put(c, fo, bo);
+                lds_sync();
+            }
         }
     }
 
@@ -817,7 +838,7 @@ __device__ __forceinline__ void tile_level(const TileInput &in, int w, int h, co
 }
 
 // One fine level, output tile `tile`: the level's F and B come from the stored previous level.
-template <typename T, bool EN = false>
+template <typename T, bool EN = false, bool JAC = false>
 __device__ __forceinline__ void tile_body(const TileArgs &args, int tile, TileLds &lds,
                                           double *epart = nullptr, double *ered = nullptr) {
     const int w = args.w, h = args.h;
@@ -832,8 +853,9 @@ __device__ __forceinline__ void tile_body(const TileArgs &args, int tile, TileLd
     TileInput in;
     tile_fetch<T>(static_cast<const T *>(args.I), static_cast<const T *>(args.A), args.W, args.H,
                   w, h, R, in);
-    tile_level<T, false, EN>(in, w, h, pv, R, lds.FA, lds.B, args.omega, args.eps,
-                             static_cast<T *>(args.Fo), static_cast<T *>(args.Bo), epart, tile, ered);
+    tile_level<T, false, EN, JAC>(in, w, h, pv, R, lds.FA, lds.B, args.omega, args.eps,
+                                  static_cast<T *>(args.Fo), static_cast<T *>(args.Bo), epart, tile,
+                                  ered);
 }
 
 template <typename T>
@@ -843,14 +865,15 @@ __global__ __launch_bounds__(kTileThreads) void tile_kernel(TileArgs args) {
 }
 
 // The convergence form's passes (float32 state): a tile pass that also reduces the energy of
-// the state it starts from, one partial per tile.  A non-null `skip` holding a non-zero value
-// (the level has stopped) makes the launch a no-op.
+// the state it starts from, one partial per tile; JAC: its two sweeps in the Jacobi order.  A
+// non-null `skip` holding a non-zero value (the level has stopped) makes the launch a no-op.
+template <bool JAC>
 __global__ __launch_bounds__(kTileThreads) void tile_energy_kernel(TileArgs args, double *epart,
                                                                   const int *skip) {
     if (skip && *skip) return;
     __shared__ TileLds lds;
     __shared__ double ered[kTileThreads / 64];
-    tile_body<float, true>(args, blockIdx.x, lds, epart, ered);
+    tile_body<float, true, JAC>(args, blockIdx.x, lds, epart, ered);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -2201,13 +2224,17 @@ int pass_energy_parts(const LevelIO &io, int strip_rows, bool tile) {
 }
 
 int launch_pass_energy(const LevelIO &io, int strip_rows, bool tile, double *epart,
-                       const int *skip, void *stream) {
+                       const int *skip, void *stream, bool jacobi) {
     hipStream_t s = static_cast<hipStream_t>(stream);
-    if (tile) {
+    if (tile || jacobi) {
         TileArgs a;
         make_tile_args(io, &a);
-        hipLaunchKernelGGL(tile_energy_kernel, dim3(tile_units(a)), dim3(kTileThreads), 0, s, a, epart,
-                           skip);
+        if (jacobi)
+            hipLaunchKernelGGL(tile_energy_kernel<true>, dim3(tile_units(a)), dim3(kTileThreads), 0, s,
+                               a, epart, skip);
+        else
+            hipLaunchKernelGGL(tile_energy_kernel<false>, dim3(tile_units(a)), dim3(kTileThreads), 0,
+                               s, a, epart, skip);
     } else {
         FineArgs a;
         make_fine_args(io, strip_rows, &a);

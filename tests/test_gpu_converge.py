@@ -182,8 +182,9 @@ def test_converge_passes_limits(gpu):
     assert max(maxabs(F.double().cpu().numpy(), Fr), maxabs(B.double().cpu().numpy(), Br)) <= 1e-4
     _, _, ps = fge.estimate_foreground_converge_passes(I, a, p, tol=0.0, max_passes=3)
     assert ps == [3] * n
-    with pytest.raises(fge.FgeError):
-        fge.estimate_foreground_converge_passes(I, a, fge.default_params(order=fge.JACOBI))
+    _, _, ps = fge.estimate_foreground_converge_passes(I, a, fge.default_params(order=fge.JACOBI),
+                                                       tol=0.0, max_passes=2)
+    assert ps == [2] * n
     # repeatable: bit-identical results and counts
     r1 = fge.estimate_foreground_converge_passes(I, a, p, tol=1e-5, max_passes=100)
     r2 = fge.estimate_foreground_converge_passes(I, a, p, tol=1e-5, max_passes=100)
@@ -222,3 +223,36 @@ def test_converge_is_asynchronous_and_repeatable(gpu):
     r2 = fge.estimate_foreground_converge(I, a, p, tol=1e-5, max_sweeps=100)
     torch.cuda.synchronize()
     assert torch.equal(r1[2], r2[2]) and torch.equal(r1[0], r2[0]) and torch.equal(r1[1], r2[1])
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+@pytest.mark.parametrize("wh,kind", [((300, 220), "strands"), ((1024, 768), "strands"),
+                                     ((64, 64), "smooth"), ((1, 1), "smooth"), ((97, 3), "smooth")])
+def test_converge_passes_jacobi_matches_oracle(gpu, storage, wh, kind):
+    """The Jacobi order in fused passes (every level on the tile kernel, two Jacobi sweeps per
+    pass from LDS) against the oracle's Jacobi loop tested every two sweeps, under the same count
+    rule as the red-black passes."""
+    torch, fge = gpu
+    W, H = wh
+    p = fge.default_params(order=fge.JACOBI, storage=fge.F16 if storage == "f16" else fge.F32)
+    s = (synth.strands(W, H, seed=53 + W, n_strands=max(1, W * H // 4000)) if kind == "strands"
+         else synth.smooth(W, H, seed=54 + W))
+    I, a = to_dev(torch, fge, p, s)
+    tol = 1e-4
+    F, B, ps = fge.estimate_foreground_converge_passes(I, a, p, tol=tol, max_passes=150)
+    I64, a64 = inputs64(I, a)
+    Fo, Bo, ch, rel = oracle.ml_converge_every(I64, a64, 2, tol, 150, order="jacobi", rel_cap=150)
+    print(f"jacobi passes {W}x{H} {storage}: device {ps}, oracle {ch}")
+    assert all(1 <= k <= 150 for k in ps)
+
+    def replay(lv, k):
+        sched = [2 * c for c in ch[:lv]] + [2 * k] + [0] * (len(ch) - lv - 1)
+        return oracle.ml_schedule(I64, a64, sched, order="jacobi")
+
+    if check_counts(ps, ch, rel, tol, replay):
+        Fr, Br = Fo, Bo
+    else:
+        Fr, Br = oracle.ml_schedule(I64, a64, [2 * k for k in ps], order="jacobi")
+    err = max(maxabs(F.double().cpu().numpy(), Fr), maxabs(B.double().cpu().numpy(), Br))
+    print(f"  max-abs vs oracle {err:.2e}")
+    assert err <= TOL[storage], err

@@ -151,7 +151,7 @@ def test_smooth_converge_passes_replay_in_oracle(gpu, storage, wh):
 def test_passes_option_limits_and_nearest(gpu):
     """passes=True: tol 1 stops every level after its first pass, tol 0 runs max_sweeps passes;
     with the nearest resize it is fge_estimate_foreground_converge_passes (same counts, same
-    bits); the Jacobi order is refused."""
+    bits), in either order."""
     torch, fge = gpu
     p = fge.default_params()
     s = synth.smooth(200, 150, seed=12)
@@ -169,6 +169,9 @@ def test_passes_option_limits_and_nearest(gpu):
     F2, B2, c2 = fge.estimate_foreground_converge_passes(I, a, p, tol=1e-4, max_passes=60)
     torch.cuda.synchronize()
     assert c1.cpu().tolist() == list(c2) and torch.equal(F1, F2) and torch.equal(B1, B2)
-    with pytest.raises(fge.FgeError):
-        fge.estimate_foreground_levels(I, a, fge.default_params(order=fge.JACOBI), resize="smooth",
-                                       tol=1e-4, passes=True)
+    q = fge.default_params(order=fge.JACOBI)
+    F1, B1, c1 = fge.estimate_foreground_levels(I, a, q, resize="nearest", tol=1e-4, max_sweeps=60,
+                                                passes=True)
+    F2, B2, c2 = fge.estimate_foreground_converge_passes(I, a, q, tol=1e-4, max_passes=60)
+    torch.cuda.synchronize()
+    assert c1.cpu().tolist() == list(c2) and torch.equal(F1, F2) and torch.equal(B1, B2)
