@@ -23,6 +23,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdint>
 
@@ -523,7 +524,8 @@ fge_status cv_run(const Plan &pl, const fge_params &p, const void *Iv, const voi
 // write a ring of output buffers in turn, and with two or more of them pass k + 1 never writes
 // pass k's.  So the host can keep passes in flight beyond the one it judges at no risk to the
 // accepted state -- kCpDepthSmall on levels of at most kCpSmallPx pixels, whose passes are
-// shorter than a host round trip, kCpDepthBig on larger ones.  The leading
+// shorter than a host round trip, kCpDepthBig on larger ones (deeper queues only add launches
+// beyond the stop).  The leading
 // levels that fit the coarse block's LDS (at most coarse_max_px pixels, all that fit when it is
 // 0, none when it is -1) run in one launch of the coarse block, which takes the same decisions
 // on the device (energy reduced in float64 in the workgroup) with no host round trip.  The state
@@ -533,9 +535,10 @@ fge_status cv_run(const Plan &pl, const fge_params &p, const void *Iv, const voi
 constexpr long kCpSmallPx = 1L << 16;
 constexpr int kCpSmallBufs = 3;   // small levels: the accepted state and a ring of 2 outputs
 constexpr int kCpBigBufs = 3;     // full-size: likewise
-constexpr int kCpDepthSmall = 7;  // passes in flight beyond the one judged
-constexpr int kCpDepthBig = 3;
+constexpr int kCpDepthSmall = 2;  // passes in flight beyond the one judged
+constexpr int kCpDepthBig = 1;
 constexpr int kCpSlots = 16;      // energy slots in pinned memory (> passes in flight)
+constexpr int kCpSlotDoubles = 8; // a slot: fge_energy's 6 outputs, the pass's number, padding
 
 struct CpLayout {
     size_t big[kCpBigBufs] = {}, small[kCpSmallBufs] = {}, in = 0, lin = 0, rows = 0, zero = 0,
@@ -632,23 +635,43 @@ fge_status cp_run(const void *Iv, const void *Av, int W, int H, const fge_params
     double *part = reinterpret_cast<double *>(ws + L.part);
     PassCtl *ctl = reinterpret_cast<PassCtl *>(ws + L.ctl);
 
-    // pinned, mapped: the energy of the state after pass m (written with pass m + 1) goes to slot
-    // m % kCpSlots as fge_energy's 6 outputs; an event after each tells the host it is complete
-    // (after the slots: the pass counts of the coarse block's levels)
+    // pinned, mapped: the energy of the state after pass m of a level (written with pass m + 1)
+    // goes to slot m % kCpSlots as fge_energy's 6 outputs, then the pass's sequence number (its
+    // index among all passes of the call, from 1), written last: the host polls for that number
+    // instead of recording and waiting on an event per pass (after the slots: the pass counts of
+    // the coarse block's levels)
     double *host = nullptr, *hdev = nullptr;
-    const size_t slot_bytes = kCpSlots * 6 * sizeof(double);
+    const size_t slot_bytes = kCpSlots * kCpSlotDoubles * sizeof(double);
     if (hipHostMalloc(reinterpret_cast<void **>(&host), slot_bytes + kMaxLevels * sizeof(int),
                       hipHostMallocMapped) != hipSuccess)
         return FGE_ENOMEM;
     fge_status ret = FGE_OK;
-    hipEvent_t ev[kCpSlots] = {};
+    for (int k = 0; k < kCpSlots; ++k) host[k * kCpSlotDoubles + 6] = -1.0;
     if (hipHostGetDevicePointer(reinterpret_cast<void **>(&hdev), host, 0) != hipSuccess) ret = FGE_EHIP;
-    for (int k = 0; k < kCpSlots && ret == FGE_OK; ++k)
-        if (hipEventCreateWithFlags(&ev[k], hipEventDisableTiming) != hipSuccess) ret = FGE_EHIP;
 
+    long base = 0;   // passes of the call before the current level's
+    // The energy after pass m of the current level: poll its slot for pass m + 1's number; every
+    // 1024 polls ask the stream, which fails on an error, and finding it drained with no number
+    // is an error too.
     auto wait = [&](int m) {
-        if (ret == FGE_OK && hipEventSynchronize(ev[m % kCpSlots]) != hipSuccess) ret = FGE_EHIP;
-        return ret == FGE_OK ? reinterpret_cast<volatile double *>(host)[6 * (m % kCpSlots)] : 0.0;
+        if (ret != FGE_OK) return 0.0;
+        volatile double *slot = host + kCpSlotDoubles * (m % kCpSlots);
+        const double want = static_cast<double>(base + m + 1);
+        for (long it = 1; slot[6] != want; ++it) {
+            if ((it & 1023) == 0) {
+                const hipError_t q = hipStreamQuery(s);
+                if (q != hipSuccess && q != hipErrorNotReady) {
+                    ret = FGE_EHIP;
+                    return 0.0;
+                }
+                if (q == hipSuccess && slot[6] != want) {
+                    ret = FGE_EHIP;
+                    return 0.0;
+                }
+            }
+        }
+        std::atomic_thread_fence(std::memory_order_acquire);
+        return static_cast<double>(slot[0]);
     };
 
     // buffers: ids 0 .. kCpBigBufs - 1 the full-size ring, then the small ring
@@ -658,8 +681,8 @@ fge_status cp_run(const void *Iv, const void *Av, int W, int H, const fge_params
     const int n = num_levels(W, H);
     int prev = -1, wp = 1, hp = 1;   // the accepted state: buffer id (-1: the zero start), size
 
-    // the coarse block: the longest prefix of levels that fit its LDS and the limit
-    // the coarse block: red-black, nearest resize
+    // the coarse block (red-black, nearest resize): the longest prefix of levels that fit its LDS
+    // and the limit
     const bool jac = p.order == FGE_JACOBI;
     const int climit = p.coarse_max_px < 0 || smooth || jac
                            ? 0 : (p.coarse_max_px == 0 ? kCoarseMaxPx : p.coarse_max_px);
@@ -771,8 +794,7 @@ fge_status cp_run(const void *Iv, const void *Av, int W, int H, const fge_params
             // (pass k + 1 reports the energy after pass k) return at once
             if (launch_pass_energy(io, p.strip_rows, tile, part, k == 1 ? nullptr : &ctl->stop, s,
                                    jac) ||
-                launch_pass_final(part, parts, hdev + 6 * sl, ctl, k, tol, s) ||
-                hipEventRecord(ev[sl], s) != hipSuccess)
+                launch_pass_final(part, parts, hdev + kCpSlotDoubles * sl, ctl, k, tol, base + k, s))
                 ret = FGE_EHIP;
         };
         int hi = 0;   // passes enqueued
@@ -791,6 +813,7 @@ fge_status cp_run(const void *Iv, const void *Av, int W, int H, const fge_params
             ++k;
         }
         if (passes_out) passes_out[j] = k;
+        base += hi;
         prev = outs[(k - 1) % R];
         wp = w;
         hp = h;
@@ -804,8 +827,6 @@ fge_status cp_run(const void *Iv, const void *Av, int W, int H, const fge_params
     if (hipStreamSynchronize(s) != hipSuccess && ret == FGE_OK) ret = FGE_EHIP;
     if (ret == FGE_OK && passes_out)
         for (int l = 0; l < nc; ++l) passes_out[l] = reinterpret_cast<volatile int *>(hcounts)[l];
-    for (hipEvent_t e : ev)
-        if (e) (void)hipEventDestroy(e);
     (void)hipHostFree(host);
     return ret;
 }

@@ -272,8 +272,10 @@ struct PassCtl {
     int stop;
     int pad;
 };
+// out: 7 doubles of host-visible memory -- the total as fge_energy's 6 outputs, then seq, written
+// last (behind a system-scope fence) so that the host can poll for it.
 int launch_pass_final(const double *part, int nb, double *out, PassCtl *ctl, int m, double tol,
-                      void *stream);
+                      long seq, void *stream);
 
 // Level loop with the convergence stop or the Jacobi order (fge_converge.hip); tol < 0 runs the
 // fixed counts.

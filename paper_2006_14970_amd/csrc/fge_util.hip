@@ -146,10 +146,12 @@ __global__ __launch_bounds__(kRedThreads) void energy_final_kernel(const double 
     }
 }
 
-// energy_final_kernel's total plus the convergence form's stop rule (PassCtl).
+// energy_final_kernel's total plus the convergence form's stop rule (PassCtl).  out is host
+// memory: out[6] = seq is written after the six values, behind a system-scope fence, so the host
+// can poll it.
 __global__ __launch_bounds__(kRedThreads) void pass_final_kernel(const double *part, int nb,
                                                                  double *out, PassCtl *ctl, int m,
-                                                                 double tol) {
+                                                                 double tol, double seq) {
     if (m > 1 && ctl->stop) return;
     __shared__ double red[2][kRedThreads];
     double acc[2] = {0.0, 0.0};
@@ -181,6 +183,8 @@ __global__ __launch_bounds__(kRedThreads) void pass_final_kernel(const double *p
         } else {
             ctl->e_prev = e;
         }
+        __threadfence_system();
+        reinterpret_cast<volatile double *>(out)[6] = seq;
     }
 }
 
@@ -519,9 +523,10 @@ int launch_energy_final(const double *part, int nb, double *out, void *stream) {
 }
 
 int launch_pass_final(const double *part, int nb, double *out, PassCtl *ctl, int m, double tol,
-                      void *stream) {
+                      long seq, void *stream) {
     hipLaunchKernelGGL(pass_final_kernel, dim3(1), dim3(kRedThreads), 0,
-                       static_cast<hipStream_t>(stream), part, nb, out, ctl, m, tol);
+                       static_cast<hipStream_t>(stream), part, nb, out, ctl, m, tol,
+                       static_cast<double>(seq));
     return static_cast<int>(hipGetLastError());
 }
 
