@@ -347,6 +347,21 @@ def test_level_options_host_side(fge):
     assert run(odd) == fge.FGE_EINVAL
     assert run(fge.level_options("smooth", tol=1e-4, max_sweeps=0)) == fge.FGE_EINVAL
     assert run(smooth, ws=None) == fge.FGE_EWORKSPACE
+    # passes = 1: the layout of the fused passes (the smooth one adds its row pass), errors
+    pn = fge.level_options("nearest", tol=1e-4, passes=True)
+    ps = fge.level_options("smooth", tol=1e-4, passes=True)
+    wpn = lib.fge_levels_workspace_bytes(768, 1024, ctypes.byref(p), ctypes.byref(pn))
+    wps = lib.fge_levels_workspace_bytes(768, 1024, ctypes.byref(p), ctypes.byref(ps))
+    assert wpn == lib.fge_converge_passes_workspace_bytes(768, 1024, ctypes.byref(p))
+    assert wps >= wpn + 16 * 512 * 768
+    nps = lib.fge_levels_workspace_bytes(64, 64, ctypes.byref(p), ctypes.byref(ps))
+    assert run(fge.level_options("smooth", tol=-1.0, passes=True), ws=WS0) == fge.FGE_EINVAL
+    assert run(fge.level_options("smooth", tol=1e-4, max_sweeps=0, passes=True)) == fge.FGE_EINVAL
+    two = fge.level_options("smooth", tol=1e-4, passes=True)
+    two.passes = 2
+    assert run(two) == fge.FGE_EINVAL
+    assert lib.fge_estimate_foreground_levels(I0, A0, 64, 64, ctypes.byref(p), ctypes.byref(ps),
+                                              F0, B0, None, WS0, nps - 1, None) == fge.FGE_EWORKSPACE
 
 
 def test_staged_inputs_do_not_grow_workspace(fge):
