@@ -3,7 +3,7 @@
 //
 // Per level: resize F and B from the previous level (nearest), then sweep.  With a tolerance
 // tol >= 0 the level's energy (fge_energy's quadratic on the level's F, B against its resized
-// image and matte) is reduced on the device after every sweep and a one-thread check kernel
+// image and matte) is reduced on the device after every sweep, and the launch that totals it
 // compares it with the energy before the sweep: when |E_prev - E| <= tol E_prev, or after
 // max_sweeps sweeps, it raises a stop flag that turns every later launch of the level into a
 // no-op (grid-stride kernels with capped grids, so a stopped launch retires quickly).  The host
@@ -269,18 +269,6 @@ __global__ void cv_begin_kernel(int *stop, int *count) {
     }
 }
 
-// After sweep k of a level (k = 0: the resized start): record the count and decide.
-__global__ void cv_check_kernel(const double *enow, double *eprev, int *stop, int *count,
-                                double tol, int k, int kmax) {
-    if (threadIdx.x != 0 || stop[0]) return;
-    const double e = enow[0];
-    if (k > 0) {
-        count[0] = k;
-        if (fabs(eprev[0] - e) <= tol * eprev[0] || k >= kmax) stop[0] = 1;
-    }
-    eprev[0] = e;
-}
-
 // Fused passes (two sweeps per memory round trip) run on the LDS tile kernel up to tile_max_px
 // and on the streaming kernel above, except where a level's float32 state (6 planes, one buffer
 // resource) would reach 4 GiB, the reach of the streaming kernel's addressing.
@@ -362,12 +350,9 @@ fge_status cv_sweep_level(const fge_params &p, const TI *I, const TI *A, int Wi,
     const int *guard = conv ? stop : nullptr;
     if (conv) {
         hipLaunchKernelGGL(cv_begin_kernel, dim3(1), dim3(64), 0, s, stop, count);
-        if (launch_energy(I, A, Wi, Hi, Fo, Bo, w, h, p.omega, p.eps_r, ti, FGE_F32, stop, part,
-                          enow, s))
+        if (launch_energy_check(I, A, Wi, Hi, Fo, Bo, w, h, p.omega, p.eps_r, ti, FGE_F32, part,
+                                enow, eprev, stop, count, tol, 0, kmax, s))
             return FGE_EHIP;
-        hipLaunchKernelGGL(cv_check_kernel, dim3(1), dim3(64), 0, s, enow, eprev, stop, count, tol,
-                           0, kmax);
-        if (hipGetLastError() != hipSuccess) return FGE_EHIP;
     }
     for (int k = 1; k <= kmax; ++k) {
         if (jac) {
@@ -383,14 +368,10 @@ fge_status cv_sweep_level(const fge_params &p, const TI *I, const TI *A, int Wi,
                                    p.omega, p.eps_r, guard);
         }
         if (hipGetLastError() != hipSuccess) return FGE_EHIP;
-        if (conv) {
-            if (launch_energy(I, A, Wi, Hi, Fo, Bo, w, h, p.omega, p.eps_r, ti, FGE_F32, stop, part,
-                              enow, s))
-                return FGE_EHIP;
-            hipLaunchKernelGGL(cv_check_kernel, dim3(1), dim3(64), 0, s, enow, eprev, stop, count,
-                               tol, k, kmax);
-            if (hipGetLastError() != hipSuccess) return FGE_EHIP;
-        }
+        if (conv &&
+            launch_energy_check(I, A, Wi, Hi, Fo, Bo, w, h, p.omega, p.eps_r, ti, FGE_F32, part,
+                                enow, eprev, stop, count, tol, k, kmax, s))
+            return FGE_EHIP;
     }
     return FGE_OK;
 }

@@ -263,6 +263,14 @@ int launch_energy_mapped(const void *I, const void *A, int W, int H, const void 
 // Totals nb partial sums of fge_energy's layout (5 doubles each) into out[0..5], as fge_energy
 // reports them (out[0] the energy).
 int launch_energy_final(const double *part, int nb, double *out, void *stream);
+// launch_energy's partial sums, then in one launch their total and the stop rule of the level
+// loop tested after every sweep (k = 0: the level's resized start; k > 0 records count = k and
+// sets stop when |eprev - E| <= tol eprev or k >= kmax; eprev = E).  Both launches are no-ops
+// once stop is set.
+int launch_energy_check(const void *I, const void *A, int W, int H, const void *F, const void *B,
+                        int w, int h, float omega, float eps, int storage, int state_storage,
+                        double *part, double *out, double *eprev, int *stop, int *count,
+                        double tol, int k, int kmax, void *stream);
 // The convergence form's stop rule on the device, beside the host's: pass m's total (the energy
 // after pass m - 1) also updates ctl -- m == 1 starts the level (e_prev = that energy, stop = 0);
 // m > 1 sets stop when |e_prev - e| <= tol e_prev, else e_prev = e.  Once stop is set the later

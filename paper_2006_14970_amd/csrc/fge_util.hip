@@ -115,9 +115,7 @@ __global__ __launch_bounds__(kRedThreads) void energy_partial_kernel(
 
 // out[0] = E, [1] data term, [2] smoothness term, [3] mean |residual| over fractional pixels,
 // [4] max |residual| there, [5] number of fractional pixels.
-__global__ __launch_bounds__(kRedThreads) void energy_final_kernel(const double *part, int nb,
-                                                                   const int *stop, double *out) {
-    if (stop && *stop) return;
+__device__ __forceinline__ void energy_total(const double *part, int nb, double *out) {
     __shared__ double red[5][kRedThreads];
     double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     for (int b = threadIdx.x; b < nb; b += kRedThreads) {
@@ -143,6 +141,32 @@ __global__ __launch_bounds__(kRedThreads) void energy_final_kernel(const double 
         out[3] = red[3][0] > 0.0 ? red[2][0] / red[3][0] : 0.0;
         out[4] = red[4][0];
         out[5] = red[3][0];
+    }
+}
+
+__global__ __launch_bounds__(kRedThreads) void energy_final_kernel(const double *part, int nb,
+                                                                   const int *stop, double *out) {
+    if (stop && *stop) return;
+    energy_total(part, nb, out);
+}
+
+// energy_final_kernel's total, then the stop rule of the level loop tested after every sweep:
+// after sweep k of a level (k = 0: the resized start) record the count and stop when the energy
+// changed by at most tol times its value before the sweep, or k reached kmax.  One launch instead
+// of a total and a one-thread check.
+__global__ __launch_bounds__(kRedThreads) void energy_check_kernel(const double *part, int nb,
+                                                                   double *out, double *eprev,
+                                                                   int *stop, int *count,
+                                                                   double tol, int k, int kmax) {
+    if (*stop) return;
+    energy_total(part, nb, out);
+    if (threadIdx.x == 0) {
+        const double e = out[0];
+        if (k > 0) {
+            count[0] = k;
+            if (fabs(eprev[0] - e) <= tol * eprev[0] || k >= kmax) stop[0] = 1;
+        }
+        eprev[0] = e;
     }
 }
 
@@ -495,11 +519,10 @@ int launch_energy(const void *I, const void *A, int W, int H, const void *F, con
                                 stop, part, out, stream);
 }
 
-int launch_energy_mapped(const void *I, const void *A, int W, int H, const void *F, const void *B,
-                         int fw, int fh, int w, int h, float omega, float eps, int storage,
-                         int state_storage, const int *stop, double *part, double *out,
-                         void *stream) {
-    hipStream_t s = static_cast<hipStream_t>(stream);
+// The partial sums of launch_energy_mapped (one launch).
+int launch_energy_parts(const void *I, const void *A, int W, int H, const void *F, const void *B,
+                        int fw, int fh, int w, int h, float omega, float eps, int storage,
+                        int state_storage, const int *stop, double *part, hipStream_t s) {
     const int nb = energy_blocks(w, h);
     const bool i16 = storage == FGE_F16, f16 = state_storage == FGE_F16;
     if (i16 && f16)
@@ -510,9 +533,32 @@ int launch_energy_mapped(const void *I, const void *A, int W, int H, const void 
         launch_energy_t<float, _Float16>(I, A, W, H, F, B, fw, fh, w, h, omega, eps, stop, part, nb, s);
     else
         launch_energy_t<float, float>(I, A, W, H, F, B, fw, fh, w, h, omega, eps, stop, part, nb, s);
-    int err = static_cast<int>(hipGetLastError());
+    return static_cast<int>(hipGetLastError());
+}
+
+int launch_energy_mapped(const void *I, const void *A, int W, int H, const void *F, const void *B,
+                         int fw, int fh, int w, int h, float omega, float eps, int storage,
+                         int state_storage, const int *stop, double *part, double *out,
+                         void *stream) {
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int err = launch_energy_parts(I, A, W, H, F, B, fw, fh, w, h, omega, eps, storage,
+                                        state_storage, stop, part, s);
     if (err) return err;
-    hipLaunchKernelGGL(energy_final_kernel, dim3(1), dim3(kRedThreads), 0, s, part, nb, stop, out);
+    hipLaunchKernelGGL(energy_final_kernel, dim3(1), dim3(kRedThreads), 0, s, part,
+                       energy_blocks(w, h), stop, out);
+    return static_cast<int>(hipGetLastError());
+}
+
+int launch_energy_check(const void *I, const void *A, int W, int H, const void *F, const void *B,
+                        int w, int h, float omega, float eps, int storage, int state_storage,
+                        double *part, double *out, double *eprev, int *stop, int *count,
+                        double tol, int k, int kmax, void *stream) {
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int err = launch_energy_parts(I, A, W, H, F, B, w, h, w, h, omega, eps, storage,
+                                        state_storage, stop, part, s);
+    if (err) return err;
+    hipLaunchKernelGGL(energy_check_kernel, dim3(1), dim3(kRedThreads), 0, s, part,
+                       energy_blocks(w, h), out, eprev, stop, count, tol, k, kmax);
     return static_cast<int>(hipGetLastError());
 }
 
