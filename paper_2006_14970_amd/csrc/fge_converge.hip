@@ -16,7 +16,8 @@
 // the fused kernels (cv_fused_sweeps).
 //
 // Orders: red-black (two half-sweeps in place, (x + y) even first) or Jacobi (every pixel from
-// the previous sweep's values: sweep into a temporary, copy back).  The per-pixel update is the
+// the previous sweep's values: sweeps alternate between two buffers, the result copied back
+// once at the end of the level if it ran an odd number).  The per-pixel update is the
 // 2x2 solve of eq. 9 in the same Sherman-Morrison form as the other kernels.  A level sweeps on
 // float32 working buffers and its state is converted to the storage type once, when the level is
 // written (so binary16 storage rounds once per level, as on the fused path).
@@ -262,6 +263,19 @@ __global__ __launch_bounds__(kCvThreads) void cv_copy_kernel(const float *Fs, co
     }
 }
 
+// The Jacobi sweeps of a level alternate between two state buffers; the level's result is in the
+// second one when the count of sweeps run is odd: copy it back then.
+__global__ __launch_bounds__(kCvThreads) void cv_copy_odd_kernel(const float *Fs, const float *Bs,
+                                                                 float *F, float *B, size_t n,
+                                                                 const int *count) {
+    if ((count[0] & 1) == 0) return;
+    for (size_t p = static_cast<size_t>(blockIdx.x) * kCvThreads + threadIdx.x; p < 3 * n;
+         p += static_cast<size_t>(gridDim.x) * kCvThreads) {
+        F[p] = Fs[p];
+        B[p] = Bs[p];
+    }
+}
+
 __global__ void cv_begin_kernel(int *stop, int *count) {
     if (threadIdx.x == 0) {
         stop[0] = 0;
@@ -355,11 +369,12 @@ fge_status cv_sweep_level(const fge_params &p, const TI *I, const TI *A, int Wi,
             return FGE_EHIP;
     }
     for (int k = 1; k <= kmax; ++k) {
+        // Jacobi: sweep k reads one buffer and writes the other (odd k: Fo -> Ft)
+        float *Fd = jac && (k & 1) ? Ft : Fo, *Bd = jac && (k & 1) ? Bt : Bo;
         if (jac) {
+            const float *Fs = (k & 1) ? Fo : Ft, *Bs = (k & 1) ? Bo : Bt;
             hipLaunchKernelGGL(cv_jacobi_kernel<TI>, dim3(blocks_for(n)), dim3(kCvThreads), 0, s, I,
-                               A, Wi, Hi, Fo, Bo, Ft, Bt, w, h, p.omega, p.eps_r, guard);
-            hipLaunchKernelGGL(cv_copy_kernel<float>, dim3(blocks_for(3 * n)), dim3(kCvThreads), 0,
-                               s, Ft, Bt, Fo, Bo, n, guard);
+                               A, Wi, Hi, Fs, Bs, Fd, Bd, w, h, p.omega, p.eps_r, guard);
         } else {
             const size_t npairs = static_cast<size_t>((w + 1) >> 1) * h;
             for (int colour = 0; colour < 2; ++colour)
@@ -369,9 +384,18 @@ fge_status cv_sweep_level(const fge_params &p, const TI *I, const TI *A, int Wi,
         }
         if (hipGetLastError() != hipSuccess) return FGE_EHIP;
         if (conv &&
-            launch_energy_check(I, A, Wi, Hi, Fo, Bo, w, h, p.omega, p.eps_r, ti, FGE_F32, part,
+            launch_energy_check(I, A, Wi, Hi, Fd, Bd, w, h, p.omega, p.eps_r, ti, FGE_F32, part,
                                 enow, eprev, stop, count, tol, k, kmax, s))
             return FGE_EHIP;
+    }
+    if (jac && conv) {   // the sweeps that ran decide where the result is
+        hipLaunchKernelGGL(cv_copy_odd_kernel, dim3(blocks_for(3 * n)), dim3(kCvThreads), 0, s, Ft,
+                           Bt, Fo, Bo, n, count);
+        if (hipGetLastError() != hipSuccess) return FGE_EHIP;
+    } else if (jac && (kmax & 1)) {
+        hipLaunchKernelGGL(cv_copy_kernel<float>, dim3(blocks_for(3 * n)), dim3(kCvThreads), 0, s,
+                           Ft, Bt, Fo, Bo, n, nullptr);
+        if (hipGetLastError() != hipSuccess) return FGE_EHIP;
     }
     return FGE_OK;
 }
