@@ -256,3 +256,20 @@ def test_converge_passes_jacobi_matches_oracle(gpu, storage, wh, kind):
     err = max(maxabs(F.double().cpu().numpy(), Fr), maxabs(B.double().cpu().numpy(), Br))
     print(f"  max-abs vs oracle {err:.2e}")
     assert err <= TOL[storage], err
+
+
+@pytest.mark.parametrize("iters", [(3, 1), (10, 3)])
+def test_jacobi_odd_sweep_counts(gpu, iters):
+    """Fixed odd sweep counts in the Jacobi order on the per-level kernels, whose sweeps alternate
+    between two buffers: the result of an odd count is copied back at the level's end."""
+    torch, fge = gpu
+    W, H = 211, 157
+    p = fge.default_params(order=fge.JACOBI, iters_small=iters[0], iters_big=iters[1])
+    s = synth.strands(W, H, seed=97, n_strands=10)
+    I, a = to_dev(torch, fge, p, s)
+    F, B, _ = fge.estimate_foreground_converge(I, a, p, tol=-1.0)
+    torch.cuda.synchronize()
+    sweeps = [k for _, _, k in oracle.level_plan(W, H, iters_small=iters[0], iters_big=iters[1])]
+    Fo, Bo = oracle.ml_schedule(*inputs64(I, a), sweeps, order="jacobi")
+    err = max(maxabs(F.double().cpu().numpy(), Fo), maxabs(B.double().cpu().numpy(), Bo))
+    assert err <= TOL["f32"], err
